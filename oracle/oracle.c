@@ -1,0 +1,600 @@
+/*
+ * CPU oracle for the HashPoint hot path (arXiv 2404.14044).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, obviously correct
+ * restatement of what the method computes.  Only the test suite, the smoke
+ * check and the benchmark's CPU-baseline leg load it; the product library
+ * never links, calls or includes anything from here, and this file shares no
+ * source with the GPU path.
+ *
+ * The neighbour search is brute force over every point (Sec. 3.5 names brute
+ * force as the baseline that hashed-point searching accelerates, and Sec. 4.2
+ * notes that all search structures must retrieve the same points), so the
+ * table-based GPU search must reproduce it exactly.
+ *
+ * Two stages:
+ *   exact stage (binary32): every discrete decision is a function of values
+ *     produced by a fixed sequence of correctly rounded IEEE-754 binary32
+ *     operations (+ - * / sqrt, rint, floor, and fmaf only where written).
+ *     Built with -ffp-contract=off so the compiler adds no fused operations.
+ *   continuous stage (binary64): feature aggregation, MLP, compositing (Eq. 2)
+ *     and their gradients.
+ *
+ * Readings of the paper taken where it is silent are listed next to the code
+ * that applies them.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int32_t W, H;
+    float fx, fy, cx, cy;
+    float R[9]; /* world -> camera rotation, row-major */
+    float C[3]; /* camera centre, world coordinates */
+} orc_camera;
+
+typedef struct {
+    float radius, inv_tref, t_near, t_far;
+    int32_t K, n_samples, m_cap;
+    float gamma, inv_beta2, eps_w, eps_idw, delta_last;
+    float bg[3];
+} orc_params;
+
+#define ORC_HID 64
+#define ORC_OUT 4
+
+/* ------------------------------------------------------------------------ */
+/* exp for the confidence alpha = gamma * exp(-d^2 / beta^2) (Sec. 3.3).     */
+/* Cody-Waite reduction x = k ln2 + r, |r| <= ln2/2, then the degree-7      */
+/* Taylor polynomial of exp(r) in Horner form, then scaling by 2^k.          */
+/* Constants are the FP64 values rounded once to binary32.                   */
+/* ------------------------------------------------------------------------ */
+float or_exp32(float x)
+{
+    if (!(x >= -86.0f)) return 0.0f; /* also maps NaN to 0 */
+    const float inv_ln2 = (float)(1.0 / 0.69314718055994530942);
+    const float ln2_hi = 0.693145751953125f; /* 45426 / 65536: 16 significant bits */
+    const float ln2_lo = (float)(0.69314718055994530942 - 0.693145751953125);
+    const float k = rintf(x * inv_ln2);
+    float r = fmaf(-k, ln2_hi, x);
+    r = fmaf(-k, ln2_lo, r);
+    const float c[8] = {1.0f, 1.0f, (float)(1.0 / 2.0), (float)(1.0 / 6.0), (float)(1.0 / 24.0),
+                        (float)(1.0 / 120.0), (float)(1.0 / 720.0), (float)(1.0 / 5040.0)};
+    float p = c[7];
+    for (int i = 6; i >= 0; --i) p = fmaf(p, r, c[i]);
+    const int ki = (int)k;
+    union { uint32_t u; float f; } s;
+    s.u = (uint32_t)(ki + 127) << 23;
+    return p * s.f;
+}
+
+void or_exp32_array(const float *x, float *y, int64_t n)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) y[i] = or_exp32(x[i]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Search radius rho(t) = r * max(1, t * inv_tref).  With inv_tref = 0 it is */
+/* the fixed radius; with inv_tref = 1/t_near it is the cone of Eq. 3, which */
+/* grows linearly with the distance from the ray origin and equals the       */
+/* hyper-parameter radius at t_near (Sec. 3.2).                              */
+/* ------------------------------------------------------------------------ */
+static float rho_of(const orc_params *p, float t)
+{
+    float s = t * p->inv_tref;
+    float m = (s > 1.0f) ? s : 1.0f;
+    return p->radius * m;
+}
+
+/* Guard band g around the image (in pixels).  A point within rho(t) of a    */
+/* ray at parameter t >= t_near projects at most                             */
+/*   delta = f rho L^2 / (t - rho |w|)                                       */
+/* pixels from that ray's pixel centre, where w is the ray's normalised image */
+/* coordinate and L^2 = 1 + |w|^2; delta does not grow with t, so its value   */
+/* at t_near and the image corner bounds every ray.  Returns -1 when the      */
+/* bound does not exist (the radius swallows the near plane).                */
+int32_t or_guard(const orc_camera *cam, const orc_params *p)
+{
+    double w2 = 0.0;
+    for (int cu = 0; cu < 2; ++cu)
+        for (int cv = 0; cv < 2; ++cv) {
+            double u = cu ? (cam->W - 1) : 0, v = cv ? (cam->H - 1) : 0;
+            double a = (u + 0.5 - cam->cx) / cam->fx, b = (v + 0.5 - cam->cy) / cam->fy;
+            if (a * a + b * b > w2) w2 = a * a + b * b;
+        }
+    double f = cam->fx > cam->fy ? cam->fx : cam->fy;
+    double s = (double)p->t_near * p->inv_tref;
+    double rho = (double)p->radius * (s > 1.0 ? s : 1.0);
+    double den = p->t_near - rho * sqrt(w2);
+    if (!(den > 0.0)) return -1;
+    double delta = f * rho * (1.0 + w2) / den;
+    return (int32_t)floor(0.5 + delta) + 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Camera transform (Sec. 3.2, projection of every point): p_c = R (p - C).  */
+/* ------------------------------------------------------------------------ */
+void or_to_camera(const float *xyz, int64_t n, const orc_camera *cam, float *pc)
+{
+    const float *R = cam->R;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        float qx = xyz[3 * i + 0] - cam->C[0];
+        float qy = xyz[3 * i + 1] - cam->C[1];
+        float qz = xyz[3 * i + 2] - cam->C[2];
+        pc[3 * i + 0] = fmaf(R[2], qz, fmaf(R[1], qy, R[0] * qx));
+        pc[3 * i + 1] = fmaf(R[5], qz, fmaf(R[4], qy, R[3] * qx));
+        pc[3 * i + 2] = fmaf(R[8], qz, fmaf(R[7], qy, R[6] * qx));
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pixel-keyed table (Sec. 3.2, Fig. 2): every point in front of the camera  */
+/* is projected (no z-buffer) and assigned to the pixel it falls in; the     */
+/* table lists, per pixel, the points of that pixel.  Reading: pixels form a */
+/* grid widened by the guard band g on each side, the key is the row-major   */
+/* pixel index of that grid, and points of one pixel are ordered by depth    */
+/* z_c and then by point index.                                              */
+/* key[i] = -1 for points that are not inserted.  order[0..n_in) lists the   */
+/* inserted point indices sorted by (key, z_c, index).  Returns n_in.        */
+/* ------------------------------------------------------------------------ */
+typedef struct { int32_t key; float z; int32_t idx; } tab_ent;
+
+static int cmp_tab(const void *a, const void *b)
+{
+    const tab_ent *x = (const tab_ent *)a, *y = (const tab_ent *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    if (x->z != y->z) return x->z < y->z ? -1 : 1;
+    return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+int64_t or_table(const float *pc, int64_t n, const orc_camera *cam, int32_t g,
+                 int32_t *key, int32_t *order)
+{
+    const int64_t Wg = (int64_t)cam->W + 2 * g;
+    const float lo = (float)(-g), hiu = (float)(cam->W + g), hiv = (float)(cam->H + g);
+    for (int64_t i = 0; i < n; ++i) {
+        float x = pc[3 * i], y = pc[3 * i + 1], z = pc[3 * i + 2];
+        key[i] = -1;
+        if (!(z > 0.0f) || !isfinite(x) || !isfinite(y) || !isfinite(z)) continue;
+        float uf = fmaf(cam->fx, x / z, cam->cx);
+        float vf = fmaf(cam->fy, y / z, cam->cy);
+        if (!(uf >= lo && uf < hiu && vf >= lo && vf < hiv)) continue;
+        int64_t bu = (int64_t)floorf(uf) + g, bv = (int64_t)floorf(vf) + g;
+        key[i] = (int32_t)(bv * Wg + bu);
+    }
+    int64_t n_in = 0;
+    for (int64_t i = 0; i < n; ++i) n_in += key[i] >= 0;
+    tab_ent *e = (tab_ent *)malloc((size_t)(n_in ? n_in : 1) * sizeof(tab_ent));
+    int64_t k = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (key[i] >= 0) { e[k].key = key[i]; e[k].z = pc[3 * i + 2]; e[k].idx = (int32_t)i; ++k; }
+    qsort(e, (size_t)n_in, sizeof(tab_ent), cmp_tab);
+    for (int64_t j = 0; j < n_in; ++j) order[j] = e[j].idx;
+    free(e);
+    return n_in;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ray of pixel (u, v): from the optical centre through the pixel centre     */
+/* (u + 0.5, v + 0.5), unit length, camera coordinates.                      */
+/* ------------------------------------------------------------------------ */
+void or_ray_dir(const orc_camera *cam, int32_t u, int32_t v, float d[3])
+{
+    float a = (((float)u + 0.5f) - cam->cx) / cam->fx;
+    float b = (((float)v + 0.5f) - cam->cy) / cam->fy;
+    float L = sqrtf(fmaf(b, b, fmaf(a, a, 1.0f)));
+    d[0] = a / L;
+    d[1] = b / L;
+    d[2] = 1.0f / L;
+}
+
+/* Projection parameter t of camera-space point x on ray d, and the squared  */
+/* distance between x and the ray point at parameter s.                      */
+static float ray_t(const float *x, const float *d)
+{
+    return fmaf(x[2], d[2], fmaf(x[1], d[1], x[0] * d[0]));
+}
+
+static float dist2_at(const float *x, const float *d, float s)
+{
+    float ex = fmaf(-s, d[0], x[0]);
+    float ey = fmaf(-s, d[1], x[1]);
+    float ez = fmaf(-s, d[2], x[2]);
+    return fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+}
+
+typedef struct { float key; int32_t idx; int32_t aux; } kv_ent;
+
+static int cmp_kv(const void *a, const void *b)
+{
+    const kv_ent *x = (const kv_ent *)a, *y = (const kv_ent *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact stage for a list of rays (pixel indices v*W + u of one camera).     */
+/*                                                                           */
+/* Search (Sec. 3.2): the neighbours of a ray are the points whose distance  */
+/* to the ray is at most rho(t) at their projection parameter t, with t in   */
+/* [t_near, t_far].  Brute force over all n points.  N(ray) is the           */
+/* neighbour list ordered by (t, index) and cut to its first m_cap entries;  */
+/* flags bit 0 records that the cut dropped some.                            */
+/*                                                                           */
+/* Sampling (Sec. 3.3, Eq. 4, Eq. 5): every neighbour, projected onto the    */
+/* ray, is a sample candidate; candidates are visited in depth order.  For   */
+/* candidate j at t_j with R_j = rho(t_j): its K neighbouring points are the */
+/* K entries of N(ray) nearest to the candidate (ties by index) among those  */
+/* within R_j; missing ones count as distance R_j (reading: an isolated      */
+/* candidate then scores as far from any surface).  Pseudo-UDF d_j is their */
+/* mean distance (Eq. 4), alpha_j = gamma exp(-d_j^2 / beta^2), and the      */
+/* occlusion-aware weight is w_j = alpha_j prod_{k<j} (1 - alpha_k) over all */
+/* earlier candidates (Eq. 5).  A candidate becomes a sample when            */
+/* w_j > eps_w (reading of "larger than zero"), up to n_samples per ray.     */
+/* The primary surface is the point of the first sample, or -1.              */
+/*                                                                           */
+/* Outputs, per ray r (M = m_cap, S = n_samples):                            */
+/*   n_nbr[r], flags[r], nbr_idx/nbr_t[r*M + j] (j < n_nbr; rest -1 / 0),    */
+/*   n_sel[r], primary[r], smp_t[r*S + s], knn_cnt[r*S + s],                 */
+/*   knn_idx/knn_dist[(r*S + s)*K + k] (k < knn_cnt; rest -1 / 0).           */
+/* Optional per-candidate diagnostics (may be NULL), [r*M + j]:              */
+/*   cand_d (d_j), cand_alpha, cand_w, cand_T (transmittance before j).      */
+/* ------------------------------------------------------------------------ */
+void or_exact(const float *pc, int64_t n, const orc_camera *cam, const orc_params *p,
+              const int32_t *pix, int64_t n_rays,
+              int32_t *n_nbr, uint32_t *flags, int32_t *nbr_idx, float *nbr_t,
+              int32_t *n_sel, int32_t *primary, float *smp_t, int32_t *knn_idx,
+              float *knn_dist, int32_t *knn_cnt,
+              float *cand_d, float *cand_alpha, float *cand_w, float *cand_T)
+{
+    const int M = p->m_cap, S = p->n_samples, K = p->K;
+#pragma omp parallel
+    {
+        uint8_t *pass = (uint8_t *)malloc((size_t)(n ? n : 1));
+        float *tv = (float *)malloc((size_t)(n ? n : 1) * sizeof(float));
+        int64_t cap = 1024;
+        kv_ent *nb = (kv_ent *)malloc((size_t)cap * sizeof(kv_ent));
+        kv_ent *kn = (kv_ent *)malloc((size_t)(M > 0 ? M : 1) * sizeof(kv_ent));
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t r = 0; r < n_rays; ++r) {
+            const int32_t u = pix[r] % cam->W, v = pix[r] / cam->W;
+            float d[3];
+            or_ray_dir(cam, u, v, d);
+            /* brute-force predicate over all points */
+            for (int64_t i = 0; i < n; ++i) {
+                const float *x = pc + 3 * i;
+                float t = ray_t(x, d);
+                float e2 = dist2_at(x, d, t);
+                float rho = rho_of(p, t);
+                tv[i] = t;
+                pass[i] = (uint8_t)((x[2] > 0.0f) & (t >= p->t_near) & (t <= p->t_far) &
+                                    (e2 <= rho * rho));
+            }
+            int64_t cnt = 0;
+            for (int64_t i = 0; i < n; ++i) {
+                if (!pass[i]) continue;
+                if (cnt == cap) {
+                    cap *= 2;
+                    nb = (kv_ent *)realloc(nb, (size_t)cap * sizeof(kv_ent));
+                }
+                nb[cnt].key = tv[i];
+                nb[cnt].idx = (int32_t)i;
+                nb[cnt].aux = 0;
+                ++cnt;
+            }
+            qsort(nb, (size_t)cnt, sizeof(kv_ent), cmp_kv);
+            const int m = (int)(cnt < M ? cnt : M);
+            n_nbr[r] = m;
+            flags[r] = (cnt > M) ? 1u : 0u;
+            for (int j = 0; j < M; ++j) {
+                nbr_idx[r * M + j] = j < m ? nb[j].idx : -1;
+                nbr_t[r * M + j] = j < m ? nb[j].key : 0.0f;
+            }
+            /* candidate walk in depth order */
+            float T = 1.0f;
+            int sel = 0;
+            primary[r] = -1;
+            for (int j = 0; j < m; ++j) {
+                const float tj = nb[j].key;
+                const float Rj = rho_of(p, tj);
+                const float R2 = Rj * Rj;
+                int kc = 0;
+                for (int i = 0; i < m; ++i) {
+                    float dd = dist2_at(pc + 3 * (int64_t)nb[i].idx, d, tj);
+                    if (dd <= R2) { kn[kc].key = dd; kn[kc].idx = nb[i].idx; ++kc; }
+                }
+                qsort(kn, (size_t)kc, sizeof(kv_ent), cmp_kv);
+                const int kj = kc < K ? kc : K;
+                float sum = 0.0f;
+                for (int k = 0; k < kj; ++k) sum = sum + sqrtf(kn[k].key);
+                const float dj = (sum + (float)(K - kj) * Rj) / (float)K;
+                const float uj = (dj * dj) * p->inv_beta2;
+                const float aj = p->gamma * or_exp32(-uj);
+                const float wj = aj * T;
+                if (cand_d) cand_d[r * M + j] = dj;
+                if (cand_alpha) cand_alpha[r * M + j] = aj;
+                if (cand_w) cand_w[r * M + j] = wj;
+                if (cand_T) cand_T[r * M + j] = T;
+                if (wj > p->eps_w && sel < S) {
+                    const int64_t row = r * S + sel;
+                    smp_t[row] = tj;
+                    knn_cnt[row] = kj;
+                    for (int k = 0; k < K; ++k) {
+                        knn_idx[row * K + k] = k < kj ? kn[k].idx : -1;
+                        knn_dist[row * K + k] = k < kj ? sqrtf(kn[k].key) : 0.0f;
+                    }
+                    if (sel == 0) primary[r] = nb[j].idx;
+                    ++sel;
+                }
+                T = T * (1.0f - aj);
+            }
+            n_sel[r] = sel;
+            for (int s = sel; s < S; ++s) {
+                smp_t[r * S + s] = 0.0f;
+                knn_cnt[r * S + s] = 0;
+                for (int k = 0; k < K; ++k) {
+                    knn_idx[(r * S + s) * K + k] = -1;
+                    knn_dist[(r * S + s) * K + k] = 0.0f;
+                }
+            }
+            if (cand_d)
+                for (int j = m; j < M; ++j) {
+                    cand_d[r * M + j] = 0.0f;
+                    if (cand_alpha) cand_alpha[r * M + j] = 0.0f;
+                    if (cand_w) cand_w[r * M + j] = 0.0f;
+                    if (cand_T) cand_T[r * M + j] = 0.0f;
+                }
+        }
+        free(pass);
+        free(tv);
+        free(nb);
+        free(kn);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Continuous stage in binary64.                                             */
+/*                                                                           */
+/* Feature at a sample (Sec. 3.4: features of the sample's neighbouring      */
+/* points are aggregated; reading: inverse-distance weights                  */
+/* 1 / max(dist, eps_idw), normalised), an MLP 32 -> 64 -> 64 -> 4 with ReLU */
+/* giving colour c = sigmoid(o_0..2) and density sigma = softplus(o_3), and  */
+/* volume rendering (Eq. 2): transmittance tau_j = exp(-sum_{k<j} sigma_k    */
+/* Delta_k), weight tau_j (1 - exp(-sigma_j Delta_j)), with Delta_j the gap  */
+/* to the next sample and delta_last for the last one.  Outputs colour       */
+/* sum w c + (1 - sum w) bg, depth sum w t and opacity sum w.                */
+/* Geometry (t_j, ray direction, point positions) is the exact stage's       */
+/* binary32 values, widened exactly.                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const float *W1, *b1, *W2, *b2, *W3, *b3;
+} orc_mlp;
+
+static double sigm(double x) { return x >= 0 ? 1.0 / (1.0 + exp(-x)) : exp(x) / (1.0 + exp(x)); }
+static double softplus(double x) { return (x > 0 ? x : 0.0) + log1p(exp(-fabs(x))); }
+
+/* per-sample forward; keeps activations for the backward pass */
+typedef struct {
+    double f[64], h1[ORC_HID], h2[ORC_HID], o[ORC_OUT];
+    double wsum, w[64];
+} smp_state;
+
+static void sample_forward(const float *pc, const float *feat, int C, const orc_mlp *mlp,
+                           const float *d, float t, const int32_t *idx, int K, float eps_idw,
+                           smp_state *st)
+{
+    double xs[3] = {(double)t * d[0], (double)t * d[1], (double)t * d[2]};
+    for (int c = 0; c < C; ++c) st->f[c] = 0.0;
+    st->wsum = 0.0;
+    for (int k = 0; k < K; ++k) {
+        st->w[k] = 0.0;
+        if (idx[k] < 0) continue;
+        const float *x = pc + 3 * (int64_t)idx[k];
+        double dx = x[0] - xs[0], dy = x[1] - xs[1], dz = x[2] - xs[2];
+        double dist = sqrt(dx * dx + dy * dy + dz * dz);
+        double wk = 1.0 / (dist > eps_idw ? dist : (double)eps_idw);
+        st->w[k] = wk;
+        st->wsum += wk;
+        for (int c = 0; c < C; ++c) st->f[c] += wk * feat[(int64_t)idx[k] * C + c];
+    }
+    for (int c = 0; c < C; ++c) st->f[c] /= st->wsum;
+    for (int o = 0; o < ORC_HID; ++o) {
+        double a = mlp->b1[o];
+        for (int c = 0; c < C; ++c) a += (double)mlp->W1[o * C + c] * st->f[c];
+        st->h1[o] = a > 0 ? a : 0.0;
+    }
+    for (int o = 0; o < ORC_HID; ++o) {
+        double a = mlp->b2[o];
+        for (int c = 0; c < ORC_HID; ++c) a += (double)mlp->W2[o * ORC_HID + c] * st->h1[c];
+        st->h2[o] = a > 0 ? a : 0.0;
+    }
+    for (int o = 0; o < ORC_OUT; ++o) {
+        double a = mlp->b3[o];
+        for (int c = 0; c < ORC_HID; ++c) a += (double)mlp->W3[o * ORC_HID + c] * st->h2[c];
+        st->o[o] = a;
+    }
+}
+
+void or_render64(const float *pc, const float *feat, int32_t C,
+                 const float *W1, const float *b1, const float *W2, const float *b2,
+                 const float *W3, const float *b3,
+                 const orc_camera *cam, const orc_params *p, const int32_t *pix, int64_t n_rays,
+                 const int32_t *n_sel, const float *smp_t, const int32_t *knn_idx,
+                 double *rgb, double *depth, double *acc)
+{
+    const orc_mlp mlp = {W1, b1, W2, b2, W3, b3};
+    const int S = p->n_samples, K = p->K;
+#pragma omp parallel
+    {
+        smp_state *st = (smp_state *)malloc(sizeof(smp_state));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t r = 0; r < n_rays; ++r) {
+            float d[3];
+            or_ray_dir(cam, pix[r] % cam->W, pix[r] / cam->W, d);
+            double T = 1.0, col[3] = {0, 0, 0}, dep = 0.0, ws = 0.0;
+            const int ns = n_sel[r];
+            for (int s = 0; s < ns; ++s) {
+                const int64_t row = r * S + s;
+                sample_forward(pc, feat, C, &mlp, d, smp_t[row], knn_idx + row * K, K,
+                               p->eps_idw, st);
+                double sigma = softplus(st->o[3]);
+                double delta = (s + 1 < ns) ? (double)smp_t[row + 1] - (double)smp_t[row]
+                                            : (double)p->delta_last;
+                double a = -expm1(-sigma * delta);
+                double w = T * a;
+                for (int c = 0; c < 3; ++c) col[c] += w * sigm(st->o[c]);
+                dep += w * smp_t[row];
+                ws += w;
+                T = T * exp(-sigma * delta);
+            }
+            for (int c = 0; c < 3; ++c) rgb[3 * r + c] = col[c] + (1.0 - ws) * p->bg[c];
+            depth[r] = dep;
+            acc[r] = ws;
+        }
+        free(st);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gradient of sum_r grad_rgb[r] . rgb[r] with respect to the features and  */
+/* the MLP parameters, for the render above (analytic, binary64).  The      */
+/* samples are functions of geometry only, so they stay fixed.  Results are */
+/* ADDED to g_feat (n x C) and g_W1..g_b3.                                  */
+/* ------------------------------------------------------------------------ */
+void or_grad64(const float *pc, const float *feat, int32_t C,
+               const float *W1, const float *b1, const float *W2, const float *b2,
+               const float *W3, const float *b3,
+               const orc_camera *cam, const orc_params *p, const int32_t *pix, int64_t n_rays,
+               const int32_t *n_sel, const float *smp_t, const int32_t *knn_idx,
+               const double *grad_rgb, double *g_feat,
+               double *g_W1, double *g_b1, double *g_W2, double *g_b2, double *g_W3, double *g_b3)
+{
+    const orc_mlp mlp = {W1, b1, W2, b2, W3, b3};
+    const int S = p->n_samples, K = p->K;
+    const int n_w1 = ORC_HID * C, n_w2 = ORC_HID * ORC_HID, n_w3 = ORC_OUT * ORC_HID;
+    const int n_par = n_w1 + ORC_HID + n_w2 + ORC_HID + n_w3 + ORC_OUT;
+    int n_thr = 1;
+#ifdef _OPENMP
+    n_thr = omp_get_max_threads();
+#endif
+    double *gpar = (double *)calloc((size_t)n_thr * n_par, sizeof(double));
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *gw1 = gpar + (size_t)tid * n_par, *gb1 = gw1 + n_w1, *gw2 = gb1 + ORC_HID,
+               *gb2 = gw2 + n_w2, *gw3 = gb2 + ORC_HID, *gb3 = gw3 + n_w3;
+        int Smax = S > 0 ? S : 1;
+        smp_state *st = (smp_state *)malloc((size_t)Smax * sizeof(smp_state));
+        double *a = (double *)malloc((size_t)Smax * sizeof(double));
+        double *Tj = (double *)malloc((size_t)Smax * sizeof(double));
+        double *delta = (double *)malloc((size_t)Smax * sizeof(double));
+        double *sigma = (double *)malloc((size_t)Smax * sizeof(double));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t r = 0; r < n_rays; ++r) {
+            const int ns = n_sel[r];
+            if (ns == 0) continue;
+            float d[3];
+            or_ray_dir(cam, pix[r] % cam->W, pix[r] / cam->W, d);
+            double T = 1.0;
+            for (int s = 0; s < ns; ++s) {
+                const int64_t row = r * S + s;
+                sample_forward(pc, feat, C, &mlp, d, smp_t[row], knn_idx + row * K, K,
+                               p->eps_idw, &st[s]);
+                sigma[s] = softplus(st[s].o[3]);
+                delta[s] = (s + 1 < ns) ? (double)smp_t[row + 1] - (double)smp_t[row]
+                                        : (double)p->delta_last;
+                a[s] = -expm1(-sigma[s] * delta[s]);
+                Tj[s] = T;
+                T = T * exp(-sigma[s] * delta[s]);
+            }
+            const double *g = grad_rgb + 3 * r;
+            double U[3] = {0, 0, 0}, P = 1.0;
+            for (int s = ns - 1; s >= 0; --s) {
+                double c[3], dLda = 0.0;
+                for (int k = 0; k < 3; ++k) c[k] = sigm(st[s].o[k]);
+                for (int k = 0; k < 3; ++k)
+                    dLda += g[k] * (Tj[s] * (c[k] - U[k]) - p->bg[k] * Tj[s] * P);
+                double dLdsig = dLda * delta[s] * exp(-sigma[s] * delta[s]);
+                double go[ORC_OUT];
+                for (int k = 0; k < 3; ++k) go[k] = g[k] * Tj[s] * a[s] * c[k] * (1.0 - c[k]);
+                go[3] = dLdsig * sigm(st[s].o[3]);
+                for (int k = 0; k < 3; ++k) U[k] = a[s] * c[k] + (1.0 - a[s]) * U[k];
+                P = (1.0 - a[s]) * P;
+                /* MLP backward */
+                double gh2[ORC_HID], gh1[ORC_HID], gf[64];
+                for (int o = 0; o < ORC_OUT; ++o) {
+                    gb3[o] += go[o];
+                    for (int c2 = 0; c2 < ORC_HID; ++c2) gw3[o * ORC_HID + c2] += go[o] * st[s].h2[c2];
+                }
+                for (int c2 = 0; c2 < ORC_HID; ++c2) {
+                    double acc2 = 0.0;
+                    for (int o = 0; o < ORC_OUT; ++o) acc2 += (double)W3[o * ORC_HID + c2] * go[o];
+                    gh2[c2] = st[s].h2[c2] > 0 ? acc2 : 0.0;
+                }
+                for (int o = 0; o < ORC_HID; ++o) {
+                    gb2[o] += gh2[o];
+                    for (int c1 = 0; c1 < ORC_HID; ++c1) gw2[o * ORC_HID + c1] += gh2[o] * st[s].h1[c1];
+                }
+                for (int c1 = 0; c1 < ORC_HID; ++c1) {
+                    double acc1 = 0.0;
+                    for (int o = 0; o < ORC_HID; ++o) acc1 += (double)W2[o * ORC_HID + c1] * gh2[o];
+                    gh1[c1] = st[s].h1[c1] > 0 ? acc1 : 0.0;
+                }
+                for (int o = 0; o < ORC_HID; ++o) {
+                    gb1[o] += gh1[o];
+                    for (int c0 = 0; c0 < C; ++c0) gw1[o * C + c0] += gh1[o] * st[s].f[c0];
+                }
+                for (int c0 = 0; c0 < C; ++c0) {
+                    double acc0 = 0.0;
+                    for (int o = 0; o < ORC_HID; ++o) acc0 += (double)W1[o * C + c0] * gh1[o];
+                    gf[c0] = acc0;
+                }
+                /* inverse-distance aggregation backward */
+                const int32_t *idx = knn_idx + (r * S + s) * K;
+                for (int k = 0; k < K; ++k) {
+                    if (idx[k] < 0) continue;
+                    double wk = st[s].w[k] / st[s].wsum;
+                    for (int c0 = 0; c0 < C; ++c0) {
+#pragma omp atomic
+                        g_feat[(int64_t)idx[k] * C + c0] += wk * gf[c0];
+                    }
+                }
+            }
+        }
+        free(st);
+        free(a);
+        free(Tj);
+        free(delta);
+        free(sigma);
+    }
+    for (int t = 0; t < n_thr; ++t) {
+        const double *gw1 = gpar + (size_t)t * n_par, *gb1 = gw1 + n_w1, *gw2 = gb1 + ORC_HID,
+                     *gb2 = gw2 + n_w2, *gw3 = gb2 + ORC_HID, *gb3 = gw3 + n_w3;
+        for (int i = 0; i < n_w1; ++i) g_W1[i] += gw1[i];
+        for (int i = 0; i < ORC_HID; ++i) g_b1[i] += gb1[i];
+        for (int i = 0; i < n_w2; ++i) g_W2[i] += gw2[i];
+        for (int i = 0; i < ORC_HID; ++i) g_b2[i] += gb2[i];
+        for (int i = 0; i < n_w3; ++i) g_W3[i] += gw3[i];
+        for (int i = 0; i < ORC_OUT; ++i) g_b3[i] += gb3[i];
+    }
+    free(gpar);
+}
+
+int32_t or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
