@@ -1,0 +1,224 @@
+/*
+ * hashpoint.h -- C ABI of the MI355X (gfx950) HashPoint hot path.
+ *
+ * HashPoint (arXiv 2404.14044) renders a neural point cloud by ray tracing.
+ * Sec. 3.2 ("hashed-point searching") projects every point onto the image
+ * plane (no z-buffer) and regroups the point list per pixel into a table whose
+ * key is the pixel index and whose value is (first point, count); a ray then
+ * visits the pixels of a window around its own and tests each listed point
+ * by its distance to the ray.  Sec. 3.3 ("adaptive primary surface
+ * sampling") projects the neighbours onto the ray as sample candidates,
+ * scores each by the mean distance to its K nearest points (Eq. 4), turns it
+ * into a confidence alpha = gamma exp(-d^2/beta^2), weights it by the
+ * transmittance of the earlier candidates (Eq. 5) and keeps the candidates
+ * near the first surface.  Sec. 3.4 decodes the kept samples with an MLP and
+ * composites them by volume rendering (Eq. 2).
+ *
+ * The four calls below are those steps:
+ *   hp_build_table      - projection and pixel table        (Sec. 3.2, Fig. 2)
+ *   hp_search_sample    - window search and sampling        (Sec. 3.2-3.3, Eq. 4-5)
+ *   hp_render           - aggregation, MLP, compositing     (Sec. 3.4, Eq. 2)
+ *   hp_render_backward  - gradient of the render            (Sec. 3.4, Eq. 2)
+ *
+ * General rules
+ *  - All buffers are caller-owned.  Pointers documented "device" are HIP
+ *    device memory; "host" pointers are read before the call returns.  The
+ *    library allocates nothing and keeps no state between calls.
+ *  - Calls are asynchronous on the given HIP stream (0 = the null stream).
+ *    Arguments are validated on the host before any launch; a rejected call
+ *    launches nothing and returns an error status.
+ *  - Rays are numbered view-major, then row-major: ray = ray_base(view) +
+ *    v * W + u, where ray_base(view) is the sum of W * H over earlier views.
+ *  - Every discrete result (table order, neighbour lists, samples, nearest
+ *    neighbours) is deterministic and identical run to run.
+ */
+#ifndef HASHPOINT_H
+#define HASHPOINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hp_status;
+enum {
+    HP_OK = 0,
+    HP_E_INVALID = 1,     /* bad argument (null pointer, out-of-range value) */
+    HP_E_WORKSPACE = 2,   /* workspace pointer null or smaller than required */
+    HP_E_UNSUPPORTED = 3, /* valid request this build does not implement      */
+    HP_E_CAPACITY = 4,    /* an index would not fit in int32                   */
+    HP_E_HIP = 5          /* a HIP runtime call failed; see hp_last_hip_error  */
+};
+
+enum { HP_FP32 = 0, HP_BF16 = 1 };                 /* decoder precision  */
+enum { HP_LAYOUT_ROWMAJOR = 0, HP_LAYOUT_TILED = 1 }; /* bucket order     */
+
+#define HP_MAX_VIEWS 32
+#define HP_MAX_K 32
+#define HP_MAX_SAMPLES 64
+#define HP_MAX_MCAP 64
+#define HP_FEAT_DIM 32
+#define HP_HIDDEN 64
+
+/* Pinhole camera (host).  OpenCV axes: +x right, +y down, +z forward.
+ * Camera-space position of world point p is R (p - C); pixel (u, v) spans
+ * [u, u+1) x [v, v+1) and its ray passes through (u + 0.5, v + 0.5). */
+typedef struct hp_camera {
+    int32_t W, H;
+    float fx, fy, cx, cy;
+    float R[9]; /* world -> camera rotation, row-major */
+    float C[3]; /* camera centre, world coordinates     */
+} hp_camera;
+
+/* Run parameters (host).
+ *  radius, inv_tref: search radius rho(t) = radius * max(1, t * inv_tref).
+ *      inv_tref = 0 gives a fixed radius; inv_tref = 1 / t_near gives the
+ *      cone of Eq. 3, linear in t and equal to radius at t_near (Sec. 3.2).
+ *  t_near, t_far: range of the ray parameter t (0 < t_near <= t_far).
+ *  K: points per pseudo-UDF (Eq. 4), 1..HP_MAX_K.
+ *  n_samples: cap on samples per ray, 1..HP_MAX_SAMPLES.
+ *  m_cap: cap on the per-ray neighbour list, 1..HP_MAX_MCAP.
+ *  gamma, inv_beta2: alpha = gamma * exp(-d^2 * inv_beta2), 0 < gamma <= 1.
+ *  eps_w: a candidate becomes a sample when its weight (Eq. 5) > eps_w.
+ *  eps_idw: floor of the distance in the inverse-distance feature weights.
+ *  delta_last: interval length of the last sample of a ray (Eq. 2).
+ *  bg: background colour.
+ *  layout: HP_LAYOUT_ROWMAJOR or HP_LAYOUT_TILED (8x8 pixel tiles).
+ *  flags: reserved, must be 0. */
+typedef struct hp_params {
+    float radius, inv_tref, t_near, t_far;
+    int32_t K, n_samples, m_cap;
+    float gamma, inv_beta2, eps_w, eps_idw, delta_last;
+    float bg[3];
+    int32_t layout, flags;
+} hp_params;
+
+/* Per-view geometry of a table, filled by hp_build_table. */
+typedef struct hp_view_info {
+    int32_t W, H;         /* image size                                       */
+    int32_t g;            /* guard band in pixels around the image            */
+    int32_t Wg, Hg;       /* bucket grid, at least (W + 2g) x (H + 2g)         */
+    int32_t bucket_base;  /* first bucket of the view in the table            */
+    int32_t ray_base;     /* first ray of the view                            */
+    float delta_max;      /* bound on a neighbour's pixel offset from its ray  */
+} hp_view_info;
+
+/* A built table (host struct of device pointers into the caller's workspace).
+ *  offsets[b] .. offsets[b+1]: slots of bucket b; offsets has n_buckets + 1
+ *      entries and offsets[n_buckets] is the number of inserted points.
+ *  pts[4 * slot + 0..3]: camera-space x, y, z and the point index (as int32
+ *      bits), ordered by bucket, then z, then point index.
+ *  perm[slot]: the point index of each slot.
+ *  slot_of[view * n_points + i]: slot of point i in that view (only defined
+ *      for inserted points). */
+typedef struct hp_table {
+    int32_t n_views;
+    int32_t layout;
+    int64_t n_points;
+    int64_t n_buckets;
+    int64_t n_rays;
+    int32_t *offsets;
+    float *pts;
+    int32_t *perm;
+    int32_t *slot_of;
+    void *scratch;
+    hp_view_info views[HP_MAX_VIEWS];
+} hp_table;
+
+/* Per-ray and per-sample outputs of hp_search_sample (device, caller-owned).
+ *  Per ray r: n_sel[r] samples, primary[r] = point index of the first
+ *      sample (-1 if none), n_nbr[r] = neighbours kept (<= m_cap),
+ *      flags[r] bit 0 = more than m_cap neighbours were found.
+ *  Per sample s < n_sel[r] (row = r * n_samples + s): t[row] is its ray
+ *      parameter; knn_idx[row * K + k], knn_dist[row * K + k] are its nearest
+ *      neighbours in increasing distance (ties by index), padded with -1 / 0.
+ *      Rows s >= n_sel[r] are not written.
+ *  nbr_idx, nbr_t (nullable, [R * m_cap]): the neighbour list in (t, index)
+ *      order, padded with -1 / 0. */
+typedef struct hp_samples {
+    int32_t *n_sel;
+    int32_t *primary;
+    int32_t *n_nbr;
+    uint32_t *flags;
+    float *t;
+    int32_t *knn_idx;
+    float *knn_dist;
+    int32_t *nbr_idx;
+    float *nbr_t;
+} hp_samples;
+
+/* MLP 32 -> 64 -> 64 -> 4 with ReLU; colour = sigmoid(o0..2), density =
+ * softplus(o3).  Weights W[out][in], FP32, device. */
+typedef struct hp_mlp {
+    float *W1, *b1, *W2, *b2, *W3, *b3;
+} hp_mlp;
+
+/* Workspace bytes hp_build_table needs for n points and these views (host
+ * only, no GPU needed).  Returns 0 and sets *status on invalid input. */
+size_t hp_table_workspace(int64_t n, const hp_camera *cams, int32_t n_views,
+                          const hp_params *p, hp_status *status);
+
+/* Guard band and window bound of one view (host only).  The bound
+ * delta = f rho L^2 / (t - rho |w|) on the pixel offset of a point within
+ * rho(t) of a ray with normalised image coordinate w (L^2 = 1 + |w|^2) does
+ * not grow with t, so its value at t_near and the image corner bounds every
+ * neighbour; g = floor(0.5 + delta) + 1. */
+hp_status hp_view_bounds(const hp_camera *cam, const hp_params *p, int32_t *g, float *delta_max);
+
+/* Build the pixel table (Sec. 3.2, Fig. 2) for n_views cameras.
+ *  xyz: device, n x 3 FP32 world positions.  Non-finite points and points
+ *      not in front of a camera (z <= 0) or projecting outside the image
+ *      plus its guard band are not inserted for that camera.
+ *  ws: device workspace of ws_bytes >= hp_table_workspace(...).  The table
+ *      lives in it; keep it alive and unmodified while the table is used.
+ *  out: host struct filled with pointers into ws and per-view geometry.
+ * Errors: HP_E_INVALID (null pointers, bad camera or parameters),
+ *  HP_E_WORKSPACE, HP_E_CAPACITY (n * n_views or bucket count >= 2^31). */
+hp_status hp_build_table(const float *xyz, int64_t n, const hp_camera *cams, int32_t n_views,
+                         const hp_params *p, void *ws, size_t ws_bytes, hp_table *out,
+                         void *stream);
+
+/* Search and sample every ray of every view of the table (Sec. 3.2-3.3).
+ *  cams and p must be the ones the table was built with.
+ *  out: device arrays sized for R = tab->n_rays rays (see hp_samples).
+ * Errors: HP_E_INVALID, HP_E_UNSUPPORTED (K > HP_MAX_K). */
+hp_status hp_search_sample(const hp_table *tab, const hp_camera *cams, int32_t n_views,
+                           const hp_params *p, hp_samples *out, void *stream);
+
+/* Decode and composite (Sec. 3.4, Eq. 2).
+ *  smp: samples from hp_search_sample for R rays.
+ *  feat: device, n_points x C FP32 features; C must be HP_FEAT_DIM.
+ *  precision: HP_FP32, or HP_BF16 (decoder operands rounded to bfloat16,
+ *      FP32 accumulation; aggregation and compositing stay FP32).
+ *  rgb (R x 3), depth (R), acc (R): device FP32 outputs.  depth and acc may
+ *      be NULL.
+ * Errors: HP_E_INVALID, HP_E_UNSUPPORTED (C != HP_FEAT_DIM). */
+hp_status hp_render(const hp_samples *smp, int64_t R, const float *feat, int32_t C,
+                    const hp_mlp *mlp, int32_t precision, const hp_params *p, float *rgb,
+                    float *depth, float *acc, void *stream);
+
+/* Workspace bytes hp_render_backward needs (host only). */
+size_t hp_backward_workspace(const hp_table *tab, const hp_params *p, hp_status *status);
+
+/* Gradient of L with respect to the features and MLP parameters, given
+ * grad_rgb = dL/drgb (device, R x 3).  Search and sampling are recomputed
+ * from the table instead of being stored; samples depend on geometry only.
+ *  grad_feat (n_points x C) and every array of grad_mlp are ADDED to
+ *  (zero them first for a plain gradient).  Accumulation order is not fixed,
+ *  so results are reproducible to rounding only.
+ * Errors: HP_E_INVALID, HP_E_WORKSPACE, HP_E_UNSUPPORTED. */
+hp_status hp_render_backward(const hp_table *tab, const hp_camera *cams, int32_t n_views,
+                             const float *feat, int32_t C, const hp_mlp *mlp, int32_t precision,
+                             const hp_params *p, const float *grad_rgb, float *grad_feat,
+                             hp_mlp *grad_mlp, void *ws, size_t ws_bytes, void *stream);
+
+/* Status text, and the last HIP error code seen by this thread. */
+const char *hp_status_str(hp_status s);
+int32_t hp_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HASHPOINT_H */

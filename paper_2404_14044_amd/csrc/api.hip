@@ -1,0 +1,314 @@
+// C ABI of the HashPoint library: host-side validation, workspace layout and
+// kernel launches.  No allocation, no global state.
+#include <math.h>
+#include <string.h>
+
+#include "hp_device.hpp"
+#include "hp_kernels.hpp"
+#include "hp_search.hpp"
+#include "hp_table_ws.hpp"
+
+namespace {
+
+thread_local int32_t g_last_hip_error = 0;
+
+hp_status hip_fail(hipError_t e)
+{
+    g_last_hip_error = (int32_t)e;
+    return HP_E_HIP;
+}
+
+bool finite_f(float x) { return isfinite(x) != 0; }
+
+bool valid_camera(const hp_camera &c)
+{
+    if (c.W < 1 || c.H < 1) return false;
+    if (!(c.fx > 0.0f) || !(c.fy > 0.0f) || !finite_f(c.fx) || !finite_f(c.fy)) return false;
+    if (!finite_f(c.cx) || !finite_f(c.cy)) return false;
+    for (int i = 0; i < 9; ++i)
+        if (!finite_f(c.R[i])) return false;
+    for (int i = 0; i < 3; ++i)
+        if (!finite_f(c.C[i])) return false;
+    return true;
+}
+
+bool valid_params(const hp_params &p)
+{
+    if (!(p.radius > 0.0f) || !finite_f(p.radius)) return false;
+    if (!(p.inv_tref >= 0.0f) || !finite_f(p.inv_tref)) return false;
+    if (!(p.t_near > 0.0f) || !(p.t_far >= p.t_near) || !finite_f(p.t_far)) return false;
+    if (p.K < 1 || p.n_samples < 1 || p.n_samples > HP_MAX_SAMPLES) return false;
+    if (p.m_cap < 1 || p.m_cap > HP_MAX_MCAP) return false;
+    if (!(p.gamma > 0.0f) || !(p.gamma <= 1.0f)) return false;
+    if (!(p.inv_beta2 >= 0.0f) || !finite_f(p.inv_beta2)) return false;
+    if (!(p.eps_w >= 0.0f) || !finite_f(p.eps_w)) return false;
+    if (!(p.eps_idw > 0.0f) || !finite_f(p.eps_idw)) return false;
+    if (!(p.delta_last > 0.0f) || !finite_f(p.delta_last)) return false;
+    for (int i = 0; i < 3; ++i)
+        if (!finite_f(p.bg[i])) return false;
+    if (p.layout != HP_LAYOUT_ROWMAJOR && p.layout != HP_LAYOUT_TILED) return false;
+    if (p.flags != 0) return false;
+    return true;
+}
+
+// Pixel-offset bound of a neighbour (see hashpoint.h, hp_view_bounds).
+bool view_bound(const hp_camera &c, const hp_params &p, double &delta)
+{
+    double w2max = 0.0;
+    const double us[2] = {0.5, c.W - 0.5}, vs[2] = {0.5, c.H - 0.5};
+    for (double u : us)
+        for (double v : vs) {
+            const double a = (u - c.cx) / c.fx, b = (v - c.cy) / c.fy;
+            w2max = fmax(w2max, a * a + b * b);
+        }
+    const double f = fmax((double)c.fx, (double)c.fy);
+    const double rho = (double)p.radius * fmax(1.0, (double)p.t_near * p.inv_tref);
+    const double den = (double)p.t_near - rho * sqrt(w2max);
+    if (!(den > 0.0)) return false;
+    delta = f * rho * (1.0 + w2max) / den;
+    return isfinite(delta) != 0 && delta < 1e6;
+}
+
+struct Geometry {
+    hp::ViewSet vs;
+    int64_t n_buckets = 0, n_rays = 0;
+};
+
+hp_status plan_views(const hp_camera *cams, int32_t n_views, const hp_params &p, Geometry &geo,
+                     hp_view_info *info)
+{
+    memset(&geo.vs, 0, sizeof(geo.vs));
+    geo.vs.n = n_views;
+    geo.vs.layout = p.layout;
+    int64_t nb = 0, nr = 0;
+    for (int i = 0; i < n_views; ++i) {
+        const hp_camera &c = cams[i];
+        if (!valid_camera(c)) return HP_E_INVALID;
+        double delta;
+        if (!view_bound(c, p, delta)) return HP_E_INVALID;
+        const int32_t g = (int32_t)floor(0.5 + delta) + 1;
+        int64_t Wg = (int64_t)c.W + 2 * g, Hg = (int64_t)c.H + 2 * g;
+        if (p.layout == HP_LAYOUT_TILED) {
+            Wg = (Wg + 7) / 8 * 8;
+            Hg = (Hg + 7) / 8 * 8;
+        }
+        if (Wg * Hg >= ((int64_t)1 << 31) - nb - 1) return HP_E_CAPACITY;
+        hp::ViewK &V = geo.vs.v[i];
+        V.fx = c.fx;
+        V.fy = c.fy;
+        V.cx = c.cx;
+        V.cy = c.cy;
+        memcpy(V.R, c.R, sizeof(V.R));
+        memcpy(V.C, c.C, sizeof(V.C));
+        V.W = c.W;
+        V.H = c.H;
+        V.g = g;
+        V.Wg = (int32_t)Wg;
+        V.Hg = (int32_t)Hg;
+        V.bucket_base = (int32_t)nb;
+        V.ray_base = (int32_t)nr;
+        V.dmax = (float)(delta * (1.0 + 1e-5) + 1e-3);
+        V.slot_base = 0;
+        if (info) {
+            info[i].W = c.W;
+            info[i].H = c.H;
+            info[i].g = g;
+            info[i].Wg = V.Wg;
+            info[i].Hg = V.Hg;
+            info[i].bucket_base = V.bucket_base;
+            info[i].ray_base = V.ray_base;
+            info[i].delta_max = (float)delta;
+        }
+        nb += Wg * Hg;
+        nr += (int64_t)c.W * c.H;
+        if (nr >= ((int64_t)1 << 31)) return HP_E_CAPACITY;
+    }
+    geo.n_buckets = nb;
+    geo.n_rays = nr;
+    return HP_OK;
+}
+
+int knn_template(int K) { return K <= 4 ? 4 : K <= 8 ? 8 : K <= 16 ? 16 : 32; }
+
+}  // namespace
+
+extern "C" {
+
+const char *hp_status_str(hp_status s)
+{
+    switch (s) {
+    case HP_OK: return "ok";
+    case HP_E_INVALID: return "invalid argument";
+    case HP_E_WORKSPACE: return "workspace missing or too small";
+    case HP_E_UNSUPPORTED: return "unsupported request";
+    case HP_E_CAPACITY: return "index capacity exceeded (int32)";
+    case HP_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+int32_t hp_last_hip_error(void) { return g_last_hip_error; }
+
+hp_status hp_view_bounds(const hp_camera *cam, const hp_params *p, int32_t *g, float *delta_max)
+{
+    if (!cam || !p || !valid_camera(*cam) || !valid_params(*p)) return HP_E_INVALID;
+    double delta;
+    if (!view_bound(*cam, *p, delta)) return HP_E_INVALID;
+    if (g) *g = (int32_t)floor(0.5 + delta) + 1;
+    if (delta_max) *delta_max = (float)delta;
+    return HP_OK;
+}
+
+size_t hp_table_workspace(int64_t n, const hp_camera *cams, int32_t n_views, const hp_params *p,
+                          hp_status *status)
+{
+    hp_status st = HP_OK;
+    Geometry geo;
+    if (!cams || !p || n < 0 || n_views < 1 || n_views > HP_MAX_VIEWS || !valid_params(*p)) st = HP_E_INVALID;
+    else if (n * n_views >= ((int64_t)1 << 31)) st = HP_E_CAPACITY;
+    else st = plan_views(cams, n_views, *p, geo, nullptr);
+    if (status) *status = st;
+    if (st != HP_OK) return 0;
+    return hp::table_ws_layout(nullptr, n, n_views, geo.n_buckets).bytes;
+}
+
+hp_status hp_build_table(const float *xyz, int64_t n, const hp_camera *cams, int32_t n_views,
+                         const hp_params *p, void *ws, size_t ws_bytes, hp_table *out, void *stream)
+{
+    if (!cams || !p || !out || n < 0 || n_views < 1 || n_views > HP_MAX_VIEWS) return HP_E_INVALID;
+    if (n > 0 && !xyz) return HP_E_INVALID;
+    if (!valid_params(*p)) return HP_E_INVALID;
+    if (n * n_views >= ((int64_t)1 << 31)) return HP_E_CAPACITY;
+    Geometry geo;
+    hp_view_info info[HP_MAX_VIEWS];
+    const hp_status st = plan_views(cams, n_views, *p, geo, info);
+    if (st != HP_OK) return st;
+    const hp::TableWs tw = hp::table_ws_layout(ws, n, n_views, geo.n_buckets);
+    if (!ws || ws_bytes < tw.bytes) return HP_E_WORKSPACE;
+
+    const hipError_t e =
+        hp::launch_build(xyz, n, geo.vs, geo.n_buckets, tw, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+
+    memset(out, 0, sizeof(*out));
+    out->n_views = n_views;
+    out->layout = p->layout;
+    out->n_points = n;
+    out->n_buckets = geo.n_buckets;
+    out->n_rays = geo.n_rays;
+    out->offsets = tw.offsets;
+    out->pts = reinterpret_cast<float *>(tw.pts);
+    out->perm = tw.perm;
+    out->slot_of = tw.slot_of;
+    out->scratch = tw.views;
+    memcpy(out->views, info, sizeof(hp_view_info) * n_views);
+    return HP_OK;
+}
+
+static hp_status make_ctx(const hp_table *tab, const hp_camera *cams, int32_t n_views,
+                          const hp_params *p, hp::SearchCtx &c)
+{
+    if (!tab || !cams || !p || n_views != tab->n_views || !valid_params(*p)) return HP_E_INVALID;
+    if (p->layout != tab->layout) return HP_E_INVALID;
+    if (p->K > HP_MAX_K) return HP_E_UNSUPPORTED;
+    if (!tab->offsets || !tab->pts || !tab->slot_of || !tab->scratch) return HP_E_INVALID;
+    Geometry geo;
+    const hp_status st = plan_views(cams, n_views, *p, geo, nullptr);
+    if (st != HP_OK) return st;
+    if (geo.n_rays != tab->n_rays || geo.n_buckets != tab->n_buckets) return HP_E_INVALID;
+    for (int i = 0; i < n_views; ++i)
+        if (tab->views[i].g != geo.vs.v[i].g || tab->views[i].W != cams[i].W ||
+            tab->views[i].H != cams[i].H)
+            return HP_E_INVALID;
+    c.offsets = tab->offsets;
+    c.pts = reinterpret_cast<const float4 *>(tab->pts);
+    c.slot_of = tab->slot_of;
+    c.views = reinterpret_cast<const hp::ViewK *>(tab->scratch);
+    c.n_views = n_views;
+    c.layout = tab->layout;
+    c.n_points = tab->n_points;
+    c.n_rays = tab->n_rays;
+    c.radius = p->radius;
+    c.inv_tref = p->inv_tref;
+    c.t_near = p->t_near;
+    c.t_far = p->t_far;
+    c.gamma = p->gamma;
+    c.inv_beta2 = p->inv_beta2;
+    c.eps_w = p->eps_w;
+    c.K = p->K;
+    c.S = p->n_samples;
+    c.M = p->m_cap;
+    return HP_OK;
+}
+
+hp_status hp_search_sample(const hp_table *tab, const hp_camera *cams, int32_t n_views,
+                           const hp_params *p, hp_samples *out, void *stream)
+{
+    hp::SearchCtx c;
+    const hp_status st = make_ctx(tab, cams, n_views, p, c);
+    if (st != HP_OK) return st;
+    if (!out || !out->n_sel || !out->primary || !out->n_nbr || !out->flags || !out->t ||
+        !out->knn_idx || !out->knn_dist)
+        return HP_E_INVALID;
+    if ((out->nbr_idx == nullptr) != (out->nbr_t == nullptr)) return HP_E_INVALID;
+    hp::SampleOut o{out->n_sel, out->primary, out->n_nbr, out->flags, out->t,
+                    out->knn_idx, out->knn_dist, out->nbr_idx, out->nbr_t};
+    const hipError_t e = hp::launch_search_sample(c, o, knn_template(p->K), (hipStream_t)stream);
+    return e == hipSuccess ? HP_OK : hip_fail(e);
+}
+
+hp_status hp_render(const hp_samples *smp, int64_t R, const float *feat, int32_t C,
+                    const hp_mlp *mlp, int32_t precision, const hp_params *p, float *rgb,
+                    float *depth, float *acc, void *stream)
+{
+    if (!smp || !mlp || !p || R < 0 || !valid_params(*p)) return HP_E_INVALID;
+    if (C != HP_FEAT_DIM) return HP_E_UNSUPPORTED;
+    if (precision != HP_FP32 && precision != HP_BF16) return HP_E_INVALID;
+    if (p->K > HP_MAX_K) return HP_E_UNSUPPORTED;
+    if (R >= ((int64_t)1 << 31)) return HP_E_CAPACITY;
+    if (R > 0 && (!smp->n_sel || !smp->t || !smp->knn_idx || !smp->knn_dist || !feat || !rgb))
+        return HP_E_INVALID;
+    if (!mlp->W1 || !mlp->b1 || !mlp->W2 || !mlp->b2 || !mlp->W3 || !mlp->b3) return HP_E_INVALID;
+    hp::RenderArgs a;
+    a.n_sel = smp->n_sel;
+    a.t = smp->t;
+    a.knn_idx = smp->knn_idx;
+    a.knn_dist = smp->knn_dist;
+    a.n_rays = R;
+    a.feat = feat;
+    a.W1 = mlp->W1;
+    a.b1 = mlp->b1;
+    a.W2 = mlp->W2;
+    a.b2 = mlp->b2;
+    a.W3 = mlp->W3;
+    a.b3 = mlp->b3;
+    a.K = p->K;
+    a.S = p->n_samples;
+    a.eps_idw = p->eps_idw;
+    a.delta_last = p->delta_last;
+    for (int i = 0; i < 3; ++i) a.bg[i] = p->bg[i];
+    a.rgb = rgb;
+    a.depth = depth;
+    a.acc = acc;
+    const hipError_t e = hp::launch_render(a, precision, (hipStream_t)stream);
+    return e == hipSuccess ? HP_OK : hip_fail(e);
+}
+
+size_t hp_backward_workspace(const hp_table *tab, const hp_params *p, hp_status *status)
+{
+    if (status) *status = (tab && p) ? HP_E_UNSUPPORTED : HP_E_INVALID;
+    return 0;
+}
+
+hp_status hp_render_backward(const hp_table *tab, const hp_camera *cams, int32_t n_views,
+                             const float *feat, int32_t C, const hp_mlp *mlp, int32_t precision,
+                             const hp_params *p, const float *grad_rgb, float *grad_feat,
+                             hp_mlp *grad_mlp, void *ws, size_t ws_bytes, void *stream)
+{
+    (void)tab; (void)cams; (void)n_views; (void)feat; (void)C; (void)mlp; (void)precision;
+    (void)p; (void)grad_rgb; (void)grad_feat; (void)grad_mlp; (void)ws; (void)ws_bytes;
+    (void)stream;
+    return HP_E_UNSUPPORTED;
+}
+
+}  // extern "C"

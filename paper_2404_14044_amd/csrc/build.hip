@@ -1,0 +1,333 @@
+// Pixel-table construction (Sec. 3.2, Fig. 2): project every point into every
+// view, count points per bucket, scan the counts into bucket offsets, scatter
+// the points into their bucket with atomics, and order each bucket by depth.
+//
+// Passes (each a coalesced sweep except the scatter and the bucket sorts):
+//   k_project      (view, point)  -> (bucket, z) and a per-bucket count
+//   k_scan_*       counts         -> exclusive offsets, three passes
+//   k_scatter      (view, point)  -> 64-bit key (z bits, point index) per slot
+//   k_sort_small   one lane per bucket of at most 16 points, register network
+//   k_sort_big     one workgroup per larger bucket, bitonic in LDS or global
+//   k_materialize  one lane per slot: camera-space point, perm, slot_of
+#include "hp_device.hpp"
+#include "hp_kernels.hpp"
+#include "hp_table_ws.hpp"
+
+namespace hp {
+
+__global__ void k_init_views(ViewSet vs, ViewK *out)
+{
+    const int i = threadIdx.x;
+    if (i < vs.n) out[i] = vs.v[i];
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t val, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = val;
+}
+
+// grid: (ceil(n / 256), n_views)
+__global__ void __launch_bounds__(256) k_project(const float *__restrict__ xyz, int64_t n,
+                                                 const ViewK *__restrict__ views, int layout,
+                                                 int2 *__restrict__ kz, int32_t *__restrict__ count)
+{
+    const int vi = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const ViewK &V = views[vi];
+    float x, y, z;
+    to_camera(V, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], x, y, z);
+    int32_t key = -1;
+    if (z > 0.0f && __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z)) {
+        const float uf = fma_rn(V.fx, x / z, V.cx);
+        const float vf = fma_rn(V.fy, y / z, V.cy);
+        const float lo = (float)(-V.g);
+        if (uf >= lo && uf < (float)(V.W + V.g) && vf >= lo && vf < (float)(V.H + V.g)) {
+            const int bx = (int)__builtin_floorf(uf) + V.g;
+            const int by = (int)__builtin_floorf(vf) + V.g;
+            key = bucket_of(V, layout, bx, by);
+            atomicAdd(&count[key], 1);
+        }
+    }
+    kz[(int64_t)vi * n + i] = make_int2(key, __float_as_int(z));
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32 counts -> offsets[n + 1]
+// ---------------------------------------------------------------------------
+constexpr int SCAN_T = 256;
+constexpr int SCAN_PER = 16;
+constexpr int SCAN_TILE = SCAN_T * SCAN_PER;
+
+__device__ __forceinline__ int block_excl_scan(int v, int *sh_warp, int &total)
+{
+    const int l = lane_id();
+    const int w = threadIdx.x / WAVE;
+    const int inc = wave_incl_scan_i32(v);
+    if (l == WAVE - 1) sh_warp[w] = inc;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_T / WAVE; ++k) {
+        const int s = sh_warp[k];
+        base += (k < w) ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return base + inc - v;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_reduce(const int32_t *__restrict__ in, int64_t n,
+                                                        int32_t *__restrict__ block_sums)
+{
+    __shared__ int sh[SCAN_T / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; ++k) s += (base + k < n) ? in[base + k] : 0;
+    int total;
+    block_excl_scan(s, sh, total);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// single workgroup: exclusive scan of the block sums in place
+__global__ void __launch_bounds__(SCAN_T) k_scan_blocks(int32_t *__restrict__ sums, int64_t nb)
+{
+    __shared__ int sh[SCAN_T / WAVE];
+    int carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += SCAN_T) {
+        const int64_t i = b0 + threadIdx.x;
+        const int v = (i < nb) ? sums[i] : 0;
+        int total;
+        const int ex = block_excl_scan(v, sh, total);
+        if (i < nb) sums[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_apply(const int32_t *__restrict__ in, int64_t n,
+                                                       const int32_t *__restrict__ block_base,
+                                                       int32_t *__restrict__ out)
+{
+    __shared__ int sh[SCAN_T / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER;
+    int v[SCAN_PER];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int run = block_excl_scan(s, sh, total) + block_base[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = block_base[blockIdx.x] + total;
+}
+
+// ---------------------------------------------------------------------------
+// scatter: one 64-bit key per slot, (z bits) << 32 | point index.  z > 0, so
+// the bits of z order like z, and the key orders by (z, index).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_scatter(const int2 *__restrict__ kz, int64_t total,
+                                                 int64_t n, const int32_t *__restrict__ offsets,
+                                                 int32_t *__restrict__ count,
+                                                 uint64_t *__restrict__ skey)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int2 e = kz[i];
+    if (e.x < 0) return;
+    const int pos = atomicSub(&count[e.x], 1) - 1;
+    const int64_t p = i % n;
+    skey[offsets[e.x] + pos] = ((uint64_t)(uint32_t)e.y << 32) | (uint32_t)p;
+}
+
+// ---------------------------------------------------------------------------
+// per-bucket sort of the keys
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void sort_net(uint64_t (&k)[N])
+{
+    // bitonic network with all comparators ascending in the merge phase
+#pragma unroll
+    for (int s = 2; s <= N; s <<= 1) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int p = i ^ (s - 1);
+            if (p > i) {
+                const uint64_t a = k[i], b = k[p];
+                k[i] = umin64(a, b);
+                k[p] = umax64(a, b);
+            }
+        }
+#pragma unroll
+        for (int j = s >> 2; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int p = i ^ j;
+                if (p > i) {
+                    const uint64_t a = k[i], b = k[p];
+                    k[i] = umin64(a, b);
+                    k[p] = umax64(a, b);
+                }
+            }
+        }
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void sort_bucket_regs(uint64_t *__restrict__ skey, int start, int cnt)
+{
+    uint64_t k[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) k[i] = (i < cnt) ? skey[start + i] : ~0ull;
+    sort_net<N>(k);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (i < cnt) skey[start + i] = k[i];
+}
+
+constexpr int SMALL_MAX = 16;
+
+__global__ void __launch_bounds__(256) k_sort_small(const int32_t *__restrict__ offsets, int64_t nb,
+                                                    uint64_t *__restrict__ skey,
+                                                    int32_t *__restrict__ big_list,
+                                                    int32_t *__restrict__ big_n)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int start = offsets[b];
+    const int cnt = offsets[b + 1] - start;
+    if (cnt <= 1) return;
+    if (cnt <= 4) sort_bucket_regs<4>(skey, start, cnt);
+    else if (cnt <= 8) sort_bucket_regs<8>(skey, start, cnt);
+    else if (cnt <= SMALL_MAX) sort_bucket_regs<16>(skey, start, cnt);
+    else big_list[atomicAdd(big_n, 1)] = (int32_t)b;
+}
+
+constexpr int BIG_T = 256;
+constexpr int BIG_LDS = 4096;
+
+// Bitonic sort of cnt keys with all comparators placing the minimum at the
+// lower index ("flip" form): virtual +inf keys beyond cnt never move, so the
+// length need not be a power of two.
+template <typename Load, typename Store>
+__device__ void block_flip_bitonic(int cnt, Load ld, Store st)
+{
+    int P = 1;
+    while (P < cnt) P <<= 1;
+    for (int s = 2; s <= P; s <<= 1) {
+        for (int j = s >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P / 2; i += blockDim.x) {
+                // comparator i of this stage joins positions lo < hi
+                int lo, hi;
+                if (j == (s >> 1)) {
+                    const int blk = i / j, off = i % j;
+                    lo = blk * s + off;
+                    hi = blk * s + s - 1 - off;
+                } else {
+                    const int blk = i / j, off = i % j;
+                    lo = blk * 2 * j + off;
+                    hi = lo + j;
+                }
+                if (hi < cnt) {
+                    const uint64_t a = ld(lo), b = ld(hi);
+                    if (b < a) {
+                        st(lo, b);
+                        st(hi, a);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void __launch_bounds__(BIG_T) k_sort_big(const int32_t *__restrict__ offsets,
+                                                    uint64_t *__restrict__ skey,
+                                                    const int32_t *__restrict__ big_list,
+                                                    const int32_t *__restrict__ big_n)
+{
+    __shared__ uint64_t sh[BIG_LDS];
+    const int nbig = *big_n;
+    for (int it = blockIdx.x; it < nbig; it += gridDim.x) {
+        const int b = big_list[it];
+        const int start = offsets[b];
+        const int cnt = offsets[b + 1] - start;
+        uint64_t *g = skey + start;
+        if (cnt <= BIG_LDS) {
+            for (int i = threadIdx.x; i < cnt; i += blockDim.x) sh[i] = g[i];
+            __syncthreads();
+            block_flip_bitonic(cnt, [&](int i) { return sh[i]; }, [&](int i, uint64_t v) { sh[i] = v; });
+            for (int i = threadIdx.x; i < cnt; i += blockDim.x) g[i] = sh[i];
+        } else {
+            block_flip_bitonic(cnt, [&](int i) { return g[i]; },
+                               [&](int i, uint64_t v) { g[i] = v; });
+        }
+        __syncthreads();
+    }
+}
+
+// first slot of every view (views are contiguous in the bucket space)
+__global__ void k_view_slots(const int32_t *__restrict__ offsets, ViewK *views, int n_views)
+{
+    const int i = threadIdx.x;
+    if (i < n_views) views[i].slot_base = offsets[views[i].bucket_base];
+}
+
+__global__ void __launch_bounds__(256) k_materialize(const uint64_t *__restrict__ skey,
+                                                     const int32_t *__restrict__ n_in_ptr,
+                                                     const float *__restrict__ xyz, int64_t n,
+                                                     const ViewK *__restrict__ views, int n_views,
+                                                     float4 *__restrict__ pts,
+                                                     int32_t *__restrict__ perm,
+                                                     int32_t *__restrict__ slot_of)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= *n_in_ptr) return;
+    int vi = 0;
+    while (vi + 1 < n_views && views[vi + 1].slot_base <= s) ++vi;
+    const uint64_t key = skey[s];
+    const int32_t idx = (int32_t)(uint32_t)key;
+    float x, y, z;
+    to_camera(views[vi], xyz[3 * (int64_t)idx], xyz[3 * (int64_t)idx + 1], xyz[3 * (int64_t)idx + 2],
+              x, y, z);
+    pts[s] = make_float4(x, y, z, __int_as_float(idx));
+    perm[s] = idx;
+    slot_of[(int64_t)vi * n + idx] = (int32_t)s;
+}
+
+}  // namespace hp
+
+namespace hp {
+
+hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t n_buckets,
+                        const TableWs &tw, hipStream_t s)
+{
+    const int V = vs.n;
+    const int64_t nv = n * V;
+    k_init_views<<<1, HP_MAX_VIEWS, 0, s>>>(vs, tw.views);
+    k_fill_i32<<<1024, 256, 0, s>>>(tw.count, 0, n_buckets);
+    k_fill_i32<<<1, 64, 0, s>>>(tw.big_n, 0, 1);
+    if (n > 0) k_project<<<dim3((unsigned)((n + 255) / 256), V), 256, 0, s>>>(xyz, n, tw.views, vs.layout, tw.kz, tw.count);
+    const int64_t nblk = (n_buckets + SCAN_TILE - 1) / SCAN_TILE;
+    k_scan_reduce<<<(unsigned)nblk, SCAN_T, 0, s>>>(tw.count, n_buckets, tw.block_sums);
+    k_scan_blocks<<<1, SCAN_T, 0, s>>>(tw.block_sums, nblk);
+    k_scan_apply<<<(unsigned)nblk, SCAN_T, 0, s>>>(tw.count, n_buckets, tw.block_sums, tw.offsets);
+    if (nv > 0) k_scatter<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tw.kz, nv, n, tw.offsets, tw.count, tw.skey);
+    k_sort_small<<<(unsigned)((n_buckets + 255) / 256), 256, 0, s>>>(tw.offsets, n_buckets, tw.skey, tw.big_list, tw.big_n);
+    k_sort_big<<<512, BIG_T, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n);
+    k_view_slots<<<1, HP_MAX_VIEWS, 0, s>>>(tw.offsets, tw.views, V);
+    if (nv > 0)
+        k_materialize<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tw.skey, tw.offsets + n_buckets, xyz, n, tw.views, V, tw.pts, tw.perm, tw.slot_of);
+    return hipGetLastError();
+}
+
+}  // namespace hp

@@ -1,0 +1,204 @@
+// Device-side building blocks shared by the HashPoint kernels (gfx950, wave64).
+//
+// Everything that decides a discrete result (which bucket a point falls in,
+// whether a point is a neighbour of a ray, which neighbours are nearest, which
+// candidates become samples) is written as one fixed sequence of correctly
+// rounded binary32 operations, with fused multiply-adds only where __fmaf_rn
+// is spelled out.  The library is compiled with -ffp-contract=off so the
+// compiler adds none, and with correctly rounded division and square root.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hashpoint.h"
+
+namespace hp {
+
+constexpr int WAVE = 64;
+
+// Per-view constants, stored once per table in device memory.
+struct ViewK {
+    float fx, fy, cx, cy;
+    float R[9];
+    float C[3];
+    int32_t W, H, g, Wg, Hg;
+    int32_t bucket_base, ray_base;
+    float dmax;        // window radius in pixels, with margin
+    int32_t slot_base; // first slot of the view (written on the device)
+    int32_t pad;
+};
+
+struct ViewSet {
+    int32_t n;
+    int32_t layout;
+    ViewK v[HP_MAX_VIEWS];
+};
+
+__device__ __forceinline__ float fma_rn(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Camera-space position p_c = R (p - C).
+__device__ __forceinline__ void to_camera(const ViewK &V, float px, float py, float pz, float &x,
+                                          float &y, float &z)
+{
+    const float qx = px - V.C[0], qy = py - V.C[1], qz = pz - V.C[2];
+    x = fma_rn(V.R[2], qz, fma_rn(V.R[1], qy, V.R[0] * qx));
+    y = fma_rn(V.R[5], qz, fma_rn(V.R[4], qy, V.R[3] * qx));
+    z = fma_rn(V.R[8], qz, fma_rn(V.R[7], qy, V.R[6] * qx));
+}
+
+// Bucket of grid cell (bx, by) of a view.  Row-major, or 8x8 tiles stored
+// row-major with row-major cells inside each tile.
+__device__ __forceinline__ int32_t bucket_of(const ViewK &V, int layout, int bx, int by)
+{
+    if (layout == HP_LAYOUT_TILED) {
+        const int ntx = V.Wg >> 3;
+        return V.bucket_base + ((((by >> 3) * ntx) + (bx >> 3)) << 6) + ((by & 7) << 3) + (bx & 7);
+    }
+    return V.bucket_base + by * V.Wg + bx;
+}
+
+// Unit ray through the centre of pixel (u, v), camera coordinates; also the
+// normalised image coordinates (a, b) and L = sqrt(1 + a^2 + b^2).
+__device__ __forceinline__ void ray_dir(const ViewK &V, int u, int v, float &dx, float &dy,
+                                        float &dz, float &a, float &b, float &L)
+{
+    a = (((float)u + 0.5f) - V.cx) / V.fx;
+    b = (((float)v + 0.5f) - V.cy) / V.fy;
+    L = __builtin_sqrtf(fma_rn(b, b, fma_rn(a, a, 1.0f)));
+    dx = a / L;
+    dy = b / L;
+    dz = 1.0f / L;
+}
+
+// rho(t) = radius * max(1, t * inv_tref)
+__device__ __forceinline__ float search_radius(float radius, float inv_tref, float t)
+{
+    const float s = t * inv_tref;
+    return radius * (s > 1.0f ? s : 1.0f);
+}
+
+// Ray parameter of camera-space point x on unit ray d.
+__device__ __forceinline__ float ray_param(float x, float y, float z, float dx, float dy, float dz)
+{
+    return fma_rn(z, dz, fma_rn(y, dy, x * dx));
+}
+
+// Squared distance between point x and the ray point s * d.
+__device__ __forceinline__ float dist2_at(float x, float y, float z, float dx, float dy, float dz,
+                                          float s)
+{
+    const float ex = fma_rn(-s, dx, x);
+    const float ey = fma_rn(-s, dy, y);
+    const float ez = fma_rn(-s, dz, z);
+    return fma_rn(ez, ez, fma_rn(ey, ey, ex * ex));
+}
+
+// exp(x) for x <= 0 in binary32, bit-reproducible: x = k ln2 + r with
+// ln2 split in a 16-bit head (k * head exact) and a tail, |r| <= ln2 / 2,
+// exp(r) by its Taylor polynomial of degree 7 in Horner form (truncation
+// below 1e-8 relative), then scaled by 2^k built from exponent bits.  Each
+// constant is the binary64 value rounded once to binary32.  Returns 0 below
+// -86 and for NaN.  Never exceeds 1.
+__device__ __forceinline__ float exp_neg(float x)
+{
+    if (!(x >= -86.0f)) return 0.0f;
+    constexpr float kInvLn2 = (float)(1.0 / 0.69314718055994530942);
+    constexpr float kLn2Head = 0.693145751953125f;
+    constexpr float kLn2Tail = (float)(0.69314718055994530942 - 0.693145751953125);
+    const float k = __builtin_rintf(x * kInvLn2);
+    float r = fma_rn(-k, kLn2Head, x);
+    r = fma_rn(-k, kLn2Tail, r);
+    float q = (float)(1.0 / 5040.0);
+    q = fma_rn(q, r, (float)(1.0 / 720.0));
+    q = fma_rn(q, r, (float)(1.0 / 120.0));
+    q = fma_rn(q, r, (float)(1.0 / 24.0));
+    q = fma_rn(q, r, (float)(1.0 / 6.0));
+    q = fma_rn(q, r, 0.5f);
+    q = fma_rn(q, r, 1.0f);
+    q = fma_rn(q, r, 1.0f);
+    const int ki = (int)k;
+    return q * __uint_as_float((uint32_t)(ki + 127) << 23);
+}
+
+// ---------------------------------------------------------------------------
+// wave-level helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
+{
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, WAVE);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, WAVE);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a < b ? b : a; }
+
+// Ascending bitonic sort of one 64-bit key per lane across the wave.
+__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t x)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int k = 2; k <= WAVE; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint64_t y = shfl_xor_u64(x, j);
+            const bool up = (l & k) == 0;
+            const bool lower = (l & j) == 0;
+            x = (lower == up) ? umin64(x, y) : umax64(x, y);
+        }
+    }
+    return x;
+}
+
+// Keep the 64 smallest of two ascending wave-sorted lists, ascending.
+__device__ __forceinline__ uint64_t wave_merge_low_u64(uint64_t a, uint64_t b)
+{
+    const int l = lane_id();
+    uint64_t x = umin64(a, shfl_u64(b, WAVE - 1 - l));
+#pragma unroll
+    for (int j = WAVE >> 1; j > 0; j >>= 1) {
+        const uint64_t y = shfl_xor_u64(x, j);
+        x = ((l & j) == 0) ? umin64(x, y) : umax64(x, y);
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
+
+// number of set bits of m below this lane
+__device__ __forceinline__ int rank_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
+__device__ __forceinline__ int wave_incl_scan_i32(int v)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int y = __shfl_up(v, o, WAVE);
+        if (l >= o) v += y;
+    }
+    return v;
+}
+
+__device__ __forceinline__ float readlane_f32(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ int readlane_i32(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+}  // namespace hp

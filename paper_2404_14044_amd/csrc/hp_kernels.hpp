@@ -1,0 +1,49 @@
+// Launch interfaces of the HashPoint kernels (host side of the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hashpoint.h"
+
+namespace hp {
+
+struct ViewK;
+struct ViewSet;
+struct SearchCtx;
+
+struct SampleOut {
+    int32_t *n_sel, *primary, *n_nbr;
+    uint32_t *flags;
+    float *t;
+    int32_t *knn_idx;
+    float *knn_dist;
+    int32_t *nbr_idx;
+    float *nbr_t;
+};
+
+struct RenderArgs {
+    const int32_t *n_sel;
+    const float *t;
+    const int32_t *knn_idx;
+    const float *knn_dist;
+    int64_t n_rays;
+    const float *feat;
+    const float *W1, *b1, *W2, *b2, *W3, *b3;
+    int32_t K, S;
+    float eps_idw, delta_last;
+    float bg[3];
+    float *rgb, *depth, *acc;
+};
+
+struct TableWs;
+
+// table build
+hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t n_buckets,
+                        const TableWs &tw, hipStream_t s);
+
+hipError_t launch_search_sample(const SearchCtx &c, const SampleOut &o, int kt, hipStream_t s);
+
+hipError_t launch_render(const RenderArgs &a, int precision, hipStream_t s);
+
+}  // namespace hp

@@ -1,0 +1,54 @@
+// Layout of the table workspace (device memory owned by the caller).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hp_device.hpp"
+
+namespace hp {
+
+struct TableWs {
+    ViewK *views;          // [HP_MAX_VIEWS]  per-view constants
+    int32_t *count;        // [n_buckets]     per-bucket counters
+    int32_t *offsets;      // [n_buckets + 1] bucket offsets (the table)
+    int32_t *block_sums;   // [scan blocks]
+    int2 *kz;              // [n_views * n]   (bucket, z bits) per point and view
+    uint64_t *skey;        // [n_views * n]   (z bits, index) per slot
+    float4 *pts;           // [n_views * n]   camera-space point per slot
+    int32_t *perm;         // [n_views * n]   point index per slot
+    int32_t *slot_of;      // [n_views * n]   slot per point and view
+    int32_t *big_list;     // [n_buckets]     buckets too large for one lane
+    int32_t *big_n;        // [1]
+    size_t bytes;
+};
+
+inline TableWs table_ws_layout(void *base, int64_t n, int n_views, int64_t n_buckets)
+{
+    TableWs w;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        void *p = base ? (void *)((char *)base + off) : nullptr;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    const int64_t nv = n * n_views;
+    const int64_t nvs = nv > 0 ? nv : 1;
+    const int64_t scan_blocks = (n_buckets + 4095) / 4096 + 1;
+    w.views = (ViewK *)take(sizeof(ViewK) * HP_MAX_VIEWS);
+    w.count = (int32_t *)take(sizeof(int32_t) * n_buckets);
+    w.offsets = (int32_t *)take(sizeof(int32_t) * (n_buckets + 1));
+    w.block_sums = (int32_t *)take(sizeof(int32_t) * scan_blocks);
+    w.kz = (int2 *)take(sizeof(int2) * nvs);
+    w.skey = (uint64_t *)take(sizeof(uint64_t) * nvs);
+    w.pts = (float4 *)take(sizeof(float4) * nvs);
+    w.perm = (int32_t *)take(sizeof(int32_t) * nvs);
+    w.slot_of = (int32_t *)take(sizeof(int32_t) * nvs);
+    w.big_list = (int32_t *)take(sizeof(int32_t) * n_buckets);
+    w.big_n = (int32_t *)take(sizeof(int32_t) * 64);
+    w.bytes = off;
+    return w;
+}
+
+}  // namespace hp
