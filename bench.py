@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark of the HashPoint hot path on one MI355X.
+
+A step is one pass of the whole path over one view: pixel-table build,
+search + primary-surface sampling, and decode + composite.  Workload: the
+object-scale scene (1M points on 12 random spheres, boxes and tori in
+[-1, 1]^3, 32-dim features), one 800x800 view at 40 deg from distance 4,
+r = 0.01, K = 8, 16 samples per ray, decoder 32-64-64-4.  `value` is for the
+BF16 decoder; the FP32 decoder is timed the same way (`value_fp32`).  RGB
+errors are max abs against the oracle's binary64 render on a ray sample.
+
+Prints one JSON line.  Inputs are resident in device memory before timing.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s (search+sample+render) at 800x800, 1M pts; BF16 vs FP32 at stated RGB error"
+HBM_PEAK_GBS = 8000.0
+
+
+def search_algorithmic_bytes(n_buckets, n_in, n_rays, s_tot, K):
+    """Bytes the search + sampling stage must move at minimum: the table
+    (offsets 8 B per bucket, one 16 B entry per inserted point), 16 B of
+    per-ray outputs, and per selected sample its t and K (index, distance)."""
+    return 8 * n_buckets + 16 * n_in + 16 * n_rays + (4 + 8 * K) * s_tot
+
+
+def render_algorithmic_bytes(s_tot, K, n_used, n_rays, C=32):
+    return (4 + 8 * K) * s_tot + 4 * C * n_used + 20 * n_rays
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target wall time of the oracle CPU baseline (0 = skip)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--layout", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(views would shard across GPUs with no exchange in the forward pass)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2404_14044_amd import hashpoint as hp
+    from paper_2404_14044_amd import scenes
+
+    dev = torch.device("cuda:0")
+    sc = scenes.objects_1m()
+    cam = sc.cams[0]
+    p = sc.params.replace(layout=args.layout)
+    xyz = torch.from_numpy(sc.xyz).to(dev)
+    feat = torch.from_numpy(sc.feat).to(dev)
+    mlp = hp.to_device_mlp(sc.mlp, dev)
+    R = cam.W * cam.H
+    ws = torch.empty(hp.table_workspace(xyz.shape[0], [cam], p), dtype=torch.uint8, device=dev)
+    smp = hp.alloc_samples(R, p, dev)
+    outs = {prec: {"rgb": torch.empty(R * 3, device=dev), "depth": torch.empty(R, device=dev),
+                   "acc": torch.empty(R, device=dev)} for prec in (hp.HP_FP32, hp.HP_BF16)}
+    stream = torch.cuda.current_stream()
+
+    def step(prec, ev=None):
+        if ev: ev[0].record(stream)
+        tab = hp.build_table(xyz, [cam], p, ws=ws)
+        if ev: ev[1].record(stream)
+        hp.search_sample(tab, p, out=smp)
+        if ev: ev[2].record(stream)
+        hp.render(smp, R, feat, mlp, p, prec, out=outs[prec])
+        if ev: ev[3].record(stream)
+        return tab
+
+    def timed(prec):
+        for _ in range(args.warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            tab = step(prec, evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
+                       for e in evs])
+        return wall, st, tab
+
+    wall16, st16, tab = timed(hp.HP_BF16)
+    wall32, st32, _ = timed(hp.HP_FP32)
+
+    offs = tab.offsets()
+    n_in = int(offs[-1].item())
+    n_sel = smp["n_sel"].cpu().numpy()
+    s_tot = int(n_sel.sum())
+    ki = smp["knn_idx"].view(R, p.n_samples, p.K)
+    mask = torch.arange(p.n_samples, device=dev)[None, :] < smp["n_sel"][:, None]
+    used = torch.unique(ki[mask].reshape(-1))
+    n_used = int((used >= 0).sum().item())
+
+    ms16 = wall16 * 1e3 / args.steps
+    ms32 = wall32 * 1e3 / args.steps
+    search_ms = float(np.mean(st16[:, 1]))
+    a_bytes = search_algorithmic_bytes(tab.n_buckets, n_in, R, s_tot, p.K)
+    achieved = a_bytes / (search_ms * 1e-3) / 1e9
+
+    result = {
+        "metric": METRIC,
+        "value": R / (ms16 * 1e-3) / 1e6,
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms16,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "objects_1m: 1M surface points (12 random spheres/boxes/tori, "
+                               "seed 2), one 800x800 view, hfov 40, r=0.01, K=8, S=16, "
+                               "t in [2, 6], decoder 32-64-64-4 BF16 on MFMA",
+                   "rays": R, "points": int(xyz.shape[0]), "layout": args.layout},
+        "value_fp32": R / (ms32 * 1e-3) / 1e6,
+        "ms_per_step_fp32": ms32,
+        "stage_ms_bf16": {"build": float(np.mean(st16[:, 0])), "search_sample": search_ms,
+                          "render": float(np.mean(st16[:, 2]))},
+        "stage_ms_fp32": {"build": float(np.mean(st32[:, 0])),
+                          "search_sample": float(np.mean(st32[:, 1])),
+                          "render": float(np.mean(st32[:, 2]))},
+        "workload_stats": {"n_in": n_in, "n_buckets": int(tab.n_buckets), "samples": s_tot,
+                           "hit_rays": int((n_sel > 0).sum()), "points_used": n_used},
+        "roofline": {"kernel": "k_search_sample", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes": a_bytes},
+    }
+
+    if args.calibrate_copy:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    if args.cpu_seconds > 0:
+        result.update(cpu_leg(sc, p, smp, outs, R, args.cpu_seconds))
+
+    print(json.dumps(result), flush=True)
+
+
+def cpu_leg(sc, p, smp, outs, R, seconds):
+    """Oracle (brute-force search, candidate walk, binary64 render) on a
+    bounded random sample of the same rays; also the GPU RGB error there."""
+    import oracle
+    from paper_2404_14044_amd import hashpoint as hp
+    cam = sc.cams[0]
+    pc = oracle.to_camera(sc.xyz, cam)
+    rng = np.random.default_rng(99)
+    pix = np.sort(rng.choice(R, 256, replace=False)).astype(np.int32)
+    t0 = time.perf_counter()
+    oracle.exact(pc, cam, p, pix)
+    dt = time.perf_counter() - t0
+    n = int(min(R, max(256, 256 * seconds / max(dt, 1e-3))))
+    pix = np.sort(rng.choice(R, n, replace=False)).astype(np.int32)
+    t0 = time.perf_counter()
+    ex = oracle.exact(pc, cam, p, pix)
+    ref = oracle.render64(pc, sc.feat, sc.mlp, cam, p, ex)
+    dt = time.perf_counter() - t0
+    errs = {}
+    for prec, name in ((hp.HP_BF16, "bf16"), (hp.HP_FP32, "fp32")):
+        rgb = outs[prec]["rgb"].cpu().numpy().reshape(-1, 3)[pix].astype(np.float64)
+        errs[f"rgb_err_{name}"] = float(np.abs(rgb - ref["rgb"]).max())
+    ns = smp["n_sel"].cpu().numpy()[pix]
+    errs["oracle_sample_match"] = bool(np.array_equal(ns, ex["n_sel"]))
+    return {"cpu_baseline": {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(),
+                             "kind": "oracle",
+                             "sample": f"{n} random rays of the 800x800 view (brute-force search "
+                                       f"over all 1M points, candidate walk, binary64 render), "
+                                       f"{dt:.1f} s"},
+            **errs}
+
+
+if __name__ == "__main__":
+    main()
