@@ -112,7 +112,8 @@ typedef struct hp_view_info {
  *      bits), ordered by bucket, then z, then point index.
  *  perm[slot]: the point index of each slot.
  *  slot_of[view * n_points + i]: slot of point i in that view (only defined
- *      for inserted points). */
+ *      for inserted points).
+ *  bucket_z, cell_zmin: depth summaries used to bound each ray's window. */
 typedef struct hp_table {
     int32_t n_views;
     int32_t layout;
@@ -123,6 +124,9 @@ typedef struct hp_table {
     float *pts;
     int32_t *perm;
     int32_t *slot_of;
+    float *bucket_z;      /* [n_buckets] depth of each bucket's first point, +inf if empty */
+    uint32_t *cell_zmin;  /* [n_cells] min depth (binary32 bits) of 8x8-bucket cells      */
+    int64_t n_cells;
     void *scratch;
     hp_view_info views[HP_MAX_VIEWS];
 } hp_table;

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include "hp_backward.hpp"
 #include "hp_device.hpp"
 #include "hp_kernels.hpp"
 #include "hp_search.hpp"
@@ -71,7 +72,7 @@ bool view_bound(const hp_camera &c, const hp_params &p, double &delta)
 
 struct Geometry {
     hp::ViewSet vs;
-    int64_t n_buckets = 0, n_rays = 0;
+    int64_t n_buckets = 0, n_rays = 0, n_cells = 0;
 };
 
 hp_status plan_views(const hp_camera *cams, int32_t n_views, const hp_params &p, Geometry &geo,
@@ -80,7 +81,7 @@ hp_status plan_views(const hp_camera *cams, int32_t n_views, const hp_params &p,
     memset(&geo.vs, 0, sizeof(geo.vs));
     geo.vs.n = n_views;
     geo.vs.layout = p.layout;
-    int64_t nb = 0, nr = 0;
+    int64_t nb = 0, nr = 0, nc = 0;
     for (int i = 0; i < n_views; ++i) {
         const hp_camera &c = cams[i];
         if (!valid_camera(c)) return HP_E_INVALID;
@@ -109,6 +110,9 @@ hp_status plan_views(const hp_camera *cams, int32_t n_views, const hp_params &p,
         V.ray_base = (int32_t)nr;
         V.dmax = (float)(delta * (1.0 + 1e-5) + 1e-3);
         V.slot_base = 0;
+        V.cell_base = (int32_t)nc;
+        V.ncx = (int32_t)((Wg + hp::CELL - 1) / hp::CELL);
+        nc += (int64_t)V.ncx * ((Hg + hp::CELL - 1) / hp::CELL);
         if (info) {
             info[i].W = c.W;
             info[i].H = c.H;
@@ -125,6 +129,7 @@ hp_status plan_views(const hp_camera *cams, int32_t n_views, const hp_params &p,
     }
     geo.n_buckets = nb;
     geo.n_rays = nr;
+    geo.n_cells = nc;
     return HP_OK;
 }
 
@@ -169,7 +174,7 @@ size_t hp_table_workspace(int64_t n, const hp_camera *cams, int32_t n_views, con
     else st = plan_views(cams, n_views, *p, geo, nullptr);
     if (status) *status = st;
     if (st != HP_OK) return 0;
-    return hp::table_ws_layout(nullptr, n, n_views, geo.n_buckets).bytes;
+    return hp::table_ws_layout(nullptr, n, n_views, geo.n_buckets, geo.n_cells).bytes;
 }
 
 hp_status hp_build_table(const float *xyz, int64_t n, const hp_camera *cams, int32_t n_views,
@@ -183,11 +188,11 @@ hp_status hp_build_table(const float *xyz, int64_t n, const hp_camera *cams, int
     hp_view_info info[HP_MAX_VIEWS];
     const hp_status st = plan_views(cams, n_views, *p, geo, info);
     if (st != HP_OK) return st;
-    const hp::TableWs tw = hp::table_ws_layout(ws, n, n_views, geo.n_buckets);
+    const hp::TableWs tw = hp::table_ws_layout(ws, n, n_views, geo.n_buckets, geo.n_cells);
     if (!ws || ws_bytes < tw.bytes) return HP_E_WORKSPACE;
 
     const hipError_t e =
-        hp::launch_build(xyz, n, geo.vs, geo.n_buckets, tw, (hipStream_t)stream);
+        hp::launch_build(xyz, n, geo.vs, geo.n_buckets, geo.n_cells, tw, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e);
 
     memset(out, 0, sizeof(*out));
@@ -200,6 +205,9 @@ hp_status hp_build_table(const float *xyz, int64_t n, const hp_camera *cams, int
     out->pts = reinterpret_cast<float *>(tw.pts);
     out->perm = tw.perm;
     out->slot_of = tw.slot_of;
+    out->bucket_z = tw.bucket_z;
+    out->cell_zmin = tw.cell_zmin;
+    out->n_cells = geo.n_cells;
     out->scratch = tw.views;
     memcpy(out->views, info, sizeof(hp_view_info) * n_views);
     return HP_OK;
@@ -211,7 +219,9 @@ static hp_status make_ctx(const hp_table *tab, const hp_camera *cams, int32_t n_
     if (!tab || !cams || !p || n_views != tab->n_views || !valid_params(*p)) return HP_E_INVALID;
     if (p->layout != tab->layout) return HP_E_INVALID;
     if (p->K > HP_MAX_K) return HP_E_UNSUPPORTED;
-    if (!tab->offsets || !tab->pts || !tab->slot_of || !tab->scratch) return HP_E_INVALID;
+    if (!tab->offsets || !tab->pts || !tab->slot_of || !tab->scratch || !tab->bucket_z ||
+        !tab->cell_zmin)
+        return HP_E_INVALID;
     Geometry geo;
     const hp_status st = plan_views(cams, n_views, *p, geo, nullptr);
     if (st != HP_OK) return st;
@@ -223,6 +233,8 @@ static hp_status make_ctx(const hp_table *tab, const hp_camera *cams, int32_t n_
     c.offsets = tab->offsets;
     c.pts = reinterpret_cast<const float4 *>(tab->pts);
     c.slot_of = tab->slot_of;
+    c.bucket_z = tab->bucket_z;
+    c.cell_zmin = tab->cell_zmin;
     c.views = reinterpret_cast<const hp::ViewK *>(tab->scratch);
     c.n_views = n_views;
     c.layout = tab->layout;
@@ -296,8 +308,9 @@ hp_status hp_render(const hp_samples *smp, int64_t R, const float *feat, int32_t
 
 size_t hp_backward_workspace(const hp_table *tab, const hp_params *p, hp_status *status)
 {
-    if (status) *status = (tab && p) ? HP_E_UNSUPPORTED : HP_E_INVALID;
-    return 0;
+    const hp_status st = (tab && p && valid_params(*p)) ? HP_OK : HP_E_INVALID;
+    if (status) *status = st;
+    return st == HP_OK ? hp::backward_workspace_bytes() : 0;
 }
 
 hp_status hp_render_backward(const hp_table *tab, const hp_camera *cams, int32_t n_views,
@@ -305,10 +318,32 @@ hp_status hp_render_backward(const hp_table *tab, const hp_camera *cams, int32_t
                              const hp_params *p, const float *grad_rgb, float *grad_feat,
                              hp_mlp *grad_mlp, void *ws, size_t ws_bytes, void *stream)
 {
-    (void)tab; (void)cams; (void)n_views; (void)feat; (void)C; (void)mlp; (void)precision;
-    (void)p; (void)grad_rgb; (void)grad_feat; (void)grad_mlp; (void)ws; (void)ws_bytes;
-    (void)stream;
-    return HP_E_UNSUPPORTED;
+    hp::SearchCtx c;
+    const hp_status st = make_ctx(tab, cams, n_views, p, c);
+    if (st != HP_OK) return st;
+    if (C != HP_FEAT_DIM) return HP_E_UNSUPPORTED;
+    if (precision != HP_FP32 && precision != HP_BF16) return HP_E_INVALID;
+    if (!feat || !mlp || !grad_rgb || !grad_feat || !grad_mlp) return HP_E_INVALID;
+    if (!mlp->W1 || !mlp->b1 || !mlp->W2 || !mlp->b2 || !mlp->W3 || !mlp->b3) return HP_E_INVALID;
+    if (!grad_mlp->W1 || !grad_mlp->b1 || !grad_mlp->W2 || !grad_mlp->b2 || !grad_mlp->W3 ||
+        !grad_mlp->b3)
+        return HP_E_INVALID;
+    if (!ws || ws_bytes < hp::backward_workspace_bytes()) return HP_E_WORKSPACE;
+    hp::BwdArgs A;
+    A.c = c;
+    A.feat = feat;
+    A.w = hp::MlpWeights{mlp->W1, mlp->b1, mlp->W2, mlp->b2, mlp->W3, mlp->b3};
+    A.eps_idw = p->eps_idw;
+    A.delta_last = p->delta_last;
+    for (int i = 0; i < 3; ++i) A.bg[i] = p->bg[i];
+    A.grad_rgb = grad_rgb;
+    A.grad_feat = grad_feat;
+    A.partial = (float *)ws;
+    const hp::MlpGrad gm{grad_mlp->W1, grad_mlp->b1, grad_mlp->W2,
+                         grad_mlp->b2, grad_mlp->W3, grad_mlp->b3};
+    const hipError_t e =
+        hp::launch_backward(A, knn_template(p->K), precision, gm, (hipStream_t)stream);
+    return e == hipSuccess ? HP_OK : hip_fail(e);
 }
 
 }  // extern "C"

@@ -183,7 +183,7 @@ __device__ __forceinline__ void sort_net(uint64_t (&k)[N])
 }
 
 template <int N>
-__device__ __forceinline__ void sort_bucket_regs(uint64_t *__restrict__ skey, int start, int cnt)
+__device__ __forceinline__ uint64_t sort_bucket_regs(uint64_t *__restrict__ skey, int start, int cnt)
 {
     uint64_t k[N];
 #pragma unroll
@@ -192,6 +192,7 @@ __device__ __forceinline__ void sort_bucket_regs(uint64_t *__restrict__ skey, in
 #pragma unroll
     for (int i = 0; i < N; ++i)
         if (i < cnt) skey[start + i] = k[i];
+    return k[0];
 }
 
 constexpr int SMALL_MAX = 16;
@@ -199,17 +200,23 @@ constexpr int SMALL_MAX = 16;
 __global__ void __launch_bounds__(256) k_sort_small(const int32_t *__restrict__ offsets, int64_t nb,
                                                     uint64_t *__restrict__ skey,
                                                     int32_t *__restrict__ big_list,
-                                                    int32_t *__restrict__ big_n)
+                                                    int32_t *__restrict__ big_n,
+                                                    float *__restrict__ bucket_z)
 {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
     const int start = offsets[b];
     const int cnt = offsets[b + 1] - start;
-    if (cnt <= 1) return;
-    if (cnt <= 4) sort_bucket_regs<4>(skey, start, cnt);
-    else if (cnt <= 8) sort_bucket_regs<8>(skey, start, cnt);
-    else if (cnt <= SMALL_MAX) sort_bucket_regs<16>(skey, start, cnt);
-    else big_list[atomicAdd(big_n, 1)] = (int32_t)b;
+    uint64_t first = ~0ull;
+    if (cnt == 1) first = skey[start];
+    else if (cnt > 1 && cnt <= 4) first = sort_bucket_regs<4>(skey, start, cnt);
+    else if (cnt > 4 && cnt <= 8) first = sort_bucket_regs<8>(skey, start, cnt);
+    else if (cnt > 8 && cnt <= SMALL_MAX) first = sort_bucket_regs<16>(skey, start, cnt);
+    else if (cnt > SMALL_MAX) {
+        big_list[atomicAdd(big_n, 1)] = (int32_t)b;
+        return;  // k_sort_big writes bucket_z
+    }
+    bucket_z[b] = cnt > 0 ? __uint_as_float((uint32_t)(first >> 32)) : __builtin_inff();
 }
 
 constexpr int BIG_T = 256;
@@ -253,7 +260,8 @@ __device__ void block_flip_bitonic(int cnt, Load ld, Store st)
 __global__ void __launch_bounds__(BIG_T) k_sort_big(const int32_t *__restrict__ offsets,
                                                     uint64_t *__restrict__ skey,
                                                     const int32_t *__restrict__ big_list,
-                                                    const int32_t *__restrict__ big_n)
+                                                    const int32_t *__restrict__ big_n,
+                                                    float *__restrict__ bucket_z)
 {
     __shared__ uint64_t sh[BIG_LDS];
     const int nbig = *big_n;
@@ -272,7 +280,28 @@ __global__ void __launch_bounds__(BIG_T) k_sort_big(const int32_t *__restrict__ 
                                [&](int i, uint64_t v) { g[i] = v; });
         }
         __syncthreads();
+        if (threadIdx.x == 0) bucket_z[b] = __uint_as_float((uint32_t)(g[0] >> 32));
     }
+}
+
+// Minimum depth of each CELL x CELL block of buckets, from the buckets'
+// first (nearest) points.  One wave per cell, grid (cells / 4, views).
+__global__ void __launch_bounds__(256) k_cell_zmin(const float *__restrict__ bucket_z,
+                                                   const ViewK *__restrict__ views, int layout,
+                                                   uint32_t *__restrict__ cell_zmin)
+{
+    const ViewK &V = views[blockIdx.y];
+    const int cell = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int ncy = (V.Hg + CELL - 1) / CELL;
+    if (cell >= V.ncx * ncy) return;
+    const int l = threadIdx.x & 63;
+    const int bx = (cell % V.ncx) * CELL + (l & (CELL - 1));
+    const int by = (cell / V.ncx) * CELL + (l >> CELL_SHIFT);
+    float z = __builtin_inff();
+    if (bx < V.Wg && by < V.Hg) z = bucket_z[bucket_of(V, layout, bx, by)];
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) z = __builtin_fminf(z, __shfl_xor(z, o, WAVE));
+    if (l == 0) cell_zmin[V.cell_base + cell] = __float_as_uint(z);
 }
 
 // first slot of every view (views are contiguous in the bucket space)
@@ -309,7 +338,7 @@ __global__ void __launch_bounds__(256) k_materialize(const uint64_t *__restrict_
 namespace hp {
 
 hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t n_buckets,
-                        const TableWs &tw, hipStream_t s)
+                        int64_t n_cells, const TableWs &tw, hipStream_t s)
 {
     const int V = vs.n;
     const int64_t nv = n * V;
@@ -322,8 +351,14 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
     k_scan_blocks<<<1, SCAN_T, 0, s>>>(tw.block_sums, nblk);
     k_scan_apply<<<(unsigned)nblk, SCAN_T, 0, s>>>(tw.count, n_buckets, tw.block_sums, tw.offsets);
     if (nv > 0) k_scatter<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tw.kz, nv, n, tw.offsets, tw.count, tw.skey);
-    k_sort_small<<<(unsigned)((n_buckets + 255) / 256), 256, 0, s>>>(tw.offsets, n_buckets, tw.skey, tw.big_list, tw.big_n);
-    k_sort_big<<<512, BIG_T, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n);
+    k_sort_small<<<(unsigned)((n_buckets + 255) / 256), 256, 0, s>>>(tw.offsets, n_buckets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
+    k_sort_big<<<512, BIG_T, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
+    int max_cells = 0;
+    for (int i = 0; i < V; ++i) {
+        const ViewK &vk = vs.v[i];
+        max_cells = max(max_cells, vk.ncx * ((vk.Hg + CELL - 1) / CELL));
+    }
+    k_cell_zmin<<<dim3((unsigned)((max_cells + 3) / 4), V), 256, 0, s>>>(tw.bucket_z, tw.views, vs.layout, tw.cell_zmin);
     k_view_slots<<<1, HP_MAX_VIEWS, 0, s>>>(tw.offsets, tw.views, V);
     if (nv > 0)
         k_materialize<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tw.skey, tw.offsets + n_buckets, xyz, n, tw.views, V, tw.pts, tw.perm, tw.slot_of);

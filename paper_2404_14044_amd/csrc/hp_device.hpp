@@ -26,8 +26,15 @@ struct ViewK {
     int32_t bucket_base, ray_base;
     float dmax;        // window radius in pixels, with margin
     int32_t slot_base; // first slot of the view (written on the device)
+    int32_t cell_base; // first depth cell of the view
+    int32_t ncx;       // depth cells per grid row (cells are CELL x CELL buckets)
     int32_t pad;
 };
+
+// Depth cells: blocks of CELL x CELL buckets whose minimum camera depth the
+// table keeps, so a ray can bound the depth of anything near it cheaply.
+constexpr int CELL_SHIFT = 3;
+constexpr int CELL = 1 << CELL_SHIFT;
 
 struct ViewSet {
     int32_t n;

@@ -40,7 +40,7 @@ struct TableWs;
 
 // table build
 hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t n_buckets,
-                        const TableWs &tw, hipStream_t s);
+                        int64_t n_cells, const TableWs &tw, hipStream_t s);
 
 hipError_t launch_search_sample(const SearchCtx &c, const SampleOut &o, int kt, hipStream_t s);
 

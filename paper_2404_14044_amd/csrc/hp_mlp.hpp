@@ -1,0 +1,210 @@
+// The 32 -> 64 -> 64 -> 4 decoder on matrix cores, shared by the render and
+// its backward pass.  Sixteen samples form the N dimension of each product
+// (H^T = W X^T): lane l holds sample l % 16 and, in every accumulator, rows
+// 4 (l / 16) .. +3 of a 16-row output block.  Those accumulators feed the next
+// layer's B operand directly; the contraction index is permuted consistently
+// in the weights instead of moving activations between lanes.
+#pragma once
+
+#include "hp_device.hpp"
+
+namespace hp {
+
+struct MlpWeights {
+    const float *W1, *b1, *W2, *b2, *W3, *b3;
+};
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+__device__ __forceinline__ uint32_t bf16_bits_rne(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ bf16x8 pack_bf16x8(const float *v)
+{
+    union {
+        uint32_t u[4];
+        bf16x8 b;
+    } r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r.u[i] = bf16_bits_rne(v[2 * i]) | (bf16_bits_rne(v[2 * i + 1]) << 16);
+    return r.b;
+}
+
+// Hidden-feature index that lane l's element e feeds at contraction block kb
+// of a 64-wide layer input: the previous layer's output block 2 kb + e / 4,
+// row 4 (l / 16) + e % 4.
+__device__ __forceinline__ int hid_index(int kb, int l, int e)
+{
+    return 32 * kb + 16 * (e >> 2) + 4 * (l >> 4) + (e & 3);
+}
+
+__device__ __forceinline__ float softplus_f(float x)
+{
+    return __builtin_fmaxf(x, 0.0f) + log1pf(expf(-__builtin_fabsf(x)));
+}
+
+__device__ __forceinline__ float sigmoid_f(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+
+// ---------------------------------------------------------------------------
+// decoder on one tile of 16 samples; returns o[0..3] of sample l (lanes 0..15)
+// ---------------------------------------------------------------------------
+struct MlpBf16 {
+    bf16x8 w1[4];      // [out block]
+    bf16x8 w2[4][2];   // [out block][k block]
+    bf16x8 w3[2];      // [k block]
+    float b1[4][4], b2[4][4], b3[4];
+};
+
+__device__ __forceinline__ void load_mlp_bf16(const MlpWeights &a, MlpBf16 &m)
+{
+    const int l = lane_id();
+    const int r = l & 15, q = l >> 4;
+    float tmp[8];
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) tmp[e] = a.W1[(16 * ob + r) * HP_FEAT_DIM + 8 * q + e];
+        m.w1[ob] = pack_bf16x8(tmp);
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) tmp[e] = a.W2[(16 * ob + r) * HP_HIDDEN + hid_index(kb, l, e)];
+            m.w2[ob][kb] = pack_bf16x8(tmp);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            m.b1[ob][e] = a.b1[16 * ob + 4 * q + e];
+            m.b2[ob][e] = a.b2[16 * ob + 4 * q + e];
+        }
+    }
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) tmp[e] = (r < 4) ? a.W3[r * HP_HIDDEN + hid_index(kb, l, e)] : 0.0f;
+        m.w3[kb] = pack_bf16x8(tmp);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) m.b3[e] = (4 * q + e < 4) ? a.b3[4 * q + e] : 0.0f;
+}
+
+__device__ __forceinline__ f32x4 decode_bf16(const MlpBf16 &m, const float *f, f32x4 *keep1 = nullptr,
+                                             f32x4 *keep2 = nullptr)
+{
+    const bf16x8 x = pack_bf16x8(f);
+    f32x4 h1[4];
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        f32x4 acc = {m.b1[ob][0], m.b1[ob][1], m.b1[ob][2], m.b1[ob][3]};
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.w1[ob], x, acc, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = __builtin_fmaxf(acc[e], 0.0f);
+        h1[ob] = acc;
+        if (keep1) keep1[ob] = acc;
+    }
+    bf16x8 x2[2];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+        float t8[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t8[e] = h1[2 * kb + (e >> 2)][e & 3];
+        x2[kb] = pack_bf16x8(t8);
+    }
+    f32x4 h2[4];
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        f32x4 acc = {m.b2[ob][0], m.b2[ob][1], m.b2[ob][2], m.b2[ob][3]};
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.w2[ob][0], x2[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.w2[ob][1], x2[1], acc, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = __builtin_fmaxf(acc[e], 0.0f);
+        h2[ob] = acc;
+        if (keep2) keep2[ob] = acc;
+    }
+    bf16x8 x3[2];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+        float t8[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t8[e] = h2[2 * kb + (e >> 2)][e & 3];
+        x3[kb] = pack_bf16x8(t8);
+    }
+    f32x4 o = {m.b3[0], m.b3[1], m.b3[2], m.b3[3]};
+    o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.w3[0], x3[0], o, 0, 0, 0);
+    o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.w3[1], x3[1], o, 0, 0, 0);
+    return o;
+}
+
+// FP32: v_mfma_f32_16x16x4f32, lane l supplies contraction row l / 16 of
+// each 4-deep step.  Layer 1 step ks takes feature 8 (l / 16) + ks; layer 2
+// and 3 step (ob, e) take hidden feature 16 ob + 4 (l / 16) + e.
+struct MlpF32 {
+    float w1[4][8];    // [out block][step]
+    float w2[4][16];   // [out block][step]
+    float w3[16];
+    float b1[4][4], b2[4][4], b3[4];
+};
+
+__device__ __forceinline__ void load_mlp_f32(const MlpWeights &a, MlpF32 &m)
+{
+    const int l = lane_id();
+    const int r = l & 15, q = l >> 4;
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) m.w1[ob][ks] = a.W1[(16 * ob + r) * HP_FEAT_DIM + 8 * q + ks];
+#pragma unroll
+        for (int st = 0; st < 16; ++st)
+            m.w2[ob][st] = a.W2[(16 * ob + r) * HP_HIDDEN + 16 * (st >> 2) + 4 * q + (st & 3)];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            m.b1[ob][e] = a.b1[16 * ob + 4 * q + e];
+            m.b2[ob][e] = a.b2[16 * ob + 4 * q + e];
+        }
+    }
+#pragma unroll
+    for (int st = 0; st < 16; ++st)
+        m.w3[st] = (r < 4) ? a.W3[r * HP_HIDDEN + 16 * (st >> 2) + 4 * q + (st & 3)] : 0.0f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) m.b3[e] = (4 * q + e < 4) ? a.b3[4 * q + e] : 0.0f;
+}
+
+__device__ __forceinline__ f32x4 decode_f32(const MlpF32 &m, const float *f, f32x4 *keep1 = nullptr,
+                                            f32x4 *keep2 = nullptr)
+{
+    f32x4 h1[4];
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        f32x4 acc = {m.b1[ob][0], m.b1[ob][1], m.b1[ob][2], m.b1[ob][3]};
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(m.w1[ob][ks], f[ks], acc, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = __builtin_fmaxf(acc[e], 0.0f);
+        h1[ob] = acc;
+        if (keep1) keep1[ob] = acc;
+    }
+    f32x4 h2[4];
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        f32x4 acc = {m.b2[ob][0], m.b2[ob][1], m.b2[ob][2], m.b2[ob][3]};
+#pragma unroll
+        for (int st = 0; st < 16; ++st)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(m.w2[ob][st], h1[st >> 2][st & 3], acc, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = __builtin_fmaxf(acc[e], 0.0f);
+        h2[ob] = acc;
+        if (keep2) keep2[ob] = acc;
+    }
+    f32x4 o = {m.b3[0], m.b3[1], m.b3[2], m.b3[3]};
+#pragma unroll
+    for (int st = 0; st < 16; ++st)
+        o = __builtin_amdgcn_mfma_f32_16x16x4f32(m.w3[st], h2[st >> 2][st & 3], o, 0, 0, 0);
+    return o;
+}
+
+
+}  // namespace hp

@@ -6,14 +6,19 @@
 // parameter t in [t_near, t_far].  Such a point projects at most
 //     delta(t) = f rho(t) L^2 / (t - rho(t) |w|)
 // pixels from the ray's pixel centre (w: normalised image coordinate of the
-// ray, L^2 = 1 + |w|^2, f = max(fx, fy)), and delta does not grow with t.  So
-// the wave visits the buckets of a disc of radius delta(t_near) around the
-// pixel, and inside a bucket at distance D from the pixel centre it only needs
-// points with t <= f r L^2 / D + r |w|, i.e. with camera depth
-//     z <= (f r L^2 / D + 2 r |w|) / L        (fixed-radius branch of rho),
-// and since buckets are ordered by z a bucket whose first point is deeper is
-// skipped whole.  These cuts are widened by relative margins far above binary32
-// rounding; the exact predicate decides.
+// ray, L^2 = 1 + |w|^2, f = max(fx, fy)), and delta does not grow with t.
+// Its depth z also bounds t from below, t >= (L z - |w| r) / (1 + |w| r
+// inv_tref).  So the wave
+//   1. reads the minimum depth of the 8x8-bucket cells around the pixel; if
+//      they are all empty the ray has no neighbour, else the smallest depth
+//      bounds t and thus the window radius delta(t) (two rounds, each over the
+//      cells of the previous radius);
+//   2. visits the buckets of that disc, and inside a bucket at distance D from
+//      the pixel centre only needs points with t <= f r L^2 / D + r |w|, i.e.
+//      z <= (f r L^2 / D + 2 r |w|) / L (fixed-radius branch of rho); buckets
+//      are ordered by z, so a bucket whose first point is deeper is skipped.
+// Every bound is widened by relative margins far above binary32 rounding; the
+// exact predicate decides.
 //
 // Lanes first sweep the window buckets (one bucket per lane), compact the
 // non-empty survivors into an LDS list, then sweep the points of the listed
@@ -23,13 +28,15 @@
 // 64 pending keys are sorted across the wave and merged into a running
 // ascending top-64, whose largest key then filters later appends.
 //
-// Sampling.  Lane j takes candidate j (the j-th neighbour in (t, index)
-// order).  Its K nearest neighbours among N(ray) within R_j = rho(t_j) can only
-// lie in a window |t_i - t_j| <= R_j of the sorted list, found by binary
-// search; the lane keeps a sorted register list of (dist^2 bits << 32 | index).
-// Then the wave walks the candidates in order accumulating the transmittance
-// of Eq. 5 and stops once no later candidate can pass eps_w (alpha <= gamma,
-// so w_j <= gamma T).
+// Sampling.  Candidates are the neighbours in (t, index) order.  The K
+// nearest neighbours of candidate j within R_j = rho(t_j) lie in the window
+// |t_i - t_j| <= R_j of the sorted list (distance >= |t_i - t_j| up to
+// rounding), found by binary search.  Sixteen candidates are served at once,
+// four lanes each: the lanes split the window, keep sorted register lists of
+// (dist^2 bits << 32 | index) and merge them across the quad.  The wave then
+// walks those candidates in order accumulating the transmittance of Eq. 5 and
+// stops once no later candidate can pass eps_w (alpha <= gamma, so
+// w_j <= gamma T), which usually happens within the first sixteen.
 #pragma once
 
 #include "hp_device.hpp"
@@ -40,6 +47,8 @@ struct SearchCtx {
     const int32_t *offsets;
     const float4 *pts;
     const int32_t *slot_of;
+    const float *bucket_z;
+    const uint32_t *cell_zmin;
     const ViewK *views;
     int32_t n_views, layout;
     int64_t n_points, n_rays;
@@ -67,6 +76,95 @@ struct RayGeom {
 
 __device__ __forceinline__ void lds_sync() { __syncthreads(); }
 
+// ---------------------------------------------------------------------------
+// cross-lane exchange: lane l receives lane l ^ j's value.  DPP for j < 16
+// (row rotations act inside rows of 16 lanes), swizzle for 16, permute for 32.
+// ---------------------------------------------------------------------------
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v)
+{
+    const int x = (int)v;
+    if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);
+    if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);
+    if constexpr (J == 4) {
+        const int down = __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false);  // from l - 4
+        const int up = __builtin_amdgcn_update_dpp(0, x, 0x12C, 0xF, 0xF, false);    // from l + 4
+        return (uint32_t)((lane_id() & 4) ? down : up);
+    }
+    if constexpr (J == 8) return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);
+    if constexpr (J == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x401F);
+    return (uint32_t)__shfl_xor(x, J, WAVE);
+}
+
+template <int J>
+__device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v)
+{
+    const uint32_t lo = xor_lane_u32<J>((uint32_t)v);
+    const uint32_t hi = xor_lane_u32<J>((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int K, int J>
+__device__ __forceinline__ uint64_t sort_stage(uint64_t x, int l)
+{
+    const uint64_t y = xor_lane_u64<J>(x);
+    const bool up = (l & K) == 0;
+    const bool lower = (l & J) == 0;
+    return (lower == up) ? umin64(x, y) : umax64(x, y);
+}
+
+template <int K, int J>
+__device__ __forceinline__ uint64_t sort_merge_steps(uint64_t x, int l)
+{
+    x = sort_stage<K, J>(x, l);
+    if constexpr (J > 1) x = sort_merge_steps<K, J / 2>(x, l);
+    return x;
+}
+
+template <int K>
+__device__ __forceinline__ uint64_t sort_steps(uint64_t x, int l)
+{
+    x = sort_merge_steps<K, K / 2>(x, l);
+    if constexpr (K < WAVE) x = sort_steps<K * 2>(x, l);
+    return x;
+}
+
+// Ascending bitonic sort of one key per lane across the wave.
+__device__ __forceinline__ uint64_t wave_sort_fast(uint64_t x) { return sort_steps<2>(x, lane_id()); }
+
+// Keep the 64 smallest of two ascending wave-sorted lists, ascending.
+__device__ __forceinline__ uint64_t wave_merge_low_fast(uint64_t a, uint64_t b)
+{
+    const int l = lane_id();
+    uint64_t x = umin64(a, shfl_u64(b, WAVE - 1 - l));
+    // half-cleaners: every stage keeps the minimum in the lower lane
+    return sort_merge_steps<2 * WAVE, WAVE / 2>(x, l);
+}
+
+__device__ __forceinline__ float wave_min_f32(float v)
+{
+    v = __builtin_fminf(v, __uint_as_float(xor_lane_u32<1>(__float_as_uint(v))));
+    v = __builtin_fminf(v, __uint_as_float(xor_lane_u32<2>(__float_as_uint(v))));
+    v = __builtin_fminf(v, __uint_as_float(xor_lane_u32<4>(__float_as_uint(v))));
+    v = __builtin_fminf(v, __uint_as_float(xor_lane_u32<8>(__float_as_uint(v))));
+    v = __builtin_fminf(v, __uint_as_float(xor_lane_u32<16>(__float_as_uint(v))));
+    v = __builtin_fminf(v, __uint_as_float(xor_lane_u32<32>(__float_as_uint(v))));
+    return v;
+}
+
+// Inclusive prefix maximum across the wave (row shifts, then row broadcasts).
+__device__ __forceinline__ int wave_prefix_max_i32(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x113, 0xF, 0xF, false));  // row_shr:3
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xF, 0xE, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xF, 0xC, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return v;
+}
+
 __device__ __forceinline__ RayGeom ray_geometry(const SearchCtx &c, int64_t ray)
 {
     RayGeom r;
@@ -82,16 +180,71 @@ __device__ __forceinline__ RayGeom ray_geometry(const SearchCtx &c, int64_t ray)
     return r;
 }
 
-// Find the index of the last prefix entry <= q among pre[0..n).
-__device__ __forceinline__ int find_bucket(const int32_t *pre, int n, int q)
+// Minimum depth of the 8x8-bucket cells holding buckets within h of grid
+// position (gx, gy).  Lane-resident: lane q keeps cell q of the widest window
+// so narrower windows re-reduce without reloading (up to 64 cells; larger
+// windows loop).
+struct CellWindow {
+    int cx0, cy0, ncw, ncell;
+    float z;  // this lane's cell minimum (+inf if none)
+    int cxx, cyy;
+};
+
+__device__ __forceinline__ CellWindow load_cells(const SearchCtx &c, const ViewK &V, int gx, int gy,
+                                                 int h)
 {
-    int lo = 0, hi = n;  // answer in [lo, hi)
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (pre[mid] <= q) lo = mid;
-        else hi = mid;
+    const int l = lane_id();
+    CellWindow w;
+    w.cx0 = max(gx - h, 0) >> CELL_SHIFT;
+    w.cy0 = max(gy - h, 0) >> CELL_SHIFT;
+    const int cx1 = min(gx + h, V.Wg - 1) >> CELL_SHIFT, cy1 = min(gy + h, V.Hg - 1) >> CELL_SHIFT;
+    w.ncw = cx1 - w.cx0 + 1;
+    w.ncell = w.ncw * (cy1 - w.cy0 + 1);
+    w.z = __builtin_inff();
+    w.cxx = w.cyy = -1;
+    for (int q0 = 0; q0 < w.ncell; q0 += WAVE) {
+        const int q = q0 + l;
+        if (q < w.ncell) {
+            const int qy = q / w.ncw;
+            const int cxx = w.cx0 + (q - qy * w.ncw), cyy = w.cy0 + qy;
+            w.z = __builtin_fminf(w.z, __uint_as_float(c.cell_zmin[V.cell_base + cyy * V.ncx + cxx]));
+            if (q0 == 0) {
+                w.cxx = cxx;
+                w.cyy = cyy;
+            }
+        }
     }
-    return lo;
+    return w;
+}
+
+// Minimum over the cells of the narrower window h (exact when the widest
+// window had at most 64 cells; otherwise the wide minimum, still a bound).
+__device__ __forceinline__ float cells_zmin(const CellWindow &w, const ViewK &V, int gx, int gy, int h)
+{
+    float z = w.z;
+    if (w.ncell <= WAVE) {
+        const bool in = w.cxx >= (max(gx - h, 0) >> CELL_SHIFT) &&
+                        w.cxx <= (min(gx + h, V.Wg - 1) >> CELL_SHIFT) &&
+                        w.cyy >= (max(gy - h, 0) >> CELL_SHIFT) &&
+                        w.cyy <= (min(gy + h, V.Hg - 1) >> CELL_SHIFT);
+        z = in ? z : __builtin_inff();
+    }
+    return wave_min_f32(z);
+}
+
+// Window radius (pixels) for neighbours whose depth is at least zmin.
+__device__ __forceinline__ float radius_for_depth(const SearchCtx &c, const RayGeom &g, float f,
+                                                  float L2, float zmin, float dcap)
+{
+    const float k = c.radius * c.inv_tref;
+    float t = (g.L * zmin - g.wn * c.radius) / (1.0f + g.wn * k);
+    t = t * 0.9999f - 1e-6f;
+    if (!(t > c.t_near)) t = c.t_near;
+    const float rho = search_radius(c.radius, c.inv_tref, t);
+    const float den = t - rho * g.wn;
+    if (!(den > 0.0f)) return dcap;
+    const float d = (f * rho * L2 / den) * 1.0001f + 0.01f;
+    return d < dcap ? d : dcap;
 }
 
 // Search one ray.  Returns, in `top` (one key per lane, ascending), the
@@ -117,16 +270,28 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
     }
     const float frL2 = f * c.radius * L2;
     const float two_rw = 2.0f * c.radius * g.wn;
-    const float Dmax = V.dmax;
-    int h = (int)__builtin_floorf(Dmax + 0.5f);
-    if (h > V.g) h = V.g;
-    const int Wd = 2 * h + 1;
-    const int total = Wd * Wd;
     const int gx = g.u + V.g, gy = g.v + V.g;
 
     top = ~0ull;
-    uint64_t tau = ~0ull;
     count = 0;
+
+    // window radius from the depth cells
+    float Dmax = V.dmax;
+    int h = min((int)__builtin_floorf(Dmax + 0.5f), V.g);
+    {
+        const CellWindow cw = load_cells(c, V, gx, gy, h);
+#pragma unroll
+        for (int round = 0; round < 2; ++round) {
+            const float zmin = cells_zmin(cw, V, gx, gy, h);
+            if (!(zmin < __builtin_inff())) return;  // no point anywhere near this ray
+            Dmax = radius_for_depth(c, g, f, L2, zmin, Dmax);
+            h = min((int)__builtin_floorf(Dmax + 0.5f), V.g);
+        }
+    }
+    const int Wd = 2 * h + 1;
+    const int total = Wd * Wd;
+
+    uint64_t tau = ~0ull;
     int npend = 0;
     int nbl = 0;
 
@@ -139,32 +304,43 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
         lds_sync();
         if (l < rem) sh.pend[l] = y;
         npend = rem;
-        x = wave_sort_u64(x);
-        top = wave_merge_low_u64(top, x);
+        x = wave_sort_fast(x);
+        top = wave_merge_low_fast(top, x);
         tau = shfl_u64(top, WAVE - 1);
         lds_sync();
     };
 
     auto sweep_points = [&](int nb) {
-        // prefix sums of the listed bucket sizes
+        // points of the listed buckets, flattened; each lane finds its bucket
+        // by a prefix maximum over the bucket heads that fall in its chunk
         lds_sync();
         const int c0 = (l < nb) ? sh.bl_cnt[l] : 0;
         const int i0 = wave_incl_scan_i32(c0);
         const int c1 = (WAVE + l < nb) ? sh.bl_cnt[WAVE + l] : 0;
         const int i1 = wave_incl_scan_i32(c1) + readlane_i32(i0, WAVE - 1);
-        sh.bl_pre[l] = i0 - c0;
-        sh.bl_pre[WAVE + l] = i1 - c1;
+        const int pre0 = i0 - c0, pre1 = i1 - c1;  // first flat index of buckets l, 64 + l
         const int totp = readlane_i32(i1, WAVE - 1);
-        lds_sync();
+        int carry = 0;
         for (int p0 = 0; p0 < totp; p0 += WAVE) {
+            sh.bl_pre[l] = -1;
+            lds_sync();
+            if (l < nb && pre0 >= p0 && pre0 < p0 + WAVE) sh.bl_pre[pre0 - p0] = l;
+            if (WAVE + l < nb && pre1 >= p0 && pre1 < p0 + WAVE) sh.bl_pre[pre1 - p0] = WAVE + l;
+            lds_sync();
+            int own = sh.bl_pre[l];
+            if (l == 0 && own < 0) own = carry;
+            own = wave_prefix_max_i32(own);
+            carry = readlane_i32(own, WAVE - 1);
             const int p = p0 + l;
+            const int pa = __shfl(pre0, own & (WAVE - 1), WAVE);
+            const int pb = __shfl(pre1, own & (WAVE - 1), WAVE);
             bool pass = false;
             uint64_t key = 0;
             if (p < totp) {
-                const int bsel = find_bucket(sh.bl_pre, nb, p);
-                const int slot = sh.bl_start[bsel] + (p - sh.bl_pre[bsel]);
+                const int bpre = (own < WAVE) ? pa : pb;
+                const int slot = sh.bl_start[own] + (p - bpre);
                 const float4 P = c.pts[slot];
-                if (P.z <= sh.bl_zmax[bsel] && P.z >= z_lo) {
+                if (P.z <= sh.bl_zmax[own] && P.z >= z_lo) {
                     const float t = ray_param(P.x, P.y, P.z, g.dx, g.dy, g.dz);
                     const float e2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, t);
                     const float rho = search_radius(c.radius, c.inv_tref, t);
@@ -178,36 +354,33 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
             if (keep) sh.pend[npend + rank_below(km)] = key;
             npend += popc64(km);
             if (npend >= WAVE) flush(WAVE);
+            lds_sync();
         }
     };
 
-    for (int q0 = 0; q0 < total; q0 += WAVE) {
-        const int q = q0 + l;
-        bool ok = q < total;
-        int st = 0, cnt = 0;
-        float zmax = z_hi;
-        if (ok) {
-            const int qy = q / Wd;
-            const int dyi = qy - h, dxi = q - qy * Wd - h;
-            const int bx = gx + dxi, by = gy + dyi;
-            ok = bx >= 0 && bx < V.Wg && by >= 0 && by < V.Hg;
-            const float ex = __builtin_fmaxf(0.0f, __builtin_fabsf((float)dxi) - 0.5f);
-            const float ey = __builtin_fmaxf(0.0f, __builtin_fabsf((float)dyi) - 0.5f);
-            const float D = __builtin_sqrtf(ex * ex + ey * ey);
-            ok = ok && D <= Dmax;
-            const float Dp = D - 0.01f;
-            if (Dp > 0.0f && Dp > dinf) {
-                const float zc = ((frL2 / Dp + two_rw) / g.L) * 1.001f + 1e-5f;
-                zmax = zc < z_hi ? zc : z_hi;
-            }
-            if (ok) {
-                const int key = bucket_of(V, c.layout, bx, by);
-                st = c.offsets[key];
-                cnt = c.offsets[key + 1] - st;
-                ok = cnt > 0;
-                if (ok) ok = c.pts[st].z <= zmax;
-            }
+    // one window bucket: returns whether it may hold a neighbour, and its slots
+    auto probe = [&](int q, int &st, int &cnt, float &zmax) -> bool {
+        zmax = z_hi;
+        st = cnt = 0;
+        if (q >= total) return false;
+        const int qy = q / Wd;
+        const int dyi = qy - h, dxi = q - qy * Wd - h;
+        const int bx = gx + dxi, by = gy + dyi;
+        const float ex = __builtin_fmaxf(0.0f, __builtin_fabsf((float)dxi) - 0.5f);
+        const float ey = __builtin_fmaxf(0.0f, __builtin_fabsf((float)dyi) - 0.5f);
+        const float D = __builtin_sqrtf(ex * ex + ey * ey);
+        if (!(bx >= 0 && bx < V.Wg && by >= 0 && by < V.Hg && D <= Dmax)) return false;
+        const float Dp = D - 0.01f;
+        if (Dp > 0.0f && Dp > dinf) {
+            const float zc = ((frL2 / Dp + two_rw) / g.L) * 1.001f + 1e-5f;
+            zmax = zc < z_hi ? zc : z_hi;
         }
+        const int key = bucket_of(V, c.layout, bx, by);
+        st = c.offsets[key];
+        cnt = c.offsets[key + 1] - st;
+        return cnt > 0 && c.bucket_z[key] <= zmax;
+    };
+    auto append = [&](bool ok, int st, int cnt, float zmax) {
         const uint64_t m = ballot(ok);
         if (ok) {
             const int pos = nbl + rank_below(m);
@@ -216,51 +389,77 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
             sh.bl_zmax[pos] = zmax;
         }
         nbl += popc64(m);
-        if (nbl >= WAVE || (q0 + WAVE >= total && nbl > 0)) {
+        if (nbl >= WAVE) {
             sweep_points(nbl);
             nbl = 0;
         }
+    };
+    // two chunks of window buckets per step so their loads overlap
+    for (int q0 = 0; q0 < total; q0 += 2 * WAVE) {
+        int stA, cntA, stB, cntB;
+        float zA, zB;
+        const bool okA = probe(q0 + l, stA, cntA, zA);
+        const bool okB = probe(q0 + WAVE + l, stB, cntB, zB);
+        append(okA, stA, cntA, zA);
+        append(okB, stB, cntB, zB);
     }
+    if (nbl > 0) sweep_points(nbl);
     if (npend > 0) flush(npend);
 }
 
-// Candidate walk.  On return lane j < m holds candidate j: its t, point index,
-// its K nearest neighbours `kd` (ascending (dist^2 bits, index), ~0 = none),
-// their number kc, and alpha.  selmask has bit j set for selected candidates.
+// Merge two ascending KT-lists and keep the KT smallest, ascending: the
+// element-wise minimum of a and reversed b is a bitonic sequence holding the
+// KT smallest, which half-cleaners then sort.
 template <int KT>
-__device__ __forceinline__ void walk_candidates(const SearchCtx &c, const RayGeom &g, SearchLds &sh,
-                                                uint64_t top, int m, float &tj, int &idxj,
-                                                uint64_t (&kd)[KT], int &kc, float &alpha,
-                                                uint64_t &selmask, int &n_sel)
+__device__ __forceinline__ void merge_low(uint64_t (&a)[KT], const uint64_t (&b)[KT])
 {
-    const int l = lane_id();
-    const bool cand = l < m;
-    tj = __uint_as_float((uint32_t)(top >> 32));
-    idxj = (int)(uint32_t)top;
-    lds_sync();
-    if (cand) {
-        const int slot = c.slot_of[(int64_t)g.vi * c.n_points + idxj];
-        sh.nb_p[l] = c.pts[slot];
-        sh.nb_t[l] = tj;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) a[k] = umin64(a[k], b[KT - 1 - k]);
+#pragma unroll
+    for (int j = KT / 2; j > 0; j >>= 1) {
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            if ((k & j) == 0) {
+                const uint64_t x = a[k], y = a[k + j];
+                a[k] = umin64(x, y);
+                a[k + j] = umax64(x, y);
+            }
+        }
     }
-    lds_sync();
+}
+
+// Nearest neighbours of 16 candidates at once.  Lane l = 4 g + q serves
+// candidate c0 + g; its four lanes split the candidate's t-window of the
+// sorted list (entries lo + q, lo + q + 4, ...), each keeping an ascending
+// register list of (dist^2 bits << 32 | index) among entries within R_j, and
+// the quad then merges its four lists (DPP within the quad).  On return every
+// lane of the quad holds the candidate's KT smallest keys (~0 = none).
+template <int KT>
+__device__ __forceinline__ void knn_quad(const SearchCtx &c, const RayGeom &g, const SearchLds &sh,
+                                         int j, int m, uint64_t (&kd)[KT])
+{
+    const int q = lane_id() & 3;
 #pragma unroll
     for (int k = 0; k < KT; ++k) kd[k] = ~0ull;
+    const bool active = j < m;
+    float tj = 0.0f, R2 = 0.0f;
     int lo = 0, hi = 0;
-    float Rj = 0.0f, R2 = 0.0f;
-    if (cand) {
-        Rj = search_radius(c.radius, c.inv_tref, tj);
+    if (active) {
+        tj = sh.nb_t[j];
+        const float Rj = search_radius(c.radius, c.inv_tref, tj);
         R2 = Rj * Rj;
+        // |t_i - t_j| > span implies dist^2 > R_j^2 (margins above rounding)
         const float span = Rj * 1.001f + tj * 4e-6f + 1e-7f;
         const float tlo = tj - span, thi = tj + span;
-        int a = 0, b = m;  // first index with nb_t >= tlo
+        int a = 0, b = j;  // first index with t >= tlo
         while (a < b) {
             const int mid = (a + b) >> 1;
             if (sh.nb_t[mid] < tlo) a = mid + 1;
             else b = mid;
         }
         lo = a;
-        b = m;  // first index with nb_t > thi
+        a = j + 1;
+        b = m;  // first index with t > thi
         while (a < b) {
             const int mid = (a + b) >> 1;
             if (sh.nb_t[mid] <= thi) a = mid + 1;
@@ -268,65 +467,110 @@ __device__ __forceinline__ void walk_candidates(const SearchCtx &c, const RayGeo
         }
         hi = a;
     }
-    int span_n = hi - lo;
+    int n_it = (hi - lo - q + 3) >> 2;
+    n_it = n_it > 0 ? n_it : 0;
 #pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        const int y = __shfl_xor(span_n, o, WAVE);
-        span_n = span_n > y ? span_n : y;
+    for (int o = 4; o < WAVE; o <<= 1) {
+        const int y = __shfl_xor(n_it, o, WAVE);
+        n_it = n_it > y ? n_it : y;
     }
-    for (int it = 0; it < span_n; ++it) {
-        const int i = lo + it;
-        bool ins = false;
-        uint64_t key = ~0ull;
+    for (int it = 0; it < n_it; ++it) {
+        const int i = lo + q + 4 * it;
+        uint64_t x = ~0ull;
         if (i < hi) {
             const float4 P = sh.nb_p[i];
             const float d2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, tj);
-            key = ((uint64_t)__float_as_uint(d2) << 32) | __float_as_uint(P.w);
-            ins = (d2 <= R2) && (key < kd[KT - 1]);
+            if (d2 <= R2) x = ((uint64_t)__float_as_uint(d2) << 32) | __float_as_uint(P.w);
         }
-        if (ballot(ins)) {
-            if (ins) {
-                uint64_t x = key;
+        // branch-free insertion: a key of ~0 leaves the list unchanged
 #pragma unroll
-                for (int k = 0; k < KT; ++k) {
-                    const uint64_t lo64 = umin64(kd[k], x);
-                    x = umax64(kd[k], x);
-                    kd[k] = lo64;
-                }
-            }
+        for (int k = 0; k < KT; ++k) {
+            const uint64_t lo64 = umin64(kd[k], x);
+            x = umax64(kd[k], x);
+            kd[k] = lo64;
         }
     }
-    kc = 0;
-    float sum = 0.0f;
+    uint64_t other[KT];
 #pragma unroll
-    for (int k = 0; k < KT; ++k) {
-        if (k < c.K && kd[k] != ~0ull) {
-            sum = sum + __builtin_sqrtf(__uint_as_float((uint32_t)(kd[k] >> 32)));
-            ++kc;
-        }
+    for (int k = 0; k < KT; ++k) other[k] = xor_lane_u64<1>(kd[k]);
+    merge_low<KT>(kd, other);
+#pragma unroll
+    for (int k = 0; k < KT; ++k) other[k] = xor_lane_u64<2>(kd[k]);
+    merge_low<KT>(kd, other);
+}
+
+// Candidate walk.  Candidates (the neighbours in (t, index) order) are
+// processed 16 at a time, candidate c0 + g on lanes 4 g .. 4 g + 3.  After a
+// chunk's transmittance walk, emit(s, q, tj, kd, kc) is called on the four
+// lanes (q = 0..3) of every candidate that became sample s, with its K nearest
+// neighbours kd (ascending (dist^2 bits, index), ~0 = none) and their number
+// kc.  Returns the sample count and sets first_idx to the primary point.
+template <int KT, typename Emit>
+__device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom &g, SearchLds &sh,
+                                               uint64_t top, int m, int &first_idx, Emit emit)
+{
+    const int l = lane_id();
+    lds_sync();
+    if (l < m) {
+        const int idxj = (int)(uint32_t)top;
+        const int slot = c.slot_of[(int64_t)g.vi * c.n_points + idxj];
+        sh.nb_p[l] = c.pts[slot];
+        sh.nb_t[l] = __uint_as_float((uint32_t)(top >> 32));
     }
-    alpha = 0.0f;
-    if (cand) {
-        const float dj = (sum + (float)(c.K - kc) * Rj) / (float)c.K;
-        const float uj = (dj * dj) * c.inv_beta2;
-        alpha = c.gamma * exp_neg(-uj);
-    }
-    // transmittance walk in candidate order (Eq. 5)
+    lds_sync();
     float T = 1.0f;
     int sel = 0;
-    uint64_t smask = 0;
-    for (int j = 0; j < m; ++j) {
-        const float aj = readlane_f32(alpha, j);
-        const float wj = aj * T;
-        if (wj > c.eps_w && sel < c.S) {
-            smask |= 1ull << j;
-            ++sel;
+    first_idx = -1;
+    bool done = false;
+    for (int c0 = 0; c0 < m && !done; c0 += 16) {
+        const int j = c0 + (l >> 2);
+        uint64_t kd[KT];
+        knn_quad<KT>(c, g, sh, j, m, kd);
+        float alpha = 0.0f, tj = 0.0f;
+        int kc = 0;
+        if (j < m) {
+            tj = sh.nb_t[j];
+            const float Rj = search_radius(c.radius, c.inv_tref, tj);
+            float sum = 0.0f;
+#pragma unroll
+            for (int k = 0; k < KT; ++k) {
+                if (k < c.K && kd[k] != ~0ull) {
+                    sum = sum + __builtin_sqrtf(__uint_as_float((uint32_t)(kd[k] >> 32)));
+                    ++kc;
+                }
+            }
+            const float dj = (sum + (float)(c.K - kc) * Rj) / (float)c.K;
+            const float uj = (dj * dj) * c.inv_beta2;
+            alpha = c.gamma * exp_neg(-uj);
         }
-        T = T * (1.0f - aj);
-        if (sel == c.S || c.gamma * T <= c.eps_w) break;
+        // transmittance walk over this chunk (Eq. 5)
+        const int c1 = min(c0 + 16, m);
+        const int sel0 = sel;
+        uint64_t smask = 0;  // bit g: candidate c0 + g selected
+        for (int jj = c0; jj < c1; ++jj) {
+            const float aj = readlane_f32(alpha, 4 * (jj - c0));
+            const float wj = aj * T;
+            if (wj > c.eps_w && sel < c.S) {
+                smask |= 1ull << (jj - c0);
+                ++sel;
+            }
+            T = T * (1.0f - aj);
+            if (sel == c.S || c.gamma * T <= c.eps_w) {
+                done = true;
+                break;
+            }
+        }
+        if (smask) {
+            if (sel0 == 0) {
+                const int gsel = __builtin_ctzll(smask);
+                first_idx = __float_as_int(sh.nb_p[c0 + gsel].w);
+            }
+            const int gl = l >> 2;
+            if ((smask >> gl) & 1ull)
+                emit(sel0 + popc64(smask & ((1ull << gl) - 1ull)), l & 3, tj, kd, kc);
+        }
     }
-    selmask = smask;
-    n_sel = sel;
+    return sel;
 }
 
 }  // namespace hp

@@ -21,10 +21,13 @@ struct TableWs {
     int32_t *slot_of;      // [n_views * n]   slot per point and view
     int32_t *big_list;     // [n_buckets]     buckets too large for one lane
     int32_t *big_n;        // [1]
+    float *bucket_z;       // [n_buckets]     depth of the first point (+inf if empty)
+    uint32_t *cell_zmin;   // [n_cells]       min depth bits per cell (+inf if empty)
     size_t bytes;
 };
 
-inline TableWs table_ws_layout(void *base, int64_t n, int n_views, int64_t n_buckets)
+inline TableWs table_ws_layout(void *base, int64_t n, int n_views, int64_t n_buckets,
+                               int64_t n_cells)
 {
     TableWs w;
     size_t off = 0;
@@ -47,6 +50,8 @@ inline TableWs table_ws_layout(void *base, int64_t n, int n_views, int64_t n_buc
     w.slot_of = (int32_t *)take(sizeof(int32_t) * nvs);
     w.big_list = (int32_t *)take(sizeof(int32_t) * n_buckets);
     w.big_n = (int32_t *)take(sizeof(int32_t) * 64);
+    w.bucket_z = (float *)take(sizeof(float) * n_buckets);
+    w.cell_zmin = (uint32_t *)take(sizeof(uint32_t) * (n_cells > 0 ? n_cells : 1));
     w.bytes = off;
     return w;
 }

@@ -4,71 +4,84 @@
 
 namespace hp {
 
-// Ray handled by this workgroup.  Consecutive workgroup ids go to different
-// XCDs (round robin over 8); give each XCD a contiguous band of rays so the
-// rays sharing table buckets also share an L2.
-__device__ __forceinline__ int64_t xcd_ray(int64_t n_rays)
-{
-    const int64_t bid = blockIdx.x;
-    const int64_t per = gridDim.x >> 3;
-    return (bid & 7) * per + (bid >> 3);
-}
+constexpr int RAYS_PER_CHUNK = 4;
 
+// Persistent: each 64-lane workgroup takes chunks of RAYS_PER_CHUNK
+// consecutive rays (neighbouring pixels share table buckets), striding by the
+// grid size so that every workgroup sees a mix of empty and busy regions.
 template <int KT>
-__global__ void __launch_bounds__(WAVE) k_search_sample(SearchCtx c, SampleOut o)
+__device__ __forceinline__ void search_sample_body(const SearchCtx &c, const SampleOut &o)
 {
     __shared__ SearchLds sh;
-    const int64_t ray = xcd_ray(c.n_rays);
-    if (ray >= c.n_rays) return;
     const int l = lane_id();
-    const RayGeom g = ray_geometry(c, ray);
-    uint64_t top;
-    int count;
-    search_neighbours(c, g, sh, top, count);
-    const int m = count < c.M ? count : c.M;
-    float tj, alpha;
-    int idxj, kc, nsel;
-    uint64_t kd[KT], selmask;
-    walk_candidates<KT>(c, g, sh, top, m, tj, idxj, kd, kc, alpha, selmask, nsel);
-
-    if (l == 0) {
-        o.n_sel[ray] = nsel;
-        o.n_nbr[ray] = m;
-        o.flags[ray] = (count > c.M) ? 1u : 0u;
-    }
-    const int first = selmask ? __builtin_ctzll(selmask) : 0;
-    const int prim = readlane_i32(idxj, first);
-    if (l == 0) o.primary[ray] = selmask ? prim : -1;
-    if ((selmask >> l) & 1ull) {
-        const int s = popc64(selmask & ((1ull << l) - 1ull));
-        const int64_t row = ray * c.S + s;
-        o.t[row] = tj;
+    const int64_t n_chunks = (c.n_rays + RAYS_PER_CHUNK - 1) / RAYS_PER_CHUNK;
+    for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+        const int64_t r1 = min((ch + 1) * RAYS_PER_CHUNK, c.n_rays);
+        for (int64_t ray = ch * RAYS_PER_CHUNK; ray < r1; ++ray) {
+            const RayGeom g = ray_geometry(c, ray);
+            uint64_t top;
+            int count;
+            search_neighbours(c, g, sh, top, count);
+            const int m = count < c.M ? count : c.M;
+            const int64_t rbase = ray * c.S;
+            int prim;
+            const int nsel = walk_candidates<KT>(
+                c, g, sh, top, m, prim,
+                [&](int s, int q, float tj, const uint64_t(&kd)[KT], int kc) {
+                    // the candidate's four lanes share the row: lane q writes k = q, q + 4, ...
+                    const int64_t row = rbase + s;
+                    if (q == 0) o.t[row] = tj;
 #pragma unroll
-        for (int k = 0; k < KT; ++k) {
-            if (k < c.K) {
-                const bool v = k < kc;
-                o.knn_idx[row * c.K + k] = v ? (int32_t)(uint32_t)kd[k] : -1;
-                o.knn_dist[row * c.K + k] =
-                    v ? __builtin_sqrtf(__uint_as_float((uint32_t)(kd[k] >> 32))) : 0.0f;
+                    for (int k = 0; k < KT; ++k) {
+                        if ((k & 3) == q && k < c.K) {
+                            const bool v = k < kc;
+                            o.knn_idx[row * c.K + k] = v ? (int32_t)(uint32_t)kd[k] : -1;
+                            o.knn_dist[row * c.K + k] =
+                                v ? __builtin_sqrtf(__uint_as_float((uint32_t)(kd[k] >> 32))) : 0.0f;
+                        }
+                    }
+                });
+            if (l == 0) {
+                o.n_sel[ray] = nsel;
+                o.n_nbr[ray] = m;
+                o.flags[ray] = (count > c.M) ? 1u : 0u;
+                o.primary[ray] = prim;
             }
+            const float tj = __uint_as_float((uint32_t)(top >> 32));
+            const int idxj = (int)(uint32_t)top;
+            if (o.nbr_idx && l < c.M) {
+                o.nbr_idx[ray * c.M + l] = l < m ? idxj : -1;
+                o.nbr_t[ray * c.M + l] = l < m ? tj : 0.0f;
+            }
+            lds_sync();
         }
     }
-    if (o.nbr_idx && l < c.M) {
-        o.nbr_idx[ray * c.M + l] = l < m ? idxj : -1;
-        o.nbr_t[ray * c.M + l] = l < m ? tj : 0.0f;
-    }
+}
+
+// The phases are latency bound, so occupancy matters more than registers:
+// ask for 8 waves per SIMD where the nearest-neighbour lists are short.
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_search_sample_k4(SearchCtx c, SampleOut o) { search_sample_body<4>(c, o); }
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_search_sample_k8(SearchCtx c, SampleOut o) { search_sample_body<8>(c, o); }
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_search_sample_k16(SearchCtx c, SampleOut o) { search_sample_body<16>(c, o); }
+__global__ void __launch_bounds__(WAVE) k_search_sample_k32(SearchCtx c, SampleOut o)
+{
+    search_sample_body<32>(c, o);
 }
 
 hipError_t launch_search_sample(const SearchCtx &c, const SampleOut &o, int kt, hipStream_t s)
 {
-    int64_t blocks = (c.n_rays + 7) / 8 * 8;
+    const int64_t chunks = (c.n_rays + RAYS_PER_CHUNK - 1) / RAYS_PER_CHUNK;
+    const int64_t blocks = chunks < 8192 ? chunks : 8192;
     if (blocks == 0) return hipSuccess;
     const dim3 grid((unsigned)blocks), block(WAVE);
     switch (kt) {
-    case 4: k_search_sample<4><<<grid, block, 0, s>>>(c, o); break;
-    case 8: k_search_sample<8><<<grid, block, 0, s>>>(c, o); break;
-    case 16: k_search_sample<16><<<grid, block, 0, s>>>(c, o); break;
-    default: k_search_sample<32><<<grid, block, 0, s>>>(c, o); break;
+    case 4: k_search_sample_k4<<<grid, block, 0, s>>>(c, o); break;
+    case 8: k_search_sample_k8<<<grid, block, 0, s>>>(c, o); break;
+    case 16: k_search_sample_k16<<<grid, block, 0, s>>>(c, o); break;
+    default: k_search_sample_k32<<<grid, block, 0, s>>>(c, o); break;
     }
     return hipGetLastError();
 }

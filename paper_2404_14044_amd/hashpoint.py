@@ -61,6 +61,8 @@ class HPTable(ctypes.Structure):
                 ("n_rays", ctypes.c_int64),
                 ("offsets", ctypes.c_void_p), ("pts", ctypes.c_void_p),
                 ("perm", ctypes.c_void_p), ("slot_of", ctypes.c_void_p),
+                ("bucket_z", ctypes.c_void_p), ("cell_zmin", ctypes.c_void_p),
+                ("n_cells", ctypes.c_int64),
                 ("scratch", ctypes.c_void_p), ("views", HPViewInfo * HP_MAX_VIEWS)]
 
 
@@ -285,3 +287,67 @@ def render(samples: Dict[str, torch.Tensor], n_rays: int, feat: torch.Tensor,
 
 def to_device_mlp(mlp: Dict[str, np.ndarray], device) -> Dict[str, torch.Tensor]:
     return {k: torch.from_numpy(np.ascontiguousarray(v, np.float32)).to(device) for k, v in mlp.items()}
+
+
+def backward_workspace(table: Table, params=None) -> int:
+    st = ctypes.c_int32()
+    p = make_params(params or table.params)
+    n = lib().hp_backward_workspace(ctypes.byref(table.tab), ctypes.byref(p), ctypes.byref(st))
+    _check(st.value, "hp_backward_workspace")
+    return int(n)
+
+
+def render_backward(table: Table, feat: torch.Tensor, mlp: Dict[str, torch.Tensor], params,
+                    precision: int, grad_rgb: torch.Tensor,
+                    grad_feat: Optional[torch.Tensor] = None,
+                    grad_mlp: Optional[Dict[str, torch.Tensor]] = None,
+                    ws: Optional[torch.Tensor] = None, stream=None):
+    """Gradients of sum(grad_rgb * rgb) w.r.t. features and MLP parameters.
+    Results are added to grad_feat / grad_mlp (zero-initialised when not given)."""
+    params = params or table.params
+    dev = feat.device
+    if grad_feat is None:
+        grad_feat = torch.zeros_like(feat)
+    if grad_mlp is None:
+        grad_mlp = {k: torch.zeros_like(v) for k, v in mlp.items()}
+    need = backward_workspace(table, params)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    arr, p = _cams_array(table.cams), make_params(params)
+    m, gm = mlp_struct(mlp), mlp_struct(grad_mlp)
+    _check(lib().hp_render_backward(ctypes.byref(table.tab), arr, len(table.cams),
+                                    _dev(feat, torch.float32, "feat"), int(feat.shape[1]),
+                                    ctypes.byref(m), int(precision), ctypes.byref(p),
+                                    _dev(grad_rgb, torch.float32, "grad_rgb"),
+                                    _dev(grad_feat, torch.float32, "grad_feat"), ctypes.byref(gm),
+                                    ws.data_ptr(), ws.numel(), _stream(stream)),
+           "hp_render_backward")
+    return grad_feat, grad_mlp
+
+
+_MLP_KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+class HashPointRender(torch.autograd.Function):
+    """rgb = render(search_sample(table), feat, mlp) with a hand-written backward.
+
+    The forward keeps no sample lists: the backward recomputes the search and
+    sampling from the table (they depend on geometry only)."""
+
+    @staticmethod
+    def forward(ctx, feat, W1, b1, W2, b2, W3, b3, table, params, precision):
+        mlp = dict(zip(_MLP_KEYS, (W1, b1, W2, b2, W3, b3)))
+        smp = search_sample(table, params)
+        out = render(smp, table.n_rays, feat, mlp, params, precision)
+        del smp
+        ctx.table, ctx.params, ctx.precision = table, params, precision
+        ctx.save_for_backward(feat, W1, b1, W2, b2, W3, b3)
+        return out["rgb"].view(table.n_rays, 3)
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        feat, W1, b1, W2, b2, W3, b3 = ctx.saved_tensors
+        mlp = dict(zip(_MLP_KEYS, (W1, b1, W2, b2, W3, b3)))
+        gf, gm = render_backward(ctx.table, feat, mlp, ctx.params, ctx.precision,
+                                 grad_rgb.contiguous().float())
+        return (gf, gm["W1"], gm["b1"], gm["W2"], gm["b2"], gm["W3"], gm["b3"], None, None, None)

@@ -1,0 +1,125 @@
+"""The C ABI library: it loads without a GPU, exports every function that
+include/hashpoint.h declares, and its host-side validation rejects bad
+arguments before any launch (so these calls never touch a device)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2404_14044_amd import hashpoint as hp
+from paper_2404_14044_amd import scenes
+
+import oracle
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "include", "hashpoint.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_function():
+    L = hp.lib()
+    names = _declared()
+    assert "hp_build_table" in names and "hp_render_backward" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(hp.EXPORTED)
+
+
+def test_struct_sizes_match_header():
+    # pointer-sized fields and int64 alignment as the C compiler lays them out
+    assert ctypes.sizeof(hp.HPCamera) == 4 * 18
+    assert ctypes.sizeof(hp.HPParams) == 4 * 17
+    assert ctypes.sizeof(hp.HPViewInfo) == 32
+    assert ctypes.sizeof(hp.HPSamples) == 8 * 9
+    assert ctypes.sizeof(hp.HPMlp) == 8 * 6
+
+
+def test_status_strings():
+    L = hp.lib()
+    for code in range(6):
+        assert len(L.hp_status_str(code)) > 0
+    assert L.hp_status_str(99) == b"unknown status"
+
+
+def test_view_bounds_match_oracle_guard():
+    for sc in (scenes.sphere_plane(n_sphere=10, n_plane=10), scenes.tiny_scene()):
+        for inv in (0.0, 1.0 / sc.params.t_near):
+            p = sc.params.replace(inv_tref=float(np.float32(inv)))
+            g, d = hp.view_bounds(sc.cams[0], p)
+            assert g == oracle.guard(sc.cams[0], p)
+            assert g == int(np.floor(0.5 + d)) + 1 or abs(0.5 + d - round(0.5 + d)) < 1e-4
+
+
+def test_workspace_size_grows_with_points():
+    sc = scenes.sphere_plane(n_sphere=10, n_plane=10)
+    a = hp.table_workspace(1000, sc.cams, sc.params)
+    b = hp.table_workspace(100000, sc.cams, sc.params)
+    assert b > a > 0
+
+
+@pytest.mark.parametrize("field,value", [
+    ("radius", 0.0), ("radius", float("nan")), ("t_near", 0.0), ("t_far", 0.5),
+    ("K", 0), ("K", 33), ("n_samples", 0), ("n_samples", 65), ("m_cap", 0), ("m_cap", 65),
+    ("gamma", 0.0), ("gamma", 1.5), ("eps_idw", 0.0), ("delta_last", 0.0), ("layout", 7),
+    ("flags", 1), ("inv_tref", -1.0),
+])
+def test_invalid_params_rejected_on_host(field, value):
+    sc = scenes.sphere_plane(n_sphere=10, n_plane=10)
+    p = sc.params.replace(**{field: value})
+    L = hp.lib()
+    st = ctypes.c_int32()
+    arr, pp = hp._cams_array(sc.cams), hp.make_params(p)
+    n = L.hp_table_workspace(10, arr, 1, ctypes.byref(pp), ctypes.byref(st))
+    if field == "K" and value == 33:
+        # K is checked by the search (unsupported), not by the table
+        return
+    assert n == 0 and st.value == hp.HP_E_INVALID
+
+
+def test_build_rejects_bad_arguments_without_launching():
+    sc = scenes.sphere_plane(n_sphere=10, n_plane=10)
+    L = hp.lib()
+    arr, pp = hp._cams_array(sc.cams), hp.make_params(sc.params)
+    tab = hp.HPTable()
+    # null xyz with n > 0
+    assert L.hp_build_table(None, 10, arr, 1, ctypes.byref(pp), None, 0, ctypes.byref(tab), None) == hp.HP_E_INVALID
+    # no workspace
+    fake = ctypes.c_void_p(0x1000)
+    assert L.hp_build_table(fake, 10, arr, 1, ctypes.byref(pp), None, 0, ctypes.byref(tab), None) == hp.HP_E_WORKSPACE
+    # too small a workspace
+    assert L.hp_build_table(fake, 10, arr, 1, ctypes.byref(pp), fake, 16, ctypes.byref(tab), None) == hp.HP_E_WORKSPACE
+    # too many views, bad camera
+    assert L.hp_build_table(fake, 10, arr, 0, ctypes.byref(pp), fake, 1 << 30, ctypes.byref(tab), None) == hp.HP_E_INVALID
+    bad = hp._cams_array(sc.cams)
+    bad[0].fx = -1.0
+    assert L.hp_build_table(fake, 10, bad, 1, ctypes.byref(pp), fake, 1 << 30, ctypes.byref(tab), None) == hp.HP_E_INVALID
+    # n * views beyond int32 indices
+    assert L.hp_build_table(fake, 1 << 31, arr, 1, ctypes.byref(pp), fake, 1 << 30, ctypes.byref(tab), None) == hp.HP_E_CAPACITY
+
+
+def test_search_and_render_reject_bad_arguments_without_launching():
+    sc = scenes.sphere_plane(n_sphere=10, n_plane=10)
+    L = hp.lib()
+    arr, pp = hp._cams_array(sc.cams), hp.make_params(sc.params)
+    tab = hp.HPTable()  # all null pointers
+    smp = hp.HPSamples()
+    assert L.hp_search_sample(ctypes.byref(tab), arr, 1, ctypes.byref(pp), ctypes.byref(smp), None) == hp.HP_E_INVALID
+    assert L.hp_search_sample(None, arr, 1, ctypes.byref(pp), ctypes.byref(smp), None) == hp.HP_E_INVALID
+    mlp = hp.HPMlp()
+    fake = ctypes.c_void_p(0x1000)
+    # feature width other than 32
+    assert L.hp_render(ctypes.byref(smp), 0, fake, 16, ctypes.byref(mlp), 0, ctypes.byref(pp), fake, None, None, None) == hp.HP_E_UNSUPPORTED
+    # null weights
+    assert L.hp_render(ctypes.byref(smp), 0, fake, 32, ctypes.byref(mlp), 0, ctypes.byref(pp), fake, None, None, None) == hp.HP_E_INVALID
+    # bad precision
+    assert L.hp_render(ctypes.byref(smp), 0, fake, 32, ctypes.byref(mlp), 7, ctypes.byref(pp), fake, None, None, None) == hp.HP_E_INVALID
+    # backward with a null table
+    assert L.hp_render_backward(None, arr, 1, fake, 32, ctypes.byref(mlp), 0, ctypes.byref(pp), fake, fake,
+                                ctypes.byref(mlp), fake, 1 << 30, None) == hp.HP_E_INVALID

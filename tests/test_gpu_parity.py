@@ -118,3 +118,16 @@ def test_deterministic(objects):
     ta = host(a["samples"]["t"]).reshape(-1, S)[mask]
     tb = host(b["samples"]["t"]).reshape(-1, S)[mask]
     assert np.array_equal(ta.view(np.int32), tb.view(np.int32))
+
+
+def test_multiview_table_and_search():
+    """Four views in one table: every view's rays match the oracle."""
+    base = scenes.objects_1m(n=200_000, res=64)
+    sc = scenes.diff_4x400(base=base, res=160)
+    out = gpu_forward(sc, debug=True)
+    tab = out["table"]
+    for v, cam in enumerate(sc.cams):
+        info = tab.view(v)
+        pix = sample_pixels(cam, 1024, seed=30 + v)
+        ex = compare_exact(sc, out["samples"], pix, view=v, ray_base=info.ray_base)
+        assert (ex["n_sel"] > 0).sum() > 50
