@@ -49,6 +49,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--layout", type=int, default=0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched-views and training-step legs")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -154,10 +156,85 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
+    if not args.no_extra:
+        result["batched_16"] = batched_leg(sc)
+        result["train_4x400"] = train_leg(sc)
+
     if args.cpu_seconds > 0:
         result.update(cpu_leg(sc, p, smp, outs, R, args.cpu_seconds))
 
     print(json.dumps(result), flush=True)
+
+
+def _time_ms(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def batched_leg(sc, reps=5):
+    """16 views of the object scene, sides uniform in {256..1024}: one batched
+    pass (eager and replayed from a captured graph) vs 16 per-view passes."""
+    import torch
+    from paper_2404_14044_amd import hashpoint as hp
+    from paper_2404_14044_amd import scenes
+    from paper_2404_14044_amd.batched import BatchedRenderer, render_views_separately
+    dev = torch.device("cuda:0")
+    bs = scenes.batched_16(base=sc)
+    xyz = torch.from_numpy(bs.xyz).to(dev)
+    feat = torch.from_numpy(bs.feat).to(dev)
+    mlp = hp.to_device_mlp(bs.mlp, dev)
+    br = BatchedRenderer(xyz, feat, mlp, bs.cams, bs.params, hp.HP_BF16)
+    t_eager = _time_ms(br.run_eager, reps)
+    br.capture()
+    t_graph = _time_ms(br.replay, reps)
+    del br
+    state = render_views_separately(xyz, feat, mlp, bs.cams, bs.params, hp.HP_BF16)
+    t_sep = _time_ms(lambda: render_views_separately(xyz, feat, mlp, bs.cams, bs.params,
+                                                     hp.HP_BF16, state), reps)
+    rays = sum(c.W * c.H for c in bs.cams)
+    return {"rays": rays, "views": len(bs.cams),
+            "graph_ms": t_graph, "eager_ms": t_eager, "separate_ms": t_sep,
+            "graph_mrays_s": rays / t_graph / 1e3, "eager_mrays_s": rays / t_eager / 1e3,
+            "separate_mrays_s": rays / t_sep / 1e3, "speedup_vs_separate": t_sep / t_graph}
+
+
+def train_leg(sc, reps=5):
+    """Training step on 4 views of 400x400: BF16 forward, FP32 gradients for
+    the 1M x 32 features and the decoder, L2 loss to a random target; the
+    backward recomputes search and sampling."""
+    import torch
+    from paper_2404_14044_amd import hashpoint as hp
+    from paper_2404_14044_amd import scenes
+    dev = torch.device("cuda:0")
+    ds = scenes.diff_4x400(base=sc)
+    xyz = torch.from_numpy(ds.xyz).to(dev)
+    feat = torch.from_numpy(ds.feat).to(dev).requires_grad_(True)
+    mlp = {k: v.requires_grad_(True) for k, v in hp.to_device_mlp(ds.mlp, dev).items()}
+    target = torch.from_numpy(ds.extra["target"]).to(dev)
+    tab = hp.build_table(xyz, ds.cams, ds.params)
+    keys = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+    def step():
+        feat.grad = None
+        for k in keys:
+            mlp[k].grad = None
+        rgb = hp.HashPointRender.apply(feat, *[mlp[k] for k in keys], tab, ds.params, hp.HP_BF16)
+        loss = ((rgb - target) ** 2).mean()
+        loss.backward()
+
+    t_step = _time_ms(step, reps)
+    smp = hp.search_sample(tab, ds.params)
+    t_fwd = _time_ms(lambda: hp.render(hp.search_sample(tab, ds.params, out=smp), tab.n_rays,
+                                       feat.detach(), {k: v.detach() for k, v in mlp.items()},
+                                       ds.params, hp.HP_BF16), reps)
+    return {"rays": tab.n_rays, "step_ms": t_step, "forward_ms": t_fwd,
+            "backward_ms": t_step - t_fwd, "step_mrays_s": tab.n_rays / t_step / 1e3}
 
 
 def cpu_leg(sc, p, smp, outs, R, seconds):

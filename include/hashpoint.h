@@ -86,13 +86,17 @@ typedef struct hp_camera {
  *  delta_last: interval length of the last sample of a ray (Eq. 2).
  *  bg: background colour.
  *  layout: HP_LAYOUT_ROWMAJOR or HP_LAYOUT_TILED (8x8 pixel tiles).
- *  flags: reserved, must be 0. */
+ *  flags: reserved, must be 0.
+ *  search_chunk: rays a search workgroup takes at a time, 0 = default (4),
+ *      at most 64; search_blocks: persistent search grid, 0 = default.
+ *      Neither changes any result; an autotuner picks them per workload. */
 typedef struct hp_params {
     float radius, inv_tref, t_near, t_far;
     int32_t K, n_samples, m_cap;
     float gamma, inv_beta2, eps_w, eps_idw, delta_last;
     float bg[3];
     int32_t layout, flags;
+    int32_t search_chunk, search_blocks;
 } hp_params;
 
 /* Per-view geometry of a table, filled by hp_build_table. */

@@ -49,6 +49,7 @@ bool valid_params(const hp_params &p)
         if (!finite_f(p.bg[i])) return false;
     if (p.layout != HP_LAYOUT_ROWMAJOR && p.layout != HP_LAYOUT_TILED) return false;
     if (p.flags != 0) return false;
+    if (p.search_chunk < 0 || p.search_chunk > 64 || p.search_blocks < 0) return false;
     return true;
 }
 
@@ -250,6 +251,8 @@ static hp_status make_ctx(const hp_table *tab, const hp_camera *cams, int32_t n_
     c.K = p->K;
     c.S = p->n_samples;
     c.M = p->m_cap;
+    c.chunk = p->search_chunk > 0 ? p->search_chunk : 4;
+    c.blocks = p->search_blocks;
     return HP_OK;
 }
 

@@ -90,11 +90,10 @@ __device__ __forceinline__ void backward_body(const BwdArgs &A)
     float gW3[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     float gb1 = 0.0f, gb2 = 0.0f, gb3 = 0.0f;
 
-    constexpr int RPC = 4;
-    const int64_t n_chunks = (c.n_rays + RPC - 1) / RPC;
+    const int64_t n_chunks = (c.n_rays + c.chunk - 1) / c.chunk;
     for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
-        const int64_t r1 = min((ch + 1) * RPC, c.n_rays);
-        for (int64_t ray = ch * RPC; ray < r1; ++ray) {
+        const int64_t r1 = min((ch + 1) * c.chunk, c.n_rays);
+        for (int64_t ray = ch * c.chunk; ray < r1; ++ray) {
             const float g0 = A.grad_rgb[3 * ray], g1 = A.grad_rgb[3 * ray + 1],
                         g2 = A.grad_rgb[3 * ray + 2];
             if (g0 == 0.0f && g1 == 0.0f && g2 == 0.0f) continue;  // no gradient through this ray
@@ -344,7 +343,7 @@ size_t backward_workspace_bytes() { return (size_t)BWD_BLOCKS * NPAR * sizeof(fl
 
 hipError_t launch_backward(const BwdArgs &A, int kt, int precision, const MlpGrad &gm, hipStream_t s)
 {
-    const int64_t chunks = (A.c.n_rays + 3) / 4;
+    const int64_t chunks = (A.c.n_rays + A.c.chunk - 1) / A.c.chunk;
     const int nblk = (int)(chunks < BWD_BLOCKS ? (chunks > 0 ? chunks : 1) : BWD_BLOCKS);
     const dim3 grid(nblk), block(WAVE);
 #define HP_BWD(KTV)                                                                 \

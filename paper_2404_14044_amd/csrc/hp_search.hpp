@@ -54,6 +54,7 @@ struct SearchCtx {
     int64_t n_points, n_rays;
     float radius, inv_tref, t_near, t_far, gamma, inv_beta2, eps_w;
     int32_t K, S, M;
+    int32_t chunk, blocks;  // rays per work chunk, persistent grid (0 = default)
 };
 
 constexpr int BL_CAP = 128;
@@ -359,20 +360,25 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
     };
 
     // one window bucket: returns whether it may hold a neighbour, and its slots
+    // (q + 0.5) / Wd is at least 0.5 / Wd from an integer, far more than the
+    // error of a float reciprocal, so the row index below is exact.
+    const float inv_wd = 1.0f / (float)Wd;
+    const float inv_L = 1.0f / g.L;
     auto probe = [&](int q, int &st, int &cnt, float &zmax) -> bool {
         zmax = z_hi;
         st = cnt = 0;
         if (q >= total) return false;
-        const int qy = q / Wd;
+        const int qy = (int)(((float)q + 0.5f) * inv_wd);
         const int dyi = qy - h, dxi = q - qy * Wd - h;
         const int bx = gx + dxi, by = gy + dyi;
         const float ex = __builtin_fmaxf(0.0f, __builtin_fabsf((float)dxi) - 0.5f);
         const float ey = __builtin_fmaxf(0.0f, __builtin_fabsf((float)dyi) - 0.5f);
-        const float D = __builtin_sqrtf(ex * ex + ey * ey);
+        // bounds only (margins of 1e-3 px and 0.1% dwarf 1-ulp approximations)
+        const float D = __builtin_amdgcn_sqrtf(ex * ex + ey * ey);
         if (!(bx >= 0 && bx < V.Wg && by >= 0 && by < V.Hg && D <= Dmax)) return false;
         const float Dp = D - 0.01f;
         if (Dp > 0.0f && Dp > dinf) {
-            const float zc = ((frL2 / Dp + two_rw) / g.L) * 1.001f + 1e-5f;
+            const float zc = ((frL2 * __builtin_amdgcn_rcpf(Dp) + two_rw) * inv_L) * 1.001f + 1e-5f;
             zmax = zc < z_hi ? zc : z_hi;
         }
         const int key = bucket_of(V, c.layout, bx, by);

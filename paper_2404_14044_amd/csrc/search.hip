@@ -4,9 +4,7 @@
 
 namespace hp {
 
-constexpr int RAYS_PER_CHUNK = 4;
-
-// Persistent: each 64-lane workgroup takes chunks of RAYS_PER_CHUNK
+// Persistent: each 64-lane workgroup takes chunks of c.chunk
 // consecutive rays (neighbouring pixels share table buckets), striding by the
 // grid size so that every workgroup sees a mix of empty and busy regions.
 template <int KT>
@@ -14,10 +12,10 @@ __device__ __forceinline__ void search_sample_body(const SearchCtx &c, const Sam
 {
     __shared__ SearchLds sh;
     const int l = lane_id();
-    const int64_t n_chunks = (c.n_rays + RAYS_PER_CHUNK - 1) / RAYS_PER_CHUNK;
+    const int64_t n_chunks = (c.n_rays + c.chunk - 1) / c.chunk;
     for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
-        const int64_t r1 = min((ch + 1) * RAYS_PER_CHUNK, c.n_rays);
-        for (int64_t ray = ch * RAYS_PER_CHUNK; ray < r1; ++ray) {
+        const int64_t r1 = min((ch + 1) * c.chunk, c.n_rays);
+        for (int64_t ray = ch * c.chunk; ray < r1; ++ray) {
             const RayGeom g = ray_geometry(c, ray);
             uint64_t top;
             int count;
@@ -73,8 +71,9 @@ __global__ void __launch_bounds__(WAVE) k_search_sample_k32(SearchCtx c, SampleO
 
 hipError_t launch_search_sample(const SearchCtx &c, const SampleOut &o, int kt, hipStream_t s)
 {
-    const int64_t chunks = (c.n_rays + RAYS_PER_CHUNK - 1) / RAYS_PER_CHUNK;
-    const int64_t blocks = chunks < 8192 ? chunks : 8192;
+    const int64_t chunks = (c.n_rays + c.chunk - 1) / c.chunk;
+    const int64_t cap = c.blocks > 0 ? c.blocks : 8192;
+    const int64_t blocks = chunks < cap ? chunks : cap;
     if (blocks == 0) return hipSuccess;
     const dim3 grid((unsigned)blocks), block(WAVE);
     switch (kt) {

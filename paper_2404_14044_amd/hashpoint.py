@@ -45,7 +45,8 @@ class HPParams(ctypes.Structure):
                 ("gamma", ctypes.c_float), ("inv_beta2", ctypes.c_float),
                 ("eps_w", ctypes.c_float), ("eps_idw", ctypes.c_float),
                 ("delta_last", ctypes.c_float), ("bg", ctypes.c_float * 3),
-                ("layout", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("layout", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("search_chunk", ctypes.c_int32), ("search_blocks", ctypes.c_int32)]
 
 
 class HPViewInfo(ctypes.Structure):
@@ -136,6 +137,8 @@ def make_params(p) -> HPParams:
     for i in range(3):
         s.bg[i] = float(p.bg[i])
     s.layout, s.flags = int(getattr(p, "layout", 0)), int(getattr(p, "flags", 0))
+    s.search_chunk = int(getattr(p, "search_chunk", 0))
+    s.search_blocks = int(getattr(p, "search_blocks", 0))
     return s
 
 

@@ -112,6 +112,8 @@ class Params:
     bg: tuple = (0.0, 0.0, 0.0)
     layout: int = 0
     flags: int = 0
+    search_chunk: int = 0
+    search_blocks: int = 0
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

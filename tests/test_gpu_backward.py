@@ -2,16 +2,24 @@
 
 The gradient flows through compositing (Eq. 2), the decoder and the
 inverse-distance aggregation; samples are recomputed from the table.
-Tolerances (max abs over a tensor, relative to that tensor's largest entry):
-FP32 forward 1e-4 (FP32 accumulation and atomics against binary64);
-BF16 forward 3e-2 (activations carry bfloat16 rounding of ~2^-9 per operand,
-amplified through two hidden layers).
+
+FP32 forward: max abs error over each tensor, relative to its largest entry,
+within 1e-4 of the binary64 gradient (FP32 accumulation and atomics).
+
+BF16 forward: the decoder's activations carry bfloat16 rounding, which flips
+the sign of ReLU units near zero, so the gradient differs from the unrounded
+binary64 one by up to ~20% of the largest entry (relative L2 ~5%).  That part
+is checked against a binary64 reference with the same bfloat16 roundings
+(tests/bf16_emul.py) to 1e-3, and against the oracle within a relative L2 of
+0.1.
 """
 import numpy as np
 import pytest
 
 import oracle
 from paper_2404_14044_amd import scenes
+
+from bf16_emul import grad_bf16
 
 pytestmark = pytest.mark.gpu
 
@@ -32,7 +40,7 @@ def _gpu(sc, grad_rgb, precision):
     return gf.cpu().numpy(), {k: v.cpu().numpy() for k, v in gm.items()}, tab
 
 
-def _oracle(sc, grad_rgb, rays_per_view):
+def _oracle(sc, grad_rgb, rays_per_view, fn=None):
     """binary64 gradient of sum(grad_rgb * rgb) over the given rays of each view."""
     out = {"feat": np.zeros(sc.feat.shape)}
     for k in KEYS:
@@ -43,27 +51,44 @@ def _oracle(sc, grad_rgb, rays_per_view):
         if len(pix):
             pc = oracle.to_camera(sc.xyz, cam)
             ex = oracle.exact(pc, cam, sc.params, pix)
-            g = oracle.grad64(pc, sc.feat, sc.mlp, cam, sc.params, ex,
-                              grad_rgb[base + np.asarray(pix, np.int64)].astype(np.float64))
+            gr = grad_rgb[base + np.asarray(pix, np.int64)].astype(np.float64)
+            g = (fn or oracle.grad64)(pc, sc.feat, sc.mlp, cam, sc.params, ex, gr)
             for k in out:
                 out[k] += g[k]
         base += cam.W * cam.H
     return out
 
 
-def _check(gpu_f, gpu_m, ref, tol):
+def _errors(gpu_f, gpu_m, ref):
     errs = {}
     for k in ("feat",) + KEYS:
         a = gpu_f if k == "feat" else gpu_m[k]
         b = ref[k]
         scale = max(np.abs(b).max(), 1e-12)
-        errs[k] = float(np.abs(a - b).max() / scale)
-    print("relative max errors", errs)
-    assert all(e <= tol for e in errs.values()), errs
+        errs[k] = (float(np.abs(a - b).max() / scale),
+                   float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)))
+    return errs
 
 
-@pytest.mark.parametrize("prec_name,tol", [("fp32", 1e-4), ("bf16", 3e-2)])
-def test_backward_sphere_plane(prec_name, tol):
+def _check(gpu_f, gpu_m, ref, tol, rel_l2=None):
+    errs = _errors(gpu_f, gpu_m, ref)
+    print("(max/max, relative L2) errors", errs)
+    if rel_l2 is None:
+        assert all(e[0] <= tol for e in errs.values()), errs
+    else:
+        assert all(e[1] <= rel_l2 for e in errs.values()), errs
+
+
+def _check_precision(sc, grad_rgb, rays, prec_name, gf, gm):
+    if prec_name == "fp32":
+        _check(gf, gm, _oracle(sc, grad_rgb, rays), 1e-4)
+    else:
+        _check(gf, gm, _oracle(sc, grad_rgb, rays, grad_bf16), 1e-3)
+        _check(gf, gm, _oracle(sc, grad_rgb, rays), None, rel_l2=0.1)
+
+
+@pytest.mark.parametrize("prec_name", ["fp32", "bf16"])
+def test_backward_sphere_plane(prec_name):
     from paper_2404_14044_amd import hashpoint as hp
     sc = scenes.sphere_plane()
     R = sc.cams[0].W * sc.cams[0].H
@@ -71,8 +96,7 @@ def test_backward_sphere_plane(prec_name, tol):
     grad_rgb = rng.normal(size=(R, 3)).astype(np.float32)
     prec = hp.HP_FP32 if prec_name == "fp32" else hp.HP_BF16
     gf, gm, _ = _gpu(sc, grad_rgb, prec)
-    ref = _oracle(sc, grad_rgb, [np.arange(R, dtype=np.int32)])
-    _check(gf, gm, ref, tol)
+    _check_precision(sc, grad_rgb, [np.arange(R, dtype=np.int32)], prec_name, gf, gm)
 
 
 def _multiview(n=200_000, res=160):
@@ -80,8 +104,8 @@ def _multiview(n=200_000, res=160):
     return scenes.diff_4x400(base=base, res=res)
 
 
-@pytest.mark.parametrize("prec_name,tol", [("fp32", 1e-4), ("bf16", 3e-2)])
-def test_backward_multiview_ray_subset(prec_name, tol):
+@pytest.mark.parametrize("prec_name", ["fp32", "bf16"])
+def test_backward_multiview_ray_subset(prec_name):
     """Four views; the gradient reaches only a random subset of rays."""
     from paper_2404_14044_amd import hashpoint as hp
     sc = _multiview()
@@ -97,8 +121,7 @@ def test_backward_multiview_ray_subset(prec_name, tol):
         base += s
     prec = hp.HP_FP32 if prec_name == "fp32" else hp.HP_BF16
     gf, gm, _ = _gpu(sc, grad_rgb, prec)
-    ref = _oracle(sc, grad_rgb, rays)
-    _check(gf, gm, ref, tol)
+    _check_precision(sc, grad_rgb, rays, prec_name, gf, gm)
 
 
 def test_backward_matches_central_differences():
@@ -133,7 +156,7 @@ def test_backward_matches_central_differences():
     worst = 0.0
     for name, ij in coords:
         base_arr = sc.feat if name == "feat" else sc.mlp[name]
-        h = 1e-3 * max(1.0, abs(float(base_arr[ij])))
+        h = 1e-5 * max(1.0, abs(float(base_arr[ij])))
         vals = []
         for sgn in (1, -1):
             arr = base_arr.astype(np.float64).copy()
