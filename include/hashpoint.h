@@ -14,11 +14,12 @@
  * near the first surface.  Sec. 3.4 decodes the kept samples with an MLP and
  * composites them by volume rendering (Eq. 2).
  *
- * The four calls below are those steps:
+ * The calls below are those steps:
  *   hp_build_table      - projection and pixel table        (Sec. 3.2, Fig. 2)
  *   hp_search_sample    - window search and sampling        (Sec. 3.2-3.3, Eq. 4-5)
  *   hp_render           - aggregation, MLP, compositing     (Sec. 3.4, Eq. 2)
  *   hp_render_backward  - gradient of the render            (Sec. 3.4, Eq. 2)
+ *   hp_render_backward_samples - the same from kept samples
  *
  * General rules
  *  - All buffers are caller-owned.  Pointers documented "device" are HIP
@@ -207,20 +208,46 @@ hp_status hp_render(const hp_samples *smp, int64_t R, const float *feat, int32_t
                     const hp_mlp *mlp, int32_t precision, const hp_params *p, float *rgb,
                     float *depth, float *acc, void *stream);
 
-/* Workspace bytes hp_render_backward needs (host only). */
+/* Workspace bytes hp_render_backward needs for this table and these
+ * parameters (host only): per-workgroup decoder-gradient slices plus the
+ * recomputed samples of all tab->n_rays rays (as hp_samples, without the
+ * optional neighbour lists). */
 size_t hp_backward_workspace(const hp_table *tab, const hp_params *p, hp_status *status);
 
-/* Gradient of L with respect to the features and MLP parameters, given
- * grad_rgb = dL/drgb (device, R x 3).  Search and sampling are recomputed
- * from the table instead of being stored; samples depend on geometry only.
- *  grad_feat (n_points x C) and every array of grad_mlp are ADDED to
- *  (zero them first for a plain gradient).  Accumulation order is not fixed,
- *  so results are reproducible to rounding only.
- * Errors: HP_E_INVALID, HP_E_WORKSPACE, HP_E_UNSUPPORTED. */
+/* Gradient of L with respect to the features and MLP parameters (Sec. 3.4,
+ * Eq. 2 differentiated through the decoder and the inverse-distance
+ * aggregation), given grad_rgb = dL/drgb (device, R x 3, R = tab->n_rays).
+ * Search and sampling are recomputed from the table into the workspace
+ * (samples depend on geometry only), then the gradient is computed as in
+ * hp_render_backward_samples.
+ *  cams, n_views, p: as given to hp_build_table; precision: the decoder
+ *      precision of the forward render (the activations are replayed in it;
+ *      the gradient itself is FP32 with FP32 weights).
+ *  grad_feat (device, n_points x C) and every array of grad_mlp (device,
+ *      FP32, shapes as hp_mlp) are ADDED to: zero them first for a plain
+ *      gradient.  Feature gradients are accumulated with atomics, so results
+ *      are reproducible to rounding only.
+ *  ws: device workspace of at least hp_backward_workspace bytes.
+ * Errors: HP_E_INVALID, HP_E_WORKSPACE, HP_E_UNSUPPORTED (C != HP_FEAT_DIM,
+ *      K > HP_MAX_K). */
 hp_status hp_render_backward(const hp_table *tab, const hp_camera *cams, int32_t n_views,
                              const float *feat, int32_t C, const hp_mlp *mlp, int32_t precision,
                              const hp_params *p, const float *grad_rgb, float *grad_feat,
                              hp_mlp *grad_mlp, void *ws, size_t ws_bytes, void *stream);
+
+/* Workspace bytes hp_render_backward_samples needs (host only). */
+size_t hp_backward_samples_workspace(const hp_params *p, hp_status *status);
+
+/* The same gradient from samples the caller kept (Sec. 3.4, Eq. 2): smp as
+ * written by hp_search_sample for R rays with these parameters (only n_sel,
+ * t, knn_idx and knn_dist are read).  Arguments otherwise as
+ * hp_render_backward; ws: at least hp_backward_samples_workspace bytes.
+ * Errors: HP_E_INVALID, HP_E_WORKSPACE, HP_E_UNSUPPORTED, HP_E_CAPACITY
+ *      (R >= 2^31). */
+hp_status hp_render_backward_samples(const hp_samples *smp, int64_t R, const float *feat,
+                                     int32_t C, const hp_mlp *mlp, int32_t precision,
+                                     const hp_params *p, const float *grad_rgb, float *grad_feat,
+                                     hp_mlp *grad_mlp, void *ws, size_t ws_bytes, void *stream);
 
 /* Status text, and the last HIP error code seen by this thread. */
 const char *hp_status_str(hp_status s);

@@ -309,11 +309,97 @@ hp_status hp_render(const hp_samples *smp, int64_t R, const float *feat, int32_t
     return e == hipSuccess ? HP_OK : hip_fail(e);
 }
 
+}  // extern "C"
+
+// Backward workspace: decoder-gradient slices, then (for the recomputing
+// entry point) the samples of every ray, each array 256-byte aligned.
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct BwdWsLayout {
+    size_t partial, n_sel, primary, n_nbr, flags, t, knn_idx, knn_dist, bytes;
+};
+
+static BwdWsLayout bwd_ws_layout(int64_t R, const hp_params &p)
+{
+    BwdWsLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += align256(bytes);
+        return at;
+    };
+    const size_t RS = (size_t)R * (size_t)p.n_samples;
+    L.partial = take(hp::backward_partial_bytes());
+    L.n_sel = take((size_t)R * 4);
+    L.primary = take((size_t)R * 4);
+    L.n_nbr = take((size_t)R * 4);
+    L.flags = take((size_t)R * 4);
+    L.t = take(RS * 4);
+    L.knn_idx = take(RS * (size_t)p.K * 4);
+    L.knn_dist = take(RS * (size_t)p.K * 4);
+    L.bytes = off;
+    return L;
+}
+
+static hp_status check_backward_args(const float *feat, int32_t C, const hp_mlp *mlp,
+                                     int32_t precision, const hp_params *p, const float *grad_rgb,
+                                     float *grad_feat, const hp_mlp *grad_mlp)
+{
+    if (!p || !valid_params(*p)) return HP_E_INVALID;
+    if (C != HP_FEAT_DIM) return HP_E_UNSUPPORTED;
+    if (p->K > HP_MAX_K) return HP_E_UNSUPPORTED;
+    if (precision != HP_FP32 && precision != HP_BF16) return HP_E_INVALID;
+    if (!feat || !mlp || !grad_rgb || !grad_feat || !grad_mlp) return HP_E_INVALID;
+    if (!mlp->W1 || !mlp->b1 || !mlp->W2 || !mlp->b2 || !mlp->W3 || !mlp->b3) return HP_E_INVALID;
+    if (!grad_mlp->W1 || !grad_mlp->b1 || !grad_mlp->W2 || !grad_mlp->b2 || !grad_mlp->W3 ||
+        !grad_mlp->b3)
+        return HP_E_INVALID;
+    return HP_OK;
+}
+
+static hp_status run_backward(const int32_t *n_sel, const float *t, const int32_t *knn_idx,
+                              const float *knn_dist, int64_t R, const float *feat,
+                              const hp_mlp *mlp, int32_t precision, const hp_params *p,
+                              const float *grad_rgb, float *grad_feat, hp_mlp *grad_mlp,
+                              float *partial, hipStream_t stream)
+{
+    hp::BwdArgs A;
+    A.n_sel = n_sel;
+    A.t = t;
+    A.knn_idx = knn_idx;
+    A.knn_dist = knn_dist;
+    A.n_rays = R;
+    A.K = p->K;
+    A.S = p->n_samples;
+    A.rpw = hp::backward_rays_per_wave(p->n_samples);
+    A.feat = feat;
+    A.w = hp::MlpWeights{mlp->W1, mlp->b1, mlp->W2, mlp->b2, mlp->W3, mlp->b3};
+    A.eps_idw = p->eps_idw;
+    A.delta_last = p->delta_last;
+    for (int i = 0; i < 3; ++i) A.bg[i] = p->bg[i];
+    A.grad_rgb = grad_rgb;
+    A.grad_feat = grad_feat;
+    A.partial = partial;
+    const hp::MlpGrad gm{grad_mlp->W1, grad_mlp->b1, grad_mlp->W2,
+                         grad_mlp->b2, grad_mlp->W3, grad_mlp->b3};
+    const hipError_t e = hp::launch_backward(A, precision, gm, stream);
+    return e == hipSuccess ? HP_OK : hip_fail(e);
+}
+
+extern "C" {
+
 size_t hp_backward_workspace(const hp_table *tab, const hp_params *p, hp_status *status)
 {
-    const hp_status st = (tab && p && valid_params(*p)) ? HP_OK : HP_E_INVALID;
+    const hp_status st = (tab && p && valid_params(*p) && tab->n_rays >= 0) ? HP_OK : HP_E_INVALID;
     if (status) *status = st;
-    return st == HP_OK ? hp::backward_workspace_bytes() : 0;
+    return st == HP_OK ? bwd_ws_layout(tab->n_rays, *p).bytes : 0;
+}
+
+size_t hp_backward_samples_workspace(const hp_params *p, hp_status *status)
+{
+    const hp_status st = (p && valid_params(*p)) ? HP_OK : HP_E_INVALID;
+    if (status) *status = st;
+    return st == HP_OK ? align256(hp::backward_partial_bytes()) : 0;
 }
 
 hp_status hp_render_backward(const hp_table *tab, const hp_camera *cams, int32_t n_views,
@@ -322,31 +408,43 @@ hp_status hp_render_backward(const hp_table *tab, const hp_camera *cams, int32_t
                              hp_mlp *grad_mlp, void *ws, size_t ws_bytes, void *stream)
 {
     hp::SearchCtx c;
-    const hp_status st = make_ctx(tab, cams, n_views, p, c);
+    hp_status st = make_ctx(tab, cams, n_views, p, c);
     if (st != HP_OK) return st;
-    if (C != HP_FEAT_DIM) return HP_E_UNSUPPORTED;
-    if (precision != HP_FP32 && precision != HP_BF16) return HP_E_INVALID;
-    if (!feat || !mlp || !grad_rgb || !grad_feat || !grad_mlp) return HP_E_INVALID;
-    if (!mlp->W1 || !mlp->b1 || !mlp->W2 || !mlp->b2 || !mlp->W3 || !mlp->b3) return HP_E_INVALID;
-    if (!grad_mlp->W1 || !grad_mlp->b1 || !grad_mlp->W2 || !grad_mlp->b2 || !grad_mlp->W3 ||
-        !grad_mlp->b3)
-        return HP_E_INVALID;
-    if (!ws || ws_bytes < hp::backward_workspace_bytes()) return HP_E_WORKSPACE;
-    hp::BwdArgs A;
-    A.c = c;
-    A.feat = feat;
-    A.w = hp::MlpWeights{mlp->W1, mlp->b1, mlp->W2, mlp->b2, mlp->W3, mlp->b3};
-    A.eps_idw = p->eps_idw;
-    A.delta_last = p->delta_last;
-    for (int i = 0; i < 3; ++i) A.bg[i] = p->bg[i];
-    A.grad_rgb = grad_rgb;
-    A.grad_feat = grad_feat;
-    A.partial = (float *)ws;
-    const hp::MlpGrad gm{grad_mlp->W1, grad_mlp->b1, grad_mlp->W2,
-                         grad_mlp->b2, grad_mlp->W3, grad_mlp->b3};
-    const hipError_t e =
-        hp::launch_backward(A, knn_template(p->K), precision, gm, (hipStream_t)stream);
-    return e == hipSuccess ? HP_OK : hip_fail(e);
+    st = check_backward_args(feat, C, mlp, precision, p, grad_rgb, grad_feat, grad_mlp);
+    if (st != HP_OK) return st;
+    const BwdWsLayout L = bwd_ws_layout(tab->n_rays, *p);
+    if (!ws || ws_bytes < L.bytes) return HP_E_WORKSPACE;
+    char *base = static_cast<char *>(ws);
+    // recompute the samples with the forward search kernel
+    hp::SampleOut o{reinterpret_cast<int32_t *>(base + L.n_sel),
+                    reinterpret_cast<int32_t *>(base + L.primary),
+                    reinterpret_cast<int32_t *>(base + L.n_nbr),
+                    reinterpret_cast<uint32_t *>(base + L.flags),
+                    reinterpret_cast<float *>(base + L.t),
+                    reinterpret_cast<int32_t *>(base + L.knn_idx),
+                    reinterpret_cast<float *>(base + L.knn_dist),
+                    nullptr,
+                    nullptr};
+    const hipError_t e = hp::launch_search_sample(c, o, knn_template(p->K), (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    return run_backward(o.n_sel, o.t, o.knn_idx, o.knn_dist, tab->n_rays, feat, mlp, precision, p,
+                        grad_rgb, grad_feat, grad_mlp, reinterpret_cast<float *>(base + L.partial),
+                        (hipStream_t)stream);
+}
+
+hp_status hp_render_backward_samples(const hp_samples *smp, int64_t R, const float *feat,
+                                     int32_t C, const hp_mlp *mlp, int32_t precision,
+                                     const hp_params *p, const float *grad_rgb, float *grad_feat,
+                                     hp_mlp *grad_mlp, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!smp || R < 0) return HP_E_INVALID;
+    const hp_status st = check_backward_args(feat, C, mlp, precision, p, grad_rgb, grad_feat, grad_mlp);
+    if (st != HP_OK) return st;
+    if (R >= ((int64_t)1 << 31)) return HP_E_CAPACITY;
+    if (R > 0 && (!smp->n_sel || !smp->t || !smp->knn_idx || !smp->knn_dist)) return HP_E_INVALID;
+    if (!ws || ws_bytes < align256(hp::backward_partial_bytes())) return HP_E_WORKSPACE;
+    return run_backward(smp->n_sel, smp->t, smp->knn_idx, smp->knn_dist, R, feat, mlp, precision, p,
+                        grad_rgb, grad_feat, grad_mlp, static_cast<float *>(ws), (hipStream_t)stream);
 }
 
 }  // extern "C"

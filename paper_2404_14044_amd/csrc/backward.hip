@@ -1,16 +1,23 @@
 // Gradient of the render (Sec. 3.4, Eq. 2) with respect to the point
-// features and the decoder parameters.
+// features and the decoder parameters, given the samples of every ray.
 //
-// One 64-lane workgroup per ray, persistent over rays like the forward search.
-// For each ray the search and the primary-surface sampling are recomputed
-// from the table (samples depend on geometry only), the decoder is replayed
-// (BF16 or FP32 on MFMA) to recover its activations, and the gradient flows
-//   compositing (sequential, FP32) -> decoder outputs
-//   decoder backward (FP32, VALU; weights FP32)   -> aggregated features
-//   inverse-distance aggregation                   -> point features (atomics)
-// Decoder-parameter gradients are accumulated per workgroup in registers and
-// written to a per-workgroup slice of the workspace; a second kernel sums the
-// slices in a fixed order into the caller's gradient arrays.
+// The samples depend on geometry only, so the caller either keeps the
+// forward pass's samples or recomputes them with the forward search kernel
+// (hp_render_backward does the latter into its workspace).  This kernel then
+// mirrors the render: one wave per chunk of consecutive rays, the chunk's
+// samples packed densely into tiles of 16.
+//   pass A   inverse-distance aggregation and decoder (BF16 or FP32 on MFMA)
+//            -> raw decoder outputs of every sample, kept in LDS;
+//   composite backward (Eq. 2), one lane per ray, FP32: the transmittance in
+//            front of each sample forward, then the suffix sums of colour and
+//            transmittance backward -> dL/d(decoder outputs), in place;
+//   pass B   per tile: the decoder is replayed keeping its activations, the
+//            gradient flows back through it on the VALU in FP32 (weights
+//            FP32) to the aggregated features, and through the aggregation
+//            to the point features with atomics.
+// Decoder-parameter gradients are summed per workgroup in LDS and written to
+// a per-workgroup slice of the workspace; a second kernel sums the slices in
+// workgroup order into the caller's gradient arrays.
 #include <type_traits>
 
 #include "hp_backward.hpp"
@@ -25,36 +32,44 @@ constexpr int OFF_W2 = OFF_B1 + HP_HIDDEN;
 constexpr int OFF_B2 = OFF_W2 + HP_HIDDEN * HP_HIDDEN;
 constexpr int OFF_W3 = OFF_B2 + HP_HIDDEN;
 constexpr int OFF_B3 = OFF_W3 + 4 * HP_HIDDEN;
-constexpr int BWD_BLOCKS = 2048;
 
-template <int KT>
-struct BwdLds {
-    SearchLds s;
-    float smp_t[HP_MAX_SAMPLES];
-    int32_t smp_idx[HP_MAX_SAMPLES][KT];
-    float smp_dist[HP_MAX_SAMPLES][KT];
-    float O[HP_MAX_SAMPLES][4];    // decoder outputs
-    float DO[HP_MAX_SAMPLES][4];   // dL/d(decoder outputs)
-    float F[16][HP_FEAT_DIM];      // tile: aggregated features
-    float H1[16][HP_HIDDEN];       // tile: layer-1 activations, then their gradients
-    float H2[16][HP_HIDDEN];       // tile: layer-2 activations, then their gradients
-    float gpar[NPAR];              // this workgroup's decoder-parameter gradients
+// Orders this wave's LDS accesses (a wave's LDS operations complete in
+// program order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wave's LDS.
+struct BwdWave {
+    float4 o[BWD_CHUNK];            // raw decoder outputs, then their gradients
+    float T[BWD_CHUNK];             // transmittance in front of each sample
+    int32_t pre[WAVE + 1];          // sample prefix over the chunk's rays
+    int64_t row[16];                // tile: sample row (ray * S + s), -1 = padding
+    float inv[16];                  // tile: 1 / sum of the inverse-distance weights
+    float F[16][HP_FEAT_DIM];       // tile: aggregated features [sample][feature]
+    float H1T[HP_HIDDEN][16];       // tile: layer-1 activations, then their gradients
+    float H2T[HP_HIDDEN][16];       // tile: layer-2 activations, then their gradients
 };
 
-// Aggregated feature slice (8 floats, features 8 q .. 8 q + 7) of sample s.
-template <int KT>
-__device__ __forceinline__ void idw_slice_lds(const BwdLds<KT> &sh, const float *feat, int K,
-                                              float eps_idw, int s, int q, float *f)
+// a tile's neighbour indices and weights fit in the layer-2 area they reuse
+static_assert(2 * 16 * HP_MAX_K <= HP_HIDDEN * 16, "neighbour staging exceeds its LDS area");
+
+// Aggregated feature slice (features 8 q .. 8 q + 7) of sample row `row`;
+// the same arithmetic as the render.
+__device__ __forceinline__ float idw_slice_bwd(const BwdArgs &A, int64_t row, int q, float *f)
 {
 #pragma unroll
     for (int e = 0; e < 8; ++e) f[e] = 0.0f;
     float wsum = 0.0f;
-    for (int k = 0; k < K; ++k) {
-        const int idx = sh.smp_idx[s][k];
+    for (int k = 0; k < A.K; ++k) {
+        const int idx = A.knn_idx[row * A.K + k];
         if (idx < 0) break;
-        const float d = sh.smp_dist[s][k];
-        const float w = 1.0f / (d > eps_idw ? d : eps_idw);
-        const float4 *src = reinterpret_cast<const float4 *>(feat + (int64_t)idx * HP_FEAT_DIM + 8 * q);
+        const float d = A.knn_dist[row * A.K + k];
+        const float w = 1.0f / (d > A.eps_idw ? d : A.eps_idw);
+        const float4 *src = reinterpret_cast<const float4 *>(A.feat + (int64_t)idx * HP_FEAT_DIM + 8 * q);
         const float4 x0 = src[0], x1 = src[1];
         f[0] = fma_rn(w, x0.x, f[0]);
         f[1] = fma_rn(w, x0.y, f[1]);
@@ -69,13 +84,32 @@ __device__ __forceinline__ void idw_slice_lds(const BwdLds<KT> &sh, const float 
     const float inv = wsum > 0.0f ? 1.0f / wsum : 0.0f;
 #pragma unroll
     for (int e = 0; e < 8; ++e) f[e] *= inv;
+    return inv;
 }
 
-template <int KT, int PREC>
-__device__ __forceinline__ void backward_body(const BwdArgs &A)
+// Chunk-local (ray, sample) of packed sample sidx: the last ray whose prefix
+// is <= sidx.
+__device__ __forceinline__ int64_t sample_row(const BwdWave &sh, const BwdArgs &A, int64_t ray0,
+                                              int nr, int sidx)
 {
-    __shared__ BwdLds<KT> sh;
-    const SearchCtx &c = A.c;
+    int lo = 0, hi = nr;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sh.pre[mid] <= sidx) lo = mid;
+        else hi = mid;
+    }
+    return (ray0 + lo) * A.S + (sidx - sh.pre[lo]);
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
+{
+    __shared__ BwdWave waves[BWD_WAVES];
+    __shared__ float gpar[NPAR];  // this workgroup's decoder-parameter gradients
+    // FP32 weights for the backward products, shared by the workgroup
+    __shared__ float sW1[HP_HIDDEN * HP_FEAT_DIM], sW2[HP_HIDDEN * HP_HIDDEN], sW3[4 * HP_HIDDEN];
+    const int wave = threadIdx.x >> 6;
+    BwdWave &sh = waves[wave];
     const int l = lane_id();
     const int r16 = l & 15, q = l >> 4;
 
@@ -84,239 +118,309 @@ __device__ __forceinline__ void backward_body(const BwdArgs &A)
         if constexpr (PREC == HP_BF16) load_mlp_bf16(A.w, m);
         else load_mlp_f32(A.w, m);
     };
-    // decoder-parameter gradients: lane l owns column l of dW2 and dW3, rows
-    // 32 (l >> 5) .. +31 of column l & 31 of dW1, and entry l of db1, db2
-    for (int i = l; i < NPAR; i += WAVE) sh.gpar[i] = 0.0f;
+    for (int i = threadIdx.x; i < NPAR; i += blockDim.x) gpar[i] = 0.0f;
+    for (int i = threadIdx.x; i < HP_HIDDEN * HP_FEAT_DIM; i += blockDim.x) sW1[i] = A.w.W1[i];
+    for (int i = threadIdx.x; i < HP_HIDDEN * HP_HIDDEN; i += blockDim.x) sW2[i] = A.w.W2[i];
+    for (int i = threadIdx.x; i < 4 * HP_HIDDEN; i += blockDim.x) sW3[i] = A.w.W3[i];
+    __syncthreads();
+    // lane l: column l of dW3, entry l of db1 and db2, entry l < 4 of db3
     float gW3[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     float gb1 = 0.0f, gb2 = 0.0f, gb3 = 0.0f;
 
-    const int64_t n_chunks = (c.n_rays + c.chunk - 1) / c.chunk;
-    for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
-        const int64_t r1 = min((ch + 1) * c.chunk, c.n_rays);
-        for (int64_t ray = ch * c.chunk; ray < r1; ++ray) {
-            const float g0 = A.grad_rgb[3 * ray], g1 = A.grad_rgb[3 * ray + 1],
-                        g2 = A.grad_rgb[3 * ray + 2];
-            if (g0 == 0.0f && g1 == 0.0f && g2 == 0.0f) continue;  // no gradient through this ray
-            const RayGeom g = ray_geometry(c, ray);
-            uint64_t top;
-            int count;
-            search_neighbours(c, g, sh.s, top, count);
-            const int m = count < c.M ? count : c.M;
-            int prim;
-            const int n = walk_candidates<KT>(
-                c, g, sh.s, top, m, prim,
-                [&](int s, int qq, float tj, const uint64_t(&kd)[KT], int kc) {
-                    if (qq == 0) sh.smp_t[s] = tj;
-#pragma unroll
-                    for (int k = 0; k < KT; ++k) {
-                        if ((k & 3) == qq) {
-                            const bool v = k < kc;
-                            sh.smp_idx[s][k] = v ? (int32_t)(uint32_t)kd[k] : -1;
-                            sh.smp_dist[s][k] =
-                                v ? __builtin_sqrtf(__uint_as_float((uint32_t)(kd[k] >> 32))) : 0.0f;
-                        }
-                    }
-                });
-            lds_sync();
-            if (n == 0) continue;
+    const int64_t n_chunks = (A.n_rays + A.rpw - 1) / A.rpw;
+    for (int64_t ch = (int64_t)blockIdx.x * BWD_WAVES + wave; ch < n_chunks;
+         ch += (int64_t)gridDim.x * BWD_WAVES) {
+        const int64_t ray0 = ch * A.rpw;
+        const int nr = (A.n_rays - ray0) < A.rpw ? (int)(A.n_rays - ray0) : A.rpw;
+        float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+        int ns = 0;
+        if (l < nr) {
+            const int64_t ray = ray0 + l;
+            g0 = A.grad_rgb[3 * ray];
+            g1 = A.grad_rgb[3 * ray + 1];
+            g2 = A.grad_rgb[3 * ray + 2];
+            // a ray without incoming gradient contributes nothing
+            if (g0 != 0.0f || g1 != 0.0f || g2 != 0.0f) ns = A.n_sel[ray];
+        }
+        const int inc = wave_incl_scan_i32(ns);
+        sh.pre[l] = inc - ns;
+        const int total = readlane_i32(inc, WAVE - 1);
+        if (l == 0) sh.pre[WAVE] = total;
+        wave_lds_sync();
+        if (total == 0) continue;
 
-            // pass A: decoder outputs of every sample
+        // pass A: raw decoder outputs of every sample (the BF16 weights stay
+        // in registers over the chunk; the larger FP32 set is reloaded per tile)
+        {
             Mlp mlp;
-            load_mlp(mlp);
-            for (int t0 = 0; t0 < n; t0 += 16) {
-                const int s = t0 + r16;
+            if constexpr (PREC == HP_BF16) load_mlp(mlp);
+            for (int s0 = 0; s0 < total; s0 += 16) {
+                const int sidx = s0 + r16;
                 float f[8];
-                if (s < n) idw_slice_lds(sh, A.feat, c.K, A.eps_idw, s, q, f);
+                if (sidx < total) idw_slice_bwd(A, sample_row(sh, A, ray0, nr, sidx), q, f);
                 else
 #pragma unroll
                     for (int e = 0; e < 8; ++e) f[e] = 0.0f;
                 f32x4 o;
-                if constexpr (PREC == HP_BF16) o = decode_bf16(mlp, f);
-                else o = decode_f32(mlp, f);
-                if (q == 0 && s < n) {
-                    sh.O[s][0] = o[0];
-                    sh.O[s][1] = o[1];
-                    sh.O[s][2] = o[2];
-                    sh.O[s][3] = o[3];
+                if constexpr (PREC == HP_BF16) {
+                    o = decode_bf16(mlp, f);
+                } else {
+                    __asm__ volatile("" ::: "memory");
+                    load_mlp(mlp);
+                    o = decode_f32(mlp, f);
                 }
+                if (q == 0 && sidx < total) sh.o[sidx] = make_float4(o[0], o[1], o[2], o[3]);
             }
-            lds_sync();
+        }
+        wave_lds_sync();
 
-            // compositing backward (Eq. 2), sequential in sample order
-            if (l == 0) {
-                float T = 1.0f;
-                float *Ts = &sh.F[0][0];  // scratch until pass B
-                for (int j = 0; j < n; ++j) {
-                    Ts[j] = T;
-                    const float sg = softplus_f(sh.O[j][3]);
-                    const float dl = (j + 1 < n) ? sh.smp_t[j + 1] - sh.smp_t[j] : A.delta_last;
-                    T *= expf(-sg * dl);
-                }
-                float U0 = 0.0f, U1 = 0.0f, U2 = 0.0f, P = 1.0f;
-                for (int j = n - 1; j >= 0; --j) {
-                    const float c0 = sigmoid_f(sh.O[j][0]), c1 = sigmoid_f(sh.O[j][1]),
-                                c2 = sigmoid_f(sh.O[j][2]);
-                    const float sg = softplus_f(sh.O[j][3]);
-                    const float dl = (j + 1 < n) ? sh.smp_t[j + 1] - sh.smp_t[j] : A.delta_last;
-                    const float e = expf(-sg * dl);
-                    const float a = 1.0f - e;
-                    const float Tj = Ts[j];
-                    const float dLda = g0 * (Tj * (c0 - U0) - A.bg[0] * Tj * P) +
-                                       g1 * (Tj * (c1 - U1) - A.bg[1] * Tj * P) +
-                                       g2 * (Tj * (c2 - U2) - A.bg[2] * Tj * P);
-                    const float ws = Tj * a;
-                    sh.DO[j][0] = g0 * ws * c0 * (1.0f - c0);
-                    sh.DO[j][1] = g1 * ws * c1 * (1.0f - c1);
-                    sh.DO[j][2] = g2 * ws * c2 * (1.0f - c2);
-                    sh.DO[j][3] = dLda * dl * e * sigmoid_f(sh.O[j][3]);
-                    U0 = a * c0 + e * U0;
-                    U1 = a * c1 + e * U1;
-                    U2 = a * c2 + e * U2;
-                    P = e * P;
-                }
+        // compositing backward (Eq. 2): lane r walks ray r of the chunk
+        if (ns > 0) {
+            const int64_t ray = ray0 + l;
+            const int base = sh.pre[l];
+            const float *tr = A.t + ray * A.S;
+            float T = 1.0f;
+            for (int j = 0; j < ns; ++j) {
+                sh.T[base + j] = T;
+                const float sg = softplus_f(sh.o[base + j].w);
+                const float dl = (j + 1 < ns) ? tr[j + 1] - tr[j] : A.delta_last;
+                T *= expf(-sg * dl);
             }
-            lds_sync();
+            // U: colour composited behind sample j relative to T_{j+1};
+            // P: transmittance through everything behind j (background weight)
+            float U0 = 0.0f, U1 = 0.0f, U2 = 0.0f, P = 1.0f;
+            for (int j = ns - 1; j >= 0; --j) {
+                const float4 o = sh.o[base + j];
+                const float c0 = sigmoid_f(o.x), c1 = sigmoid_f(o.y), c2 = sigmoid_f(o.z);
+                const float sg = softplus_f(o.w);
+                const float dl = (j + 1 < ns) ? tr[j + 1] - tr[j] : A.delta_last;
+                const float e = expf(-sg * dl);
+                const float a = 1.0f - e;
+                const float Tj = sh.T[base + j];
+                const float dLda = g0 * (Tj * (c0 - U0) - A.bg[0] * Tj * P) +
+                                   g1 * (Tj * (c1 - U1) - A.bg[1] * Tj * P) +
+                                   g2 * (Tj * (c2 - U2) - A.bg[2] * Tj * P);
+                const float ws = Tj * a;
+                sh.o[base + j] = make_float4(g0 * ws * c0 * (1.0f - c0), g1 * ws * c1 * (1.0f - c1),
+                                             g2 * ws * c2 * (1.0f - c2), dLda * dl * e * sigmoid_f(o.w));
+                U0 = a * c0 + e * U0;
+                U1 = a * c1 + e * U1;
+                U2 = a * c2 + e * U2;
+                P = e * P;
+            }
+        }
+        wave_lds_sync();
 
-            // pass B: per tile, replay the decoder keeping activations, then backward
-            for (int t0 = 0; t0 < n; t0 += 16) {
-                const int nt = min(16, n - t0);
-                {
-                    const int s = t0 + r16;
-                    float f[8];
-                    if (s < n) idw_slice_lds(sh, A.feat, c.K, A.eps_idw, s, q, f);
-                    else
+        // pass B: per tile, replay the decoder keeping activations, then backward.
+        // Activations are stored unit-major (H?T[unit][sample]) so that a row
+        // of 16 samples is four 16-byte LDS reads; padding samples are zero.
+        for (int s0 = 0; s0 < total; s0 += 16) {
+            const int nt = (total - s0) < 16 ? total - s0 : 16;
+            {
+                const int sidx = s0 + r16;
+                const bool valid = sidx < total;
+                float f[8];
+                int64_t row = -1;
+                float inv = 0.0f;
+                if (valid) {
+                    row = sample_row(sh, A, ray0, nr, sidx);
+                    inv = idw_slice_bwd(A, row, q, f);
+                } else {
 #pragma unroll
-                        for (int e = 0; e < 8; ++e) f[e] = 0.0f;
-                    f32x4 h1[4], h2[4];
-                    Mlp mlp2;
-                    load_mlp(mlp2);
-                    if constexpr (PREC == HP_BF16) decode_bf16(mlp2, f, h1, h2);
-                    else decode_f32(mlp2, f, h1, h2);
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) sh.F[r16][8 * q + e] = f[e];
-#pragma unroll
-                    for (int ob = 0; ob < 4; ++ob)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            sh.H1[r16][16 * ob + 4 * q + e] = h1[ob][e];
-                            sh.H2[r16][16 * ob + 4 * q + e] = h2[ob][e];
-                        }
+                    for (int e = 0; e < 8; ++e) f[e] = 0.0f;
                 }
-                lds_sync();
-                // output layer: lane l is hidden unit l of layer 2
-                {
-                    const float w30 = A.w.W3[0 * HP_HIDDEN + l], w31 = A.w.W3[1 * HP_HIDDEN + l],
-                                w32 = A.w.W3[2 * HP_HIDDEN + l], w33 = A.w.W3[3 * HP_HIDDEN + l];
-                    for (int s = 0; s < nt; ++s) {
-                        const float d0 = sh.DO[t0 + s][0], d1 = sh.DO[t0 + s][1],
-                                    d2 = sh.DO[t0 + s][2], d3 = sh.DO[t0 + s][3];
-                        const float h = sh.H2[s][l];
-                        gW3[0] = fma_rn(d0, h, gW3[0]);
-                        gW3[1] = fma_rn(d1, h, gW3[1]);
-                        gW3[2] = fma_rn(d2, h, gW3[2]);
-                        gW3[3] = fma_rn(d3, h, gW3[3]);
-                        float dp = w30 * d0;
-                        dp = fma_rn(w31, d1, dp);
-                        dp = fma_rn(w32, d2, dp);
-                        dp = fma_rn(w33, d3, dp);
-                        const float dh = h > 0.0f ? dp : 0.0f;
-                        sh.H2[s][l] = dh;  // activation no longer needed
-                        gb2 += dh;
-                        if (l < 4) gb3 += sh.DO[t0 + s][l];
-                    }
+                f32x4 h1[4], h2[4];
+                Mlp mlp;
+                // reload the weights here (cache hits) rather than keep them
+                // live across the whole backward
+                __asm__ volatile("" ::: "memory");
+                load_mlp(mlp);
+                if constexpr (PREC == HP_BF16) decode_bf16(mlp, f, h1, h2);
+                else decode_f32(mlp, f, h1, h2);
+                if (q == 0) {
+                    sh.row[r16] = row;
+                    sh.inv[r16] = inv;
                 }
-                lds_sync();
-                // hidden layer 2 -> 1: lane l is hidden unit l of layer 1
-                {
-                    float acc[16];
-                    float h1v[16];
 #pragma unroll
-                    for (int s = 0; s < 16; ++s) {
-                        acc[s] = 0.0f;
-                        h1v[s] = (s < nt) ? sh.H1[s][l] : 0.0f;
+                for (int e = 0; e < 8; ++e) sh.F[r16][8 * q + e] = f[e];
+#pragma unroll
+                for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        sh.H1T[16 * ob + 4 * q + e][r16] = valid ? h1[ob][e] : 0.0f;
+                        sh.H2T[16 * ob + 4 * q + e][r16] = valid ? h2[ob][e] : 0.0f;
                     }
-#pragma unroll 4
-                    for (int o2 = 0; o2 < HP_HIDDEN; ++o2) {
-                        const float w = A.w.W2[o2 * HP_HIDDEN + l];
-                        float gw = 0.0f;
-#pragma unroll
-                        for (int s = 0; s < 16; ++s) {
-                            const float d = (s < nt) ? sh.H2[s][o2] : 0.0f;
-                            acc[s] = fma_rn(w, d, acc[s]);
-                            gw = fma_rn(d, h1v[s], gw);
-                        }
-                        sh.gpar[OFF_W2 + o2 * HP_HIDDEN + l] += gw;
-                    }
-#pragma unroll
-                    for (int s = 0; s < 16; ++s) {
-                        const float dh = (s < nt && h1v[s] > 0.0f) ? acc[s] : 0.0f;
-                        if (s < nt) sh.H1[s][l] = dh;
-                        gb1 += dh;
-                    }
-                }
-                lds_sync();
-                // layer 1 -> aggregated features, and dW1
-                {
-                    const int cc = l & 31, half = l >> 5;
-                    float df[8];
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) df[i] = 0.0f;
-#pragma unroll 4
-                    for (int i = 0; i < HP_HIDDEN; ++i) {
-                        const float w = A.w.W1[i * HP_FEAT_DIM + cc];
-#pragma unroll
-                        for (int si = 0; si < 8; ++si) {
-                            const int s = 8 * half + si;
-                            df[si] = fma_rn(w, (s < nt) ? sh.H1[s][i] : 0.0f, df[si]);
-                        }
-                    }
-#pragma unroll
-                    for (int i = 0; i < 32; ++i) {
-                        float gw = 0.0f;
-                        for (int s = 0; s < nt; ++s) gw = fma_rn(sh.H1[s][32 * half + i], sh.F[s][cc], gw);
-                        sh.gpar[OFF_W1 + (32 * half + i) * HP_FEAT_DIM + cc] += gw;
-                    }
-                    // aggregation backward: d feat[idx_k][cc] += (w_k / sum w) df
-#pragma unroll
-                    for (int si = 0; si < 8; ++si) {
-                        const int s = 8 * half + si;
-                        if (s >= nt) break;
-                        float wsum = 0.0f;
-                        for (int k = 0; k < c.K; ++k) {
-                            if (sh.smp_idx[t0 + s][k] < 0) break;
-                            const float d = sh.smp_dist[t0 + s][k];
-                            wsum += 1.0f / (d > A.eps_idw ? d : A.eps_idw);
-                        }
-                        const float inv = 1.0f / wsum;
-                        for (int k = 0; k < c.K; ++k) {
-                            const int idx = sh.smp_idx[t0 + s][k];
-                            if (idx < 0) break;
-                            const float d = sh.smp_dist[t0 + s][k];
-                            const float wk = (1.0f / (d > A.eps_idw ? d : A.eps_idw)) * inv;
-                            atomicAdd(&A.grad_feat[(int64_t)idx * HP_FEAT_DIM + cc], wk * df[si]);
-                        }
-                    }
-                }
-                lds_sync();
             }
+            wave_lds_sync();
+            // output layer: lane l is hidden unit l of layer 2
+            {
+                const float w30 = sW3[0 * HP_HIDDEN + l], w31 = sW3[1 * HP_HIDDEN + l],
+                            w32 = sW3[2 * HP_HIDDEN + l], w33 = sW3[3 * HP_HIDDEN + l];
+                for (int s = 0; s < nt; ++s) {
+                    const float4 d = sh.o[s0 + s];
+                    const float h = sh.H2T[l][s];
+                    gW3[0] = fma_rn(d.x, h, gW3[0]);
+                    gW3[1] = fma_rn(d.y, h, gW3[1]);
+                    gW3[2] = fma_rn(d.z, h, gW3[2]);
+                    gW3[3] = fma_rn(d.w, h, gW3[3]);
+                    float dp = w30 * d.x;
+                    dp = fma_rn(w31, d.y, dp);
+                    dp = fma_rn(w32, d.z, dp);
+                    dp = fma_rn(w33, d.w, dp);
+                    const float dh = h > 0.0f ? dp : 0.0f;
+                    sh.H2T[l][s] = dh;  // activation no longer needed
+                    gb2 += dh;
+                    if (l < 4) gb3 += (l == 0) ? d.x : (l == 1) ? d.y : (l == 2) ? d.z : d.w;
+                }
+            }
+            wave_lds_sync();
+            // hidden layer 2 -> 1: lane l is hidden unit l of layer 1
+            {
+                float acc[16], h1v[16];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float4 v = *reinterpret_cast<const float4 *>(&sh.H1T[l][4 * k]);
+                    h1v[4 * k] = v.x;
+                    h1v[4 * k + 1] = v.y;
+                    h1v[4 * k + 2] = v.z;
+                    h1v[4 * k + 3] = v.w;
+                }
+#pragma unroll
+                for (int s = 0; s < 16; ++s) acc[s] = 0.0f;
+#pragma unroll 4
+                for (int o2 = 0; o2 < HP_HIDDEN; ++o2) {
+                    const float w = sW2[o2 * HP_HIDDEN + l];
+                    float gw = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float4 d = *reinterpret_cast<const float4 *>(&sh.H2T[o2][4 * k]);
+                        acc[4 * k] = fma_rn(w, d.x, acc[4 * k]);
+                        acc[4 * k + 1] = fma_rn(w, d.y, acc[4 * k + 1]);
+                        acc[4 * k + 2] = fma_rn(w, d.z, acc[4 * k + 2]);
+                        acc[4 * k + 3] = fma_rn(w, d.w, acc[4 * k + 3]);
+                        gw = fma_rn(d.x, h1v[4 * k], gw);
+                        gw = fma_rn(d.y, h1v[4 * k + 1], gw);
+                        gw = fma_rn(d.z, h1v[4 * k + 2], gw);
+                        gw = fma_rn(d.w, h1v[4 * k + 3], gw);
+                    }
+                    atomicAdd(&gpar[OFF_W2 + o2 * HP_HIDDEN + l], gw);
+                }
+                float4 *dst = reinterpret_cast<float4 *>(&sh.H1T[l][0]);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    float4 v;
+                    v.x = h1v[4 * k] > 0.0f ? acc[4 * k] : 0.0f;
+                    v.y = h1v[4 * k + 1] > 0.0f ? acc[4 * k + 1] : 0.0f;
+                    v.z = h1v[4 * k + 2] > 0.0f ? acc[4 * k + 2] : 0.0f;
+                    v.w = h1v[4 * k + 3] > 0.0f ? acc[4 * k + 3] : 0.0f;
+                    gb1 += v.x;
+                    gb1 += v.y;
+                    gb1 += v.z;
+                    gb1 += v.w;
+                    dst[k] = v;
+                }
+            }
+            wave_lds_sync();
+            // the tile's neighbour lists, fetched now (all loads independent,
+            // in flight during the layer-1 products) and staged in LDS after them
+            // lane (r16, q): entries q, q + 4, ... of sample r16
+            constexpr int PF = HP_MAX_K / 4;
+            int32_t pf_i[PF];
+            float pf_d[PF];
+            {
+                const int64_t prow = sh.row[r16];
+#pragma unroll
+                for (int m = 0; m < PF; ++m) {
+                    const int k = q + 4 * m;
+                    pf_i[m] = -1;
+                    pf_d[m] = 0.0f;
+                    if (prow >= 0 && k < A.K) {
+                        pf_i[m] = A.knn_idx[prow * A.K + k];
+                        pf_d[m] = A.knn_dist[prow * A.K + k];
+                    }
+                }
+            }
+            // layer 1 -> aggregated features, and dW1: lane l is feature l & 31
+            // of samples 8 (l >> 5) .. +7
+            {
+                const int cc = l & 31, half = l >> 5;
+                float df[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) df[i] = 0.0f;
+#pragma unroll 4
+                for (int i = 0; i < HP_HIDDEN; ++i) {
+                    const float w = sW1[i * HP_FEAT_DIM + cc];
+                    const float4 d0 = *reinterpret_cast<const float4 *>(&sh.H1T[i][8 * half]);
+                    const float4 d1 = *reinterpret_cast<const float4 *>(&sh.H1T[i][8 * half + 4]);
+                    df[0] = fma_rn(w, d0.x, df[0]);
+                    df[1] = fma_rn(w, d0.y, df[1]);
+                    df[2] = fma_rn(w, d0.z, df[2]);
+                    df[3] = fma_rn(w, d0.w, df[3]);
+                    df[4] = fma_rn(w, d1.x, df[4]);
+                    df[5] = fma_rn(w, d1.y, df[5]);
+                    df[6] = fma_rn(w, d1.z, df[6]);
+                    df[7] = fma_rn(w, d1.w, df[7]);
+                }
+                // dW1[i][cc] for i = 32 half .. +31: sum over the tile's samples
+                float fv[16];
+#pragma unroll
+                for (int s = 0; s < 16; ++s) fv[s] = sh.F[s][cc];
+#pragma unroll 4
+                for (int i = 32 * half; i < 32 * half + 32; ++i) {
+                    float gw = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float4 d = *reinterpret_cast<const float4 *>(&sh.H1T[i][4 * k]);
+                        gw = fma_rn(d.x, fv[4 * k], gw);
+                        gw = fma_rn(d.y, fv[4 * k + 1], gw);
+                        gw = fma_rn(d.z, fv[4 * k + 2], gw);
+                        gw = fma_rn(d.w, fv[4 * k + 3], gw);
+                    }
+                    atomicAdd(&gpar[OFF_W1 + i * HP_FEAT_DIM + cc], gw);
+                }
+                // stage (index, normalised weight) of every neighbour of the tile
+                // in the layer-2 gradient area, now dead: [sample][K] each
+                int32_t *const s_idx = reinterpret_cast<int32_t *>(&sh.H2T[0][0]);
+                float *const s_w = &sh.H2T[0][0] + 16 * HP_MAX_K;
+                {
+                    const float pinv = sh.inv[r16];
+#pragma unroll
+                    for (int m = 0; m < PF; ++m) {
+                        const int k = q + 4 * m;
+                        if (k < A.K) {
+                            const float d = pf_d[m];
+                            s_idx[r16 * A.K + k] = pf_i[m];
+                            s_w[r16 * A.K + k] =
+                                pf_i[m] >= 0 ? (1.0f / (d > A.eps_idw ? d : A.eps_idw)) * pinv : 0.0f;
+                        }
+                    }
+                }
+                wave_lds_sync();
+                // aggregation backward: d feat[idx_k][cc] += (w_k / sum w) df
+#pragma unroll
+                for (int si = 0; si < 8; ++si) {
+                    const int s = 8 * half + si;
+                    if (s >= nt) break;
+                    for (int k = 0; k < A.K; ++k) {
+                        const int idx = s_idx[s * A.K + k];
+                        if (idx < 0) break;
+                        atomicAdd(&A.grad_feat[(int64_t)idx * HP_FEAT_DIM + cc], s_w[s * A.K + k] * df[si]);
+                    }
+                }
+            }
+            wave_lds_sync();
         }
     }
 
     // this workgroup's parameter gradients -> its workspace slice
 #pragma unroll
-    for (int k = 0; k < 4; ++k) sh.gpar[OFF_W3 + k * HP_HIDDEN + l] = gW3[k];
-    sh.gpar[OFF_B1 + l] = gb1;
-    sh.gpar[OFF_B2 + l] = gb2;
-    if (l < 4) sh.gpar[OFF_B3 + l] = gb3;
-    lds_sync();
+    for (int k = 0; k < 4; ++k) atomicAdd(&gpar[OFF_W3 + k * HP_HIDDEN + l], gW3[k]);
+    atomicAdd(&gpar[OFF_B1 + l], gb1);
+    atomicAdd(&gpar[OFF_B2 + l], gb2);
+    if (l < 4) atomicAdd(&gpar[OFF_B3 + l], gb3);
+    __syncthreads();
     float *P = A.partial + (int64_t)blockIdx.x * NPAR;
-    for (int i = l; i < NPAR; i += WAVE) P[i] = sh.gpar[i];
-}
-
-template <int KT, int PREC>
-__global__ void __launch_bounds__(WAVE) k_render_backward(BwdArgs A)
-{
-    backward_body<KT, PREC>(A);
+    for (int i = threadIdx.x; i < NPAR; i += blockDim.x) P[i] = gpar[i];
 }
 
 // Sum the per-workgroup slices in workgroup order and add to the gradients.
@@ -339,26 +443,31 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const float *__restrict
     dst[j] += s;
 }
 
-size_t backward_workspace_bytes() { return (size_t)BWD_BLOCKS * NPAR * sizeof(float); }
+size_t backward_partial_bytes() { return (size_t)BWD_MAX_BLOCKS * NPAR * sizeof(float); }
 
-hipError_t launch_backward(const BwdArgs &A, int kt, int precision, const MlpGrad &gm, hipStream_t s)
+int backward_rays_per_wave(int S)
 {
-    const int64_t chunks = (A.c.n_rays + A.c.chunk - 1) / A.c.chunk;
-    const int nblk = (int)(chunks < BWD_BLOCKS ? (chunks > 0 ? chunks : 1) : BWD_BLOCKS);
-    const dim3 grid(nblk), block(WAVE);
-#define HP_BWD(KTV)                                                                 \
-    do {                                                                            \
-        if (precision == HP_BF16) k_render_backward<KTV, HP_BF16><<<grid, block, 0, s>>>(A); \
-        else k_render_backward<KTV, HP_FP32><<<grid, block, 0, s>>>(A);             \
-    } while (0)
-    switch (kt) {
-    case 4: HP_BWD(4); break;
-    case 8: HP_BWD(8); break;
-    case 16: HP_BWD(16); break;
-    default: HP_BWD(32); break;
-    }
-#undef HP_BWD
-    k_reduce_partials<<<(NPAR + 255) / 256, 256, 0, s>>>(A.partial, nblk, gm.W1, gm.b1, gm.W2,
+    const int r = BWD_CHUNK / (S > 0 ? S : 1);
+    return r > WAVE ? WAVE : r;
+}
+
+hipError_t launch_backward(const BwdArgs &A, int precision, const MlpGrad &gm, hipStream_t s)
+{
+    if (A.n_rays == 0) return hipSuccess;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t chunks = (A.n_rays + A.rpw - 1) / A.rpw;
+    int64_t nblk = (chunks + BWD_WAVES - 1) / BWD_WAVES;
+    // one workgroup fills a CU's LDS: a persistent grid of one per CU
+    if (nblk > cus) nblk = cus;
+    if (nblk > BWD_MAX_BLOCKS) nblk = BWD_MAX_BLOCKS;
+    if (nblk < 1) nblk = 1;
+    if (precision == HP_BF16)
+        k_render_backward<HP_BF16><<<dim3((unsigned)nblk), dim3(WAVE * BWD_WAVES), 0, s>>>(A);
+    else
+        k_render_backward<HP_FP32><<<dim3((unsigned)nblk), dim3(WAVE * BWD_WAVES), 0, s>>>(A);
+    k_reduce_partials<<<(NPAR + 255) / 256, 256, 0, s>>>(A.partial, (int)nblk, gm.W1, gm.b1, gm.W2,
                                                         gm.b2, gm.W3, gm.b3);
     return hipGetLastError();
 }

@@ -3,16 +3,24 @@
 
 #include "hp_kernels.hpp"
 #include "hp_mlp.hpp"
-#include "hp_search.hpp"
 
 namespace hp {
+
+constexpr int BWD_WAVES = 8;          // waves per workgroup (one workgroup per CU)
+constexpr int BWD_CHUNK = 128;        // samples one wave holds at once
+constexpr int BWD_MAX_BLOCKS = 1024;  // bound on the persistent grid (partial slices)
 
 struct MlpGrad {
     float *W1, *b1, *W2, *b2, *W3, *b3;
 };
 
 struct BwdArgs {
-    SearchCtx c;
+    const int32_t *n_sel;
+    const float *t;
+    const int32_t *knn_idx;
+    const float *knn_dist;
+    int64_t n_rays;
+    int32_t K, S, rpw;  // rpw: rays per wave chunk, rpw * S <= BWD_CHUNK
     const float *feat;
     MlpWeights w;
     float eps_idw, delta_last;
@@ -22,7 +30,8 @@ struct BwdArgs {
     float *partial;  // per-workgroup decoder-gradient slices
 };
 
-size_t backward_workspace_bytes();
-hipError_t launch_backward(const BwdArgs &A, int kt, int precision, const MlpGrad &gm, hipStream_t s);
+size_t backward_partial_bytes();
+int backward_rays_per_wave(int S);
+hipError_t launch_backward(const BwdArgs &A, int precision, const MlpGrad &gm, hipStream_t s);
 
 }  // namespace hp

@@ -75,7 +75,15 @@ struct RayGeom {
     float dx, dy, dz, a, b, L, wn;
 };
 
-__device__ __forceinline__ void lds_sync() { __syncthreads(); }
+// Orders this wave's LDS accesses.  A wave's LDS operations execute in program
+// order, so a compiler barrier is enough: lanes then see each other's writes.
+// (No workgroup barrier: several independent waves may share a workgroup.)
+__device__ __forceinline__ void lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // ---------------------------------------------------------------------------
 // cross-lane exchange: lane l receives lane l ^ j's value.  DPP for j < 16

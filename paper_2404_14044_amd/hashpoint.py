@@ -23,7 +23,8 @@ FEAT_DIM = 32
 HIDDEN = 64
 
 EXPORTED = ["hp_table_workspace", "hp_view_bounds", "hp_build_table", "hp_search_sample",
-            "hp_render", "hp_backward_workspace", "hp_render_backward", "hp_status_str",
+            "hp_render", "hp_backward_workspace", "hp_render_backward",
+            "hp_backward_samples_workspace", "hp_render_backward_samples", "hp_status_str",
             "hp_last_hip_error"]
 
 
@@ -102,6 +103,10 @@ def lib():
         L.hp_backward_workspace.argtypes = [P, P, P]
         L.hp_render_backward.restype = i32
         L.hp_render_backward.argtypes = [P, P, i32, P, i32, P, i32, P, P, P, P, P, ctypes.c_size_t, P]
+        L.hp_backward_samples_workspace.restype = ctypes.c_size_t
+        L.hp_backward_samples_workspace.argtypes = [P, P]
+        L.hp_render_backward_samples.restype = i32
+        L.hp_render_backward_samples.argtypes = [P, i64, P, i32, P, i32, P, P, P, P, P, ctypes.c_size_t, P]
         L.hp_status_str.restype = ctypes.c_char_p
         L.hp_status_str.argtypes = [i32]
         L.hp_last_hip_error.restype = i32
@@ -328,20 +333,58 @@ def render_backward(table: Table, feat: torch.Tensor, mlp: Dict[str, torch.Tenso
     return grad_feat, grad_mlp
 
 
+def backward_samples_workspace(params) -> int:
+    st = ctypes.c_int32()
+    p = make_params(params)
+    n = lib().hp_backward_samples_workspace(ctypes.byref(p), ctypes.byref(st))
+    _check(st.value, "hp_backward_samples_workspace")
+    return int(n)
+
+
+def render_backward_samples(samples: Dict[str, torch.Tensor], n_rays: int, feat: torch.Tensor,
+                            mlp: Dict[str, torch.Tensor], params, precision: int,
+                            grad_rgb: torch.Tensor, grad_feat: Optional[torch.Tensor] = None,
+                            grad_mlp: Optional[Dict[str, torch.Tensor]] = None,
+                            ws: Optional[torch.Tensor] = None, stream=None):
+    """render_backward from kept samples (as written by search_sample)."""
+    dev = feat.device
+    if grad_feat is None:
+        grad_feat = torch.zeros_like(feat)
+    if grad_mlp is None:
+        grad_mlp = {k: torch.zeros_like(v) for k, v in mlp.items()}
+    need = backward_samples_workspace(params)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    st, p = _samples_struct(samples), make_params(params)
+    m, gm = mlp_struct(mlp), mlp_struct(grad_mlp)
+    _check(lib().hp_render_backward_samples(ctypes.byref(st), int(n_rays),
+                                            _dev(feat, torch.float32, "feat"), int(feat.shape[1]),
+                                            ctypes.byref(m), int(precision), ctypes.byref(p),
+                                            _dev(grad_rgb, torch.float32, "grad_rgb"),
+                                            _dev(grad_feat, torch.float32, "grad_feat"),
+                                            ctypes.byref(gm), ws.data_ptr(), ws.numel(),
+                                            _stream(stream)),
+           "hp_render_backward_samples")
+    return grad_feat, grad_mlp
+
+
 _MLP_KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")
 
 
 class HashPointRender(torch.autograd.Function):
     """rgb = render(search_sample(table), feat, mlp) with a hand-written backward.
 
-    The forward keeps no sample lists: the backward recomputes the search and
-    sampling from the table (they depend on geometry only)."""
+    By default the forward keeps no sample lists and the backward recomputes
+    the search and sampling from the table (they depend on geometry only);
+    with keep_samples=True the forward's samples are kept for the backward
+    instead (more memory, no second search)."""
 
     @staticmethod
-    def forward(ctx, feat, W1, b1, W2, b2, W3, b3, table, params, precision):
+    def forward(ctx, feat, W1, b1, W2, b2, W3, b3, table, params, precision, keep_samples=False):
         mlp = dict(zip(_MLP_KEYS, (W1, b1, W2, b2, W3, b3)))
         smp = search_sample(table, params)
         out = render(smp, table.n_rays, feat, mlp, params, precision)
+        ctx.samples = smp if keep_samples else None
         del smp
         ctx.table, ctx.params, ctx.precision = table, params, precision
         ctx.save_for_backward(feat, W1, b1, W2, b2, W3, b3)
@@ -351,6 +394,12 @@ class HashPointRender(torch.autograd.Function):
     def backward(ctx, grad_rgb):
         feat, W1, b1, W2, b2, W3, b3 = ctx.saved_tensors
         mlp = dict(zip(_MLP_KEYS, (W1, b1, W2, b2, W3, b3)))
-        gf, gm = render_backward(ctx.table, feat, mlp, ctx.params, ctx.precision,
-                                 grad_rgb.contiguous().float())
-        return (gf, gm["W1"], gm["b1"], gm["W2"], gm["b2"], gm["W3"], gm["b3"], None, None, None)
+        g = grad_rgb.contiguous().float()
+        if ctx.samples is not None:
+            gf, gm = render_backward_samples(ctx.samples, ctx.table.n_rays, feat, mlp, ctx.params,
+                                             ctx.precision, g)
+            ctx.samples = None
+        else:
+            gf, gm = render_backward(ctx.table, feat, mlp, ctx.params, ctx.precision, g)
+        return (gf, gm["W1"], gm["b1"], gm["W2"], gm["b2"], gm["W3"], gm["b3"], None, None, None,
+                None)

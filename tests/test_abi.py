@@ -124,3 +124,45 @@ def test_search_and_render_reject_bad_arguments_without_launching():
     # backward with a null table
     assert L.hp_render_backward(None, arr, 1, fake, 32, ctypes.byref(mlp), 0, ctypes.byref(pp), fake, fake,
                                 ctypes.byref(mlp), fake, 1 << 30, None) == hp.HP_E_INVALID
+
+
+def test_backward_from_samples_rejects_bad_arguments_without_launching():
+    sc = scenes.sphere_plane(n_sphere=10, n_plane=10)
+    L = hp.lib()
+    pp = hp.make_params(sc.params)
+    fake = ctypes.c_void_p(0x1000)
+    smp = hp.HPSamples()
+    mlp = hp.HPMlp()
+    for name, _ in hp.HPMlp._fields_:
+        setattr(mlp, name, 0x1000)
+    need = hp.backward_samples_workspace(sc.params)
+    assert need > 0
+    args = lambda s, R, C, prec, ws_bytes: (ctypes.byref(s) if s is not None else None, R, fake, C,
+                                            ctypes.byref(mlp), prec, ctypes.byref(pp), fake, fake,
+                                            ctypes.byref(mlp), fake, ws_bytes, None)
+    # null sample arrays with rays to process
+    assert L.hp_render_backward_samples(*args(smp, 10, 32, 0, need)) == hp.HP_E_INVALID
+    assert L.hp_render_backward_samples(*args(None, 10, 32, 0, need)) == hp.HP_E_INVALID
+    for name, _ in hp.HPSamples._fields_:
+        setattr(smp, name, 0x1000)
+    assert L.hp_render_backward_samples(*args(smp, 10, 16, 0, need)) == hp.HP_E_UNSUPPORTED
+    assert L.hp_render_backward_samples(*args(smp, 10, 32, 5, need)) == hp.HP_E_INVALID
+    assert L.hp_render_backward_samples(*args(smp, 10, 32, 0, need - 1)) == hp.HP_E_WORKSPACE
+    assert L.hp_render_backward_samples(*args(smp, 1 << 31, 32, 0, need)) == hp.HP_E_CAPACITY
+    assert L.hp_render_backward_samples(*args(smp, -1, 32, 0, need)) == hp.HP_E_INVALID
+
+
+def test_backward_workspace_holds_the_recomputed_samples():
+    sc = scenes.sphere_plane(n_sphere=10, n_plane=10)
+    part = hp.backward_samples_workspace(sc.params)
+    st = ctypes.c_int32()
+    tab = hp.HPTable()
+    p = sc.params
+    for R in (0, 1, 4096):
+        tab.n_rays = R
+        n = hp.lib().hp_backward_workspace(ctypes.byref(tab), ctypes.byref(hp.make_params(p)),
+                                           ctypes.byref(st))
+        assert st.value == hp.HP_OK
+        S, K = p.n_samples, p.K
+        assert n >= part + R * (4 * 4 + S * 4 + 2 * S * K * 4)
+        assert n <= part + R * (4 * 4 + S * 4 + 2 * S * K * 4) + 8 * 256

@@ -99,6 +99,21 @@ def test_backward_sphere_plane(prec_name):
     _check_precision(sc, grad_rgb, [np.arange(R, dtype=np.int32)], prec_name, gf, gm)
 
 
+@pytest.mark.parametrize("S,K", [(3, 4), (24, 16), (64, 32)])
+def test_backward_sample_caps_and_widths(S, K):
+    """Sample caps that change the rays per wave chunk (S = 64 -> 4 rays,
+    S = 3 -> 64 rays, S = 24 -> a ragged 10) and every neighbour-list width,
+    FP32, full image."""
+    from paper_2404_14044_amd import hashpoint as hp
+    sc = scenes.sphere_plane()
+    sc.params = sc.params.replace(n_samples=S, K=K, radius=0.05, inv_beta2=1.0 / 0.05 ** 2)
+    R = sc.cams[0].W * sc.cams[0].H
+    rng = np.random.default_rng(13)
+    grad_rgb = rng.normal(size=(R, 3)).astype(np.float32)
+    gf, gm, _ = _gpu(sc, grad_rgb, hp.HP_FP32)
+    _check(gf, gm, _oracle(sc, grad_rgb, [np.arange(R, dtype=np.int32)]), 1e-4)
+
+
 def _multiview(n=200_000, res=160):
     base = scenes.objects_1m(n=n, res=64)
     return scenes.diff_4x400(base=base, res=res)
@@ -197,3 +212,35 @@ def test_autograd_function_matches_direct_call():
     assert torch.allclose(feat.grad, gf, rtol=1e-4, atol=1e-9)
     for k in KEYS:
         assert torch.allclose(mlp[k].grad, gm[k], rtol=1e-4, atol=1e-9)
+
+
+@pytest.mark.parametrize("prec_name", ["fp32", "bf16"])
+def test_backward_from_kept_samples_matches_recompute(prec_name):
+    """hp_render_backward_samples on the forward's samples gives the gradient
+    that hp_render_backward gives after recomputing them (atomics only
+    reorder the feature sums), and so does the autograd function with
+    keep_samples=True."""
+    import torch
+    from paper_2404_14044_amd import hashpoint as hp
+    sc = _multiview(n=100_000, res=96)
+    prec = hp.HP_FP32 if prec_name == "fp32" else hp.HP_BF16
+    dev = torch.device("cuda:0")
+    xyz = torch.from_numpy(sc.xyz).to(dev)
+    feat = torch.from_numpy(sc.feat).to(dev)
+    mlp = hp.to_device_mlp(sc.mlp, dev)
+    tab = hp.build_table(xyz, sc.cams, sc.params)
+    g = torch.randn(tab.n_rays, 3, device=dev, generator=torch.Generator(device=dev).manual_seed(4))
+    gf_a, gm_a = hp.render_backward(tab, feat, mlp, sc.params, prec, g)
+    smp = hp.search_sample(tab, sc.params)
+    gf_b, gm_b = hp.render_backward_samples(smp, tab.n_rays, feat, mlp, sc.params, prec, g)
+    f2 = feat.clone().requires_grad_(True)
+    m2 = {k: v.clone().requires_grad_(True) for k, v in mlp.items()}
+    rgb = hp.HashPointRender.apply(f2, *[m2[k] for k in KEYS], tab, sc.params, prec, True)
+    (rgb * g).sum().backward()
+    torch.cuda.synchronize()
+    assert gf_a.abs().max() > 0
+    for a, b in ((gf_a, gf_b), (gf_a, f2.grad)):
+        assert float((a - b).norm() / a.norm()) < 1e-6
+    for k in KEYS:
+        for b in (gm_b[k], m2[k].grad):
+            assert float((gm_a[k] - b).abs().max() / gm_a[k].abs().max().clamp_min(1e-30)) < 1e-5, k
