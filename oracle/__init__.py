@@ -49,7 +49,8 @@ class Params(ctypes.Structure):
                 ("K", ctypes.c_int32), ("n_samples", ctypes.c_int32), ("m_cap", ctypes.c_int32),
                 ("gamma", ctypes.c_float), ("inv_beta2", ctypes.c_float),
                 ("eps_w", ctypes.c_float), ("eps_idw", ctypes.c_float),
-                ("delta_last", ctypes.c_float), ("bg", ctypes.c_float * 3)]
+                ("delta_last", ctypes.c_float), ("bg", ctypes.c_float * 3),
+                ("radius_mode", ctypes.c_int32), ("rddot", ctypes.c_float)]
 
 
 _lib = None
@@ -72,6 +73,12 @@ def lib():
         _lib.or_table.restype = i64
         _lib.or_table.argtypes = [P, i64, P, i32, P, P]
         _lib.or_ray_dir.argtypes = [P, i32, i32, P]
+        _lib.or_paper_s.restype = i32
+        _lib.or_paper_s.argtypes = [P, P]
+        _lib.or_kappa.restype = ctypes.c_float
+        _lib.or_kappa.argtypes = [P, ctypes.c_float, ctypes.c_float, ctypes.c_float]
+        _lib.or_ray_kappa.restype = ctypes.c_float
+        _lib.or_ray_kappa.argtypes = [P, P, i32, i32]
         _lib.or_exact.argtypes = [P, i64, P, P, P, i64] + [P] * 14
         _lib.or_render64.argtypes = [P, P, i32] + [P] * 6 + [P, P, P, i64, P, P, P, P, P, P]
         _lib.or_grad64.argtypes = [P, P, i32] + [P] * 6 + [P, P, P, i64, P, P, P, P, P] + [P] * 6
@@ -102,6 +109,8 @@ def params_struct(p) -> Params:
     s.delta_last = p.delta_last
     for i in range(3):
         s.bg[i] = float(p.bg[i])
+    s.radius_mode = int(getattr(p, "radius_mode", 0))
+    s.rddot = float(getattr(p, "rddot", 0.0))
     return s
 
 
@@ -119,6 +128,24 @@ def exp32(x) -> np.ndarray:
 def guard(cam, params) -> int:
     c, p = camera_struct(cam), params_struct(params)
     return int(lib().or_guard(ctypes.byref(c), ctypes.byref(p)))
+
+
+def paper_s(cam, params) -> int:
+    """The paper's kernel size s = 2 ceil(rddot / rdot) + 1 (Sec. 3.2)."""
+    c, p = camera_struct(cam), params_struct(params)
+    return int(lib().or_paper_s(ctypes.byref(c), ctypes.byref(p)))
+
+
+def kappa(params, a: float, b: float, L: float) -> float:
+    """Cone slope of Eq. 3 (rho = kappa t) for normalised pixel coordinates."""
+    p = params_struct(params)
+    return float(lib().or_kappa(ctypes.byref(p), ctypes.c_float(a), ctypes.c_float(b),
+                                ctypes.c_float(L)))
+
+
+def ray_kappa(cam, params, u: int, v: int) -> float:
+    c, p = camera_struct(cam), params_struct(params)
+    return float(lib().or_ray_kappa(ctypes.byref(c), ctypes.byref(p), int(u), int(v)))
 
 
 def to_camera(xyz: np.ndarray, cam) -> np.ndarray:

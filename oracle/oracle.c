@@ -43,7 +43,14 @@ typedef struct {
     int32_t K, n_samples, m_cap;
     float gamma, inv_beta2, eps_w, eps_idw, delta_last;
     float bg[3];
+    int32_t radius_mode; /* 0: r max(1, t inv_tref); 1-3: Eq. 3 cone (below) */
+    float rddot;         /* Eq. 3 kernel disc radius, image plane at unit focal length */
 } orc_params;
+
+#define ORC_RADIUS_LINEAR 0
+#define ORC_RADIUS_EQ3 1    /* Eq. 3 as derived (Appendix, similar triangles) */
+#define ORC_RADIUS_EQ3_AF 2 /* Eq. 3 with AB replaced by AF (first small-angle step) */
+#define ORC_RADIUS_EQ3_AE 3 /* Eq. 3 with AB replaced by AE (second step)         */
 
 #define ORC_HID 64
 #define ORC_OUT 4
@@ -80,17 +87,50 @@ void or_exp32_array(const float *x, float *y, int64_t n)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Search radius rho(t) = r * max(1, t * inv_tref).  With inv_tref = 0 it is */
-/* the fixed radius; with inv_tref = 1/t_near it is the cone of Eq. 3, which */
-/* grows linearly with the distance from the ray origin and equals the       */
-/* hyper-parameter radius at t_near (Sec. 3.2).                              */
+/* Search radius, linear mode: rho(t) = r * max(1, t * inv_tref).  With      */
+/* inv_tref = 0 it is a fixed radius; with inv_tref = 1/t_near it is a cone  */
+/* through the optical centre equal to the hyper-parameter radius at t_near  */
+/* (Sec. 3.2), i.e. Eq. 3 without its per-pixel factor.                      */
 /* ------------------------------------------------------------------------ */
-static float rho_of(const orc_params *p, float t)
+static float rho_linear(const orc_params *p, float t)
 {
     float s = t * p->inv_tref;
     float m = (s > 1.0f) ? s : 1.0f;
     return p->radius * m;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Per-pixel cone of Eq. 3.  With the image plane at unit distance (f = 1),  */
+/* a pixel centre E = (a, b, 1) at distance AE = L = |E| from the optical    */
+/* centre A and |w| = sqrt(a^2 + b^2) from the principal point G, and the    */
+/* kernel disc of radius rddot around E, the appendix's construction gives   */
+/*   BF = rddot AG / AE = rddot / L         (B: disc edge towards G),        */
+/*   AB = sqrt((GE - rddot)^2 + AG^2) = sqrt((|w| - rddot)^2 + 1),           */
+/*   r(t) = AD BF / AB with AD = t          (rho = t kappa, kappa = BF / AB). */
+/* The small-angle variants replace AB by AF = AE - BF EG / AG = L - BF |w|  */
+/* or by AE = L.  Reading: GE is taken as |w| (equal to sqrt(AE^2 - AG^2),   */
+/* without its cancellation).                                                */
+/* ------------------------------------------------------------------------ */
+static float kappa_of(const orc_params *p, float a, float b, float L)
+{
+    if (p->radius_mode == ORC_RADIUS_LINEAR) return 0.0f;
+    const float wn = sqrtf(a * a + b * b);
+    const float bf = p->rddot / L;
+    if (p->radius_mode == ORC_RADIUS_EQ3) {
+        const float m = wn - p->rddot;
+        return bf / sqrtf(fmaf(m, m, 1.0f));
+    }
+    if (p->radius_mode == ORC_RADIUS_EQ3_AF) return bf / fmaf(-bf, wn, L);
+    return bf / L;
+}
+
+/* rho(t) of a ray with cone slope kappa (ignored in the linear mode). */
+static float rho_of(const orc_params *p, float kappa, float t)
+{
+    return p->radius_mode == ORC_RADIUS_LINEAR ? rho_linear(p, t) : t * kappa;
+}
+
+float or_kappa(const orc_params *p, float a, float b, float L) { return kappa_of(p, a, b, L); }
 
 /* Guard band g around the image (in pixels).  A point within rho(t) of a    */
 /* ray at parameter t >= t_near projects at most                             */
@@ -109,12 +149,35 @@ int32_t or_guard(const orc_camera *cam, const orc_params *p)
             if (a * a + b * b > w2) w2 = a * a + b * b;
         }
     double f = cam->fx > cam->fy ? cam->fx : cam->fy;
-    double s = (double)p->t_near * p->inv_tref;
-    double rho = (double)p->radius * (s > 1.0 ? s : 1.0);
-    double den = p->t_near - rho * sqrt(w2);
-    if (!(den > 0.0)) return -1;
-    double delta = f * rho * (1.0 + w2) / den;
+    double delta;
+    if (p->radius_mode == ORC_RADIUS_LINEAR) {
+        double s = (double)p->t_near * p->inv_tref;
+        double rho = (double)p->radius * (s > 1.0 ? s : 1.0);
+        double den = p->t_near - rho * sqrt(w2);
+        if (!(den > 0.0)) return -1;
+        delta = f * rho * (1.0 + w2) / den;
+    } else {
+        /* rho = kappa t: delta = f kappa L^2 / (1 - kappa |w|) for every t; */
+        /* every variant has kappa <= rddot / (1 - rddot^2 / 4)              */
+        double k = (double)p->rddot / (1.0 - 0.25 * (double)p->rddot * p->rddot);
+        double den = 1.0 - k * sqrt(w2);
+        if (!(k > 0.0) || !(den > 0.0)) return -1;
+        delta = f * k * (1.0 + w2) / den;
+    }
+    if (!(delta < 1e6)) return -1;
     return (int32_t)floor(0.5 + delta) + 1;
+}
+
+/* The paper's kernel size s = 2 ceil(rddot / rdot) + 1, rdot = sqrt(dx dy /  */
+/* pi) the radius of the disc of one pixel's area (Sec. 3.2).  In the linear */
+/* mode rddot is read as the radius at t_near over t_near.                   */
+int32_t or_paper_s(const orc_camera *cam, const orc_params *p)
+{
+    double rdd = p->radius_mode == ORC_RADIUS_LINEAR
+                     ? (double)rho_linear(p, p->t_near) / p->t_near
+                     : (double)p->rddot;
+    double rdot = sqrt(1.0 / ((double)cam->fx * cam->fy * 3.14159265358979323846));
+    return 2 * (int32_t)ceil(rdd / rdot) + 1;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -185,14 +248,28 @@ int64_t or_table(const float *pc, int64_t n, const orc_camera *cam, int32_t g,
 /* Ray of pixel (u, v): from the optical centre through the pixel centre     */
 /* (u + 0.5, v + 0.5), unit length, camera coordinates.                      */
 /* ------------------------------------------------------------------------ */
+static void ray_abl(const orc_camera *cam, int32_t u, int32_t v, float *a, float *b, float *L)
+{
+    *a = (((float)u + 0.5f) - cam->cx) / cam->fx;
+    *b = (((float)v + 0.5f) - cam->cy) / cam->fy;
+    *L = sqrtf(fmaf(*b, *b, fmaf(*a, *a, 1.0f)));
+}
+
 void or_ray_dir(const orc_camera *cam, int32_t u, int32_t v, float d[3])
 {
-    float a = (((float)u + 0.5f) - cam->cx) / cam->fx;
-    float b = (((float)v + 0.5f) - cam->cy) / cam->fy;
-    float L = sqrtf(fmaf(b, b, fmaf(a, a, 1.0f)));
+    float a, b, L;
+    ray_abl(cam, u, v, &a, &b, &L);
     d[0] = a / L;
     d[1] = b / L;
     d[2] = 1.0f / L;
+}
+
+/* Cone slope kappa of pixel (u, v) (0 in the linear mode). */
+float or_ray_kappa(const orc_camera *cam, const orc_params *p, int32_t u, int32_t v)
+{
+    float a, b, L;
+    ray_abl(cam, u, v, &a, &b, &L);
+    return kappa_of(p, a, b, L);
 }
 
 /* Projection parameter t of camera-space point x on ray d, and the squared  */
@@ -267,12 +344,13 @@ void or_exact(const float *pc, int64_t n, const orc_camera *cam, const orc_param
             const int32_t u = pix[r] % cam->W, v = pix[r] / cam->W;
             float d[3];
             or_ray_dir(cam, u, v, d);
+            const float kap = or_ray_kappa(cam, p, u, v);
             /* brute-force predicate over all points */
             for (int64_t i = 0; i < n; ++i) {
                 const float *x = pc + 3 * i;
                 float t = ray_t(x, d);
                 float e2 = dist2_at(x, d, t);
-                float rho = rho_of(p, t);
+                float rho = rho_of(p, kap, t);
                 tv[i] = t;
                 pass[i] = (uint8_t)((x[2] > 0.0f) & (t >= p->t_near) & (t <= p->t_far) &
                                     (e2 <= rho * rho));
@@ -303,7 +381,7 @@ void or_exact(const float *pc, int64_t n, const orc_camera *cam, const orc_param
             primary[r] = -1;
             for (int j = 0; j < m; ++j) {
                 const float tj = nb[j].key;
-                const float Rj = rho_of(p, tj);
+                const float Rj = rho_of(p, kap, tj);
                 const float R2 = Rj * Rj;
                 int kc = 0;
                 for (int i = 0; i < m; ++i) {

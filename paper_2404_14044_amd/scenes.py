@@ -86,8 +86,14 @@ def pinhole(W: int, H: int, hfov_deg: float, R, C) -> Camera:
 class Params:
     """Hyper-parameters of search, sampling and rendering.
 
-    radius, inv_tref: search radius rho(t) = radius * max(1, t * inv_tref);
-        inv_tref = 0 is a fixed radius, 1 / t_near the linear cone of Eq. 3.
+    radius, inv_tref: search radius rho(t) = radius * max(1, t * inv_tref)
+        (radius_mode 0); inv_tref = 0 is a fixed radius, 1 / t_near a linear
+        cone equal to radius at t_near.
+    radius_mode, rddot: radius_mode 1 is the per-pixel cone of Eq. 3 with
+        kernel disc radius rddot (image plane at unit focal length), 2 and 3
+        its two small-angle variants (AB replaced by AF, by AE); rho = t kappa
+        with kappa per pixel.  `eq3_rddot` picks rddot so that the principal
+        pixel's radius at t_near is `radius`.
     t_near, t_far: sampling range along the ray (Sec. 3.2).
     K: neighbours per sample (Eq. 4).  n_samples: cap on samples per ray.
     m_cap: cap on the per-ray neighbour list.
@@ -114,9 +120,22 @@ class Params:
     flags: int = 0
     search_chunk: int = 0
     search_blocks: int = 0
+    radius_mode: int = 0
+    rddot: float = 0.0
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
+
+
+def eq3_rddot(mode: int, radius: float, t_near: float) -> float:
+    """Kernel disc radius (unit focal length) for which the principal pixel's
+    cone has radius `radius` at t_near: kappa(axis) = rddot / sqrt(1 + rddot^2)
+    for the derived form, rddot for the small-angle forms (Sec. 3.2: the
+    minimum radius sits at t_near and equals the radius hyper-parameter)."""
+    r, tn = float(radius), float(t_near)
+    if mode == 1:
+        return float(np.float32(r / np.sqrt(tn * tn - r * r)))
+    return float(np.float32(r / tn))
 
 
 def default_params(radius, t_near, t_far, K, S, inv_tref=0.0) -> Params:
