@@ -159,6 +159,8 @@ def main():
     if not args.no_extra:
         result["batched_16"] = batched_leg(sc)
         result["train_4x400"] = train_leg(sc)
+        result["radius_modes"] = radius_modes_leg(sc)
+        result["samplers"] = sampler_leg(sc)
 
     if args.cpu_seconds > 0:
         result.update(cpu_leg(sc, p, smp, outs, R, args.cpu_seconds))
@@ -202,6 +204,99 @@ def batched_leg(sc, reps=5):
             "graph_ms": t_graph, "eager_ms": t_eager, "separate_ms": t_sep,
             "graph_mrays_s": rays / t_graph / 1e3, "eager_mrays_s": rays / t_eager / 1e3,
             "separate_mrays_s": rays / t_sep / 1e3, "speedup_vs_separate": t_sep / t_graph}
+
+
+def radius_modes_leg(sc, reps=5):
+    """Build + search/sample + render (BF16) on the same view under each search
+    radius law: the fixed radius, the linear cone equal to r at t_near, and the
+    per-pixel cone of Eq. 3 with its two small-angle variants (rddot puts the
+    principal pixel's radius at t_near equal to r).  Reports the guard band g
+    the search uses next to the paper's kernel size s."""
+    import torch
+    from paper_2404_14044_amd import hashpoint as hp
+    from paper_2404_14044_amd import scenes
+    dev = torch.device("cuda:0")
+    cam = sc.cams[0]
+    R = cam.W * cam.H
+    xyz = torch.from_numpy(sc.xyz).to(dev)
+    feat = torch.from_numpy(sc.feat).to(dev)
+    mlp = hp.to_device_mlp(sc.mlp, dev)
+    base = sc.params
+    modes = {
+        "fixed": base,
+        "linear_cone": base.replace(inv_tref=float(np.float32(1.0 / base.t_near))),
+    }
+    for name, m in (("eq3", hp.HP_RADIUS_EQ3), ("eq3_af", hp.HP_RADIUS_EQ3_AF),
+                    ("eq3_ae", hp.HP_RADIUS_EQ3_AE)):
+        modes[name] = base.replace(radius_mode=m, rddot=scenes.eq3_rddot(m, base.radius, base.t_near))
+    out = {}
+    for name, p in modes.items():
+        ws = torch.empty(hp.table_workspace(xyz.shape[0], [cam], p), dtype=torch.uint8, device=dev)
+        smp = hp.alloc_samples(R, p, dev)
+        o = {"rgb": torch.empty(R * 3, device=dev)}
+        holder = {}
+
+        def build():
+            holder["tab"] = hp.build_table(xyz, [cam], p, ws=ws)
+
+        t_build = _time_ms(build, reps)
+        tab = holder["tab"]
+        t_search = _time_ms(lambda: hp.search_sample(tab, p, out=smp), reps)
+        t_render = _time_ms(lambda: hp.render(smp, R, feat, mlp, p, hp.HP_BF16, out=o), reps)
+        n_nbr = smp["n_nbr"].float()
+        g, _ = hp.view_bounds(cam, p)
+        total = t_build + t_search + t_render
+        out[name] = {"build_ms": t_build, "search_ms": t_search, "render_ms": t_render,
+                     "mrays_s": R / total / 1e3, "guard_g": g,
+                     "paper_s": hp.paper_kernel_size(cam, p),
+                     "mean_n_nbr": float(n_nbr.mean().item()),
+                     "overflow_frac": float((smp["flags"] & 1).float().mean().item()),
+                     "samples": int(smp["n_sel"].sum().item())}
+        del ws, smp, o, tab, holder
+    return out
+
+
+def sampler_leg(sc, reps=5):
+    """Primary-surface walk at several gamma (Sec. 3.3 and the supplement's
+    gamma sweep: smaller gamma samples further past the primary surface) and
+    the uniform multi-surface baseline (Sec. 3.5; 400 positions over
+    [t_near, t_far], one per r), all with up to 64 samples per ray except the
+    default gamma = 0.9, S = 16 workload.  Build + search/sample + render
+    (BF16) on the same view."""
+    import torch
+    from paper_2404_14044_amd import hashpoint as hp
+    dev = torch.device("cuda:0")
+    cam = sc.cams[0]
+    R = cam.W * cam.H
+    xyz = torch.from_numpy(sc.xyz).to(dev)
+    feat = torch.from_numpy(sc.feat).to(dev)
+    mlp = hp.to_device_mlp(sc.mlp, dev)
+    base = sc.params
+    runs = {"ps_gamma0.9_S16": base}
+    for gm in (0.9, 0.5, 0.1, 0.01):
+        runs[f"ps_gamma{gm}_S64"] = base.replace(gamma=float(np.float32(gm)), n_samples=64)
+    runs["ms_400_S64"] = base.replace(sampler=hp.HP_SAMPLER_MS, ms_steps=400, n_samples=64)
+    out = {}
+    ws = torch.empty(hp.table_workspace(xyz.shape[0], [cam], base), dtype=torch.uint8, device=dev)
+    tab = hp.build_table(xyz, [cam], base, ws=ws)
+    t_build = _time_ms(lambda: hp.build_table(xyz, [cam], base, ws=ws), reps)
+    for name, p in runs.items():
+        smp = hp.alloc_samples(R, p, dev)
+        o = {"rgb": torch.empty(R * 3, device=dev)}
+        t_search = _time_ms(lambda: hp.search_sample(tab, p, out=smp), reps)
+        t_render = _time_ms(lambda: hp.render(smp, R, feat, mlp, p, hp.HP_BF16, out=o), reps)
+        ns = smp["n_sel"]
+        hit = int((ns > 0).sum().item())
+        tot = t_build + t_search + t_render
+        out[name] = {"search_ms": t_search, "render_ms": t_render, "total_ms": tot,
+                     "mrays_s": R / tot / 1e3, "samples": int(ns.sum().item()),
+                     "samples_per_hit_ray": float(ns.sum().item()) / max(hit, 1),
+                     "hit_rays": hit}
+        del smp, o
+    ms = out["ms_400_S64"]["total_ms"]
+    for name in out:
+        out[name]["speedup_vs_ms"] = ms / out[name]["total_ms"]
+    return out
 
 
 def train_leg(sc, reps=5):

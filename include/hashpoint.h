@@ -55,6 +55,18 @@ enum {
 
 enum { HP_FP32 = 0, HP_BF16 = 1 };                 /* decoder precision  */
 enum { HP_LAYOUT_ROWMAJOR = 0, HP_LAYOUT_TILED = 1 }; /* bucket order     */
+/* Search radius laws (hp_params.radius_mode). */
+enum {
+    HP_RADIUS_LINEAR = 0, /* rho = radius * max(1, t * inv_tref)                     */
+    HP_RADIUS_EQ3 = 1,    /* rho = kappa t, kappa per pixel from Eq. 3 as derived     */
+    HP_RADIUS_EQ3_AF = 2, /* the same with the first small-angle step (AB ~ AF)      */
+    HP_RADIUS_EQ3_AE = 3  /* the same with the second small-angle step (AB ~ AE)     */
+};
+/* Samplers (hp_params.sampler). */
+enum {
+    HP_SAMPLER_PS = 0, /* adaptive primary-surface sampling (Sec. 3.3, Eq. 4, Eq. 5) */
+    HP_SAMPLER_MS = 1  /* uniform multi-surface sampling, the Sec. 3.5 baseline      */
+};
 
 #define HP_MAX_VIEWS 32
 #define HP_MAX_K 32
@@ -74,9 +86,11 @@ typedef struct hp_camera {
 } hp_camera;
 
 /* Run parameters (host).
- *  radius, inv_tref: search radius rho(t) = radius * max(1, t * inv_tref).
- *      inv_tref = 0 gives a fixed radius; inv_tref = 1 / t_near gives the
- *      cone of Eq. 3, linear in t and equal to radius at t_near (Sec. 3.2).
+ *  radius, inv_tref: in HP_RADIUS_LINEAR mode the search radius is
+ *      rho(t) = radius * max(1, t * inv_tref); inv_tref = 0 gives a fixed
+ *      radius, inv_tref = 1 / t_near a cone equal to radius at t_near
+ *      (Sec. 3.2) without Eq. 3's per-pixel factor.  radius also bounds the
+ *      depth summaries' search in every mode.
  *  t_near, t_far: range of the ray parameter t (0 < t_near <= t_far).
  *  K: points per pseudo-UDF (Eq. 4), 1..HP_MAX_K.
  *  n_samples: cap on samples per ray, 1..HP_MAX_SAMPLES.
@@ -90,7 +104,22 @@ typedef struct hp_camera {
  *  flags: reserved, must be 0.
  *  search_chunk: rays a search workgroup takes at a time, 0 = default (4),
  *      at most 64; search_blocks: persistent search grid, 0 = default.
- *      Neither changes any result; an autotuner picks them per workload. */
+ *      Neither changes any result; an autotuner picks them per workload.
+ *  radius_mode: HP_RADIUS_*.  In the Eq. 3 modes rho(t) = kappa t with, for
+ *      the pixel centre E = (a, b, 1) on the image plane at unit focal
+ *      length (L = |E|, |w| = sqrt(a^2 + b^2)), BF = rddot / L and
+ *      kappa = BF / sqrt((|w| - rddot)^2 + 1) (EQ3), BF / (L - BF |w|)
+ *      (EQ3_AF) or BF / L (EQ3_AE), each a fixed sequence of binary32
+ *      operations (Sec. 3.2, Eq. 3, and the appendix's derivation).
+ *  rddot: the kernel disc radius r'' on that image plane, 0 < rddot < 1;
+ *      ignored (must be 0) in HP_RADIUS_LINEAR mode.
+ *  sampler: HP_SAMPLER_PS, or HP_SAMPLER_MS: positions
+ *      t_k = fma(k + 0.5, (t_far - t_near) / ms_steps, t_near), k < ms_steps,
+ *      each a sample (in order, up to n_samples) when a point of the ray's
+ *      neighbour list lies within rho(t_k) of it, with its K nearest listed
+ *      points; primary = the nearest point of the first sample.  gamma,
+ *      inv_beta2 and eps_w are then unused.
+ *  ms_steps: 1..2^24 with HP_SAMPLER_MS, 0 otherwise. */
 typedef struct hp_params {
     float radius, inv_tref, t_near, t_far;
     int32_t K, n_samples, m_cap;
@@ -98,6 +127,9 @@ typedef struct hp_params {
     float bg[3];
     int32_t layout, flags;
     int32_t search_chunk, search_blocks;
+    int32_t radius_mode;
+    float rddot;
+    int32_t sampler, ms_steps;
 } hp_params;
 
 /* Per-view geometry of a table, filled by hp_build_table. */
@@ -173,8 +205,17 @@ size_t hp_table_workspace(int64_t n, const hp_camera *cams, int32_t n_views,
  * delta = f rho L^2 / (t - rho |w|) on the pixel offset of a point within
  * rho(t) of a ray with normalised image coordinate w (L^2 = 1 + |w|^2) does
  * not grow with t, so its value at t_near and the image corner bounds every
- * neighbour; g = floor(0.5 + delta) + 1. */
+ * neighbour; g = floor(0.5 + delta) + 1.  In the Eq. 3 modes
+ * delta = f kappa L^2 / (1 - kappa |w|) for every t, and every variant has
+ * kappa <= rddot / (1 - rddot^2 / 4), which with the corner's |w| bounds it. */
 hp_status hp_view_bounds(const hp_camera *cam, const hp_params *p, int32_t *g, float *delta_max);
+
+/* The paper's search-kernel size s = 2 ceil(rddot / rdot) + 1 for this view
+ * (Sec. 3.2), rdot = sqrt(1 / (pi fx fy)) the radius of a disc of one pixel's
+ * area on the unit-focal image plane; in HP_RADIUS_LINEAR mode rddot is
+ * read as rho(t_near) / t_near.  Reported beside the guard band g, which is
+ * what the search uses (host only). */
+hp_status hp_paper_kernel_size(const hp_camera *cam, const hp_params *p, int32_t *s);
 
 /* Build the pixel table (Sec. 3.2, Fig. 2) for n_views cameras.
  *  xyz: device, n x 3 FP32 world positions.  Non-finite points and points

@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
                 ("gamma", ctypes.c_float), ("inv_beta2", ctypes.c_float),
                 ("eps_w", ctypes.c_float), ("eps_idw", ctypes.c_float),
                 ("delta_last", ctypes.c_float), ("bg", ctypes.c_float * 3),
-                ("radius_mode", ctypes.c_int32), ("rddot", ctypes.c_float)]
+                ("radius_mode", ctypes.c_int32), ("rddot", ctypes.c_float),
+                ("sampler", ctypes.c_int32), ("ms_steps", ctypes.c_int32)]
 
 
 _lib = None
@@ -111,6 +112,8 @@ def params_struct(p) -> Params:
         s.bg[i] = float(p.bg[i])
     s.radius_mode = int(getattr(p, "radius_mode", 0))
     s.rddot = float(getattr(p, "rddot", 0.0))
+    s.sampler = int(getattr(p, "sampler", 0))
+    s.ms_steps = int(getattr(p, "ms_steps", 0))
     return s
 
 

@@ -45,7 +45,12 @@ typedef struct {
     float bg[3];
     int32_t radius_mode; /* 0: r max(1, t inv_tref); 1-3: Eq. 3 cone (below) */
     float rddot;         /* Eq. 3 kernel disc radius, image plane at unit focal length */
+    int32_t sampler;     /* 0: adaptive primary-surface walk; 1: uniform multi-surface */
+    int32_t ms_steps;    /* uniform positions along [t_near, t_far] (sampler 1)       */
 } orc_params;
+
+#define ORC_SAMPLER_PS 0
+#define ORC_SAMPLER_MS 1
 
 #define ORC_RADIUS_LINEAR 0
 #define ORC_RADIUS_EQ3 1    /* Eq. 3 as derived (Appendix, similar triangles) */
@@ -375,11 +380,43 @@ void or_exact(const float *pc, int64_t n, const orc_camera *cam, const orc_param
                 nbr_idx[r * M + j] = j < m ? nb[j].idx : -1;
                 nbr_t[r * M + j] = j < m ? nb[j].key : 0.0f;
             }
-            /* candidate walk in depth order */
             float T = 1.0f;
             int sel = 0;
             primary[r] = -1;
-            for (int j = 0; j < m; ++j) {
+            if (p->sampler == ORC_SAMPLER_MS) {
+                /* Multi-surface sampling (Sec. 3.5, the volume-rendering baseline */
+                /* it is compared with): uniform positions t_k = t_near + (k + 1/2) */
+                /* step along the ray; a position lies on a surface when some point */
+                /* of N(ray) is within R_k = rho(t_k) of it, and every such position */
+                /* becomes a sample (in depth order, up to n_samples) with its K     */
+                /* nearest points of N(ray) within R_k.  Reading: the primary       */
+                /* surface is the nearest point of the first sample.                 */
+                const float step = (p->t_far - p->t_near) / (float)p->ms_steps;
+                for (int k = 0; k < p->ms_steps && sel < S; ++k) {
+                    const float tk = fmaf((float)k + 0.5f, step, p->t_near);
+                    const float Rk = rho_of(p, kap, tk);
+                    const float R2 = Rk * Rk;
+                    int kc = 0;
+                    for (int i = 0; i < m; ++i) {
+                        float dd = dist2_at(pc + 3 * (int64_t)nb[i].idx, d, tk);
+                        if (dd <= R2) { kn[kc].key = dd; kn[kc].idx = nb[i].idx; ++kc; }
+                    }
+                    if (kc == 0) continue;
+                    qsort(kn, (size_t)kc, sizeof(kv_ent), cmp_kv);
+                    const int kj = kc < K ? kc : K;
+                    const int64_t row = r * S + sel;
+                    smp_t[row] = tk;
+                    knn_cnt[row] = kj;
+                    for (int q = 0; q < K; ++q) {
+                        knn_idx[row * K + q] = q < kj ? kn[q].idx : -1;
+                        knn_dist[row * K + q] = q < kj ? sqrtf(kn[q].key) : 0.0f;
+                    }
+                    if (sel == 0) primary[r] = kn[0].idx;
+                    ++sel;
+                }
+            }
+            /* candidate walk in depth order */
+            for (int j = 0; j < (p->sampler == ORC_SAMPLER_MS ? 0 : m); ++j) {
                 const float tj = nb[j].key;
                 const float Rj = rho_of(p, kap, tj);
                 const float R2 = Rj * Rj;
@@ -423,7 +460,7 @@ void or_exact(const float *pc, int64_t n, const orc_camera *cam, const orc_param
                 }
             }
             if (cand_d)
-                for (int j = m; j < M; ++j) {
+                for (int j = (p->sampler == ORC_SAMPLER_MS ? 0 : m); j < M; ++j) {
                     cand_d[r * M + j] = 0.0f;
                     if (cand_alpha) cand_alpha[r * M + j] = 0.0f;
                     if (cand_w) cand_w[r * M + j] = 0.0f;

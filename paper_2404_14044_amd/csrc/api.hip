@@ -50,7 +50,18 @@ bool valid_params(const hp_params &p)
     if (p.layout != HP_LAYOUT_ROWMAJOR && p.layout != HP_LAYOUT_TILED) return false;
     if (p.flags != 0) return false;
     if (p.search_chunk < 0 || p.search_chunk > 64 || p.search_blocks < 0) return false;
-    return true;
+    if (p.sampler == HP_SAMPLER_PS) {
+        if (p.ms_steps != 0) return false;
+    } else if (p.sampler == HP_SAMPLER_MS) {
+        if (p.ms_steps < 1 || p.ms_steps > (1 << 24)) return false;
+    } else {
+        return false;
+    }
+    if (p.radius_mode == HP_RADIUS_LINEAR) return p.rddot == 0.0f;
+    if (p.radius_mode != HP_RADIUS_EQ3 && p.radius_mode != HP_RADIUS_EQ3_AF &&
+        p.radius_mode != HP_RADIUS_EQ3_AE)
+        return false;
+    return p.rddot > 0.0f && p.rddot < 1.0f;
 }
 
 // Pixel-offset bound of a neighbour (see hashpoint.h, hp_view_bounds).
@@ -64,10 +75,17 @@ bool view_bound(const hp_camera &c, const hp_params &p, double &delta)
             w2max = fmax(w2max, a * a + b * b);
         }
     const double f = fmax((double)c.fx, (double)c.fy);
-    const double rho = (double)p.radius * fmax(1.0, (double)p.t_near * p.inv_tref);
-    const double den = (double)p.t_near - rho * sqrt(w2max);
-    if (!(den > 0.0)) return false;
-    delta = f * rho * (1.0 + w2max) / den;
+    if (p.radius_mode == HP_RADIUS_LINEAR) {
+        const double rho = (double)p.radius * fmax(1.0, (double)p.t_near * p.inv_tref);
+        const double den = (double)p.t_near - rho * sqrt(w2max);
+        if (!(den > 0.0)) return false;
+        delta = f * rho * (1.0 + w2max) / den;
+    } else {
+        const double k = (double)p.rddot / (1.0 - 0.25 * (double)p.rddot * p.rddot);
+        const double den = 1.0 - k * sqrt(w2max);
+        if (!(den > 0.0)) return false;
+        delta = f * k * (1.0 + w2max) / den;
+    }
     return isfinite(delta) != 0 && delta < 1e6;
 }
 
@@ -165,6 +183,21 @@ hp_status hp_view_bounds(const hp_camera *cam, const hp_params *p, int32_t *g, f
     return HP_OK;
 }
 
+hp_status hp_paper_kernel_size(const hp_camera *cam, const hp_params *p, int32_t *s)
+{
+    if (!cam || !p || !s || !valid_camera(*cam) || !valid_params(*p)) return HP_E_INVALID;
+    double rdd = p->rddot;
+    if (p->radius_mode == HP_RADIUS_LINEAR) {
+        const float m = p->t_near * p->inv_tref;
+        rdd = (double)(p->radius * (m > 1.0f ? m : 1.0f)) / p->t_near;
+    }
+    const double rdot = sqrt(1.0 / ((double)cam->fx * cam->fy * 3.14159265358979323846));
+    const double half = ceil(rdd / rdot);
+    if (!(half < 1e6)) return HP_E_INVALID;
+    *s = 2 * (int32_t)half + 1;
+    return HP_OK;
+}
+
 size_t hp_table_workspace(int64_t n, const hp_camera *cams, int32_t n_views, const hp_params *p,
                           hp_status *status)
 {
@@ -253,6 +286,10 @@ static hp_status make_ctx(const hp_table *tab, const hp_camera *cams, int32_t n_
     c.M = p->m_cap;
     c.chunk = p->search_chunk > 0 ? p->search_chunk : 4;
     c.blocks = p->search_blocks;
+    c.rmode = p->radius_mode;
+    c.rddot = p->rddot;
+    c.sampler = p->sampler;
+    c.ms_steps = p->ms_steps;
     return HP_OK;
 }
 

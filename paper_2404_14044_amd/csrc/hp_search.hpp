@@ -55,6 +55,10 @@ struct SearchCtx {
     float radius, inv_tref, t_near, t_far, gamma, inv_beta2, eps_w;
     int32_t K, S, M;
     int32_t chunk, blocks;  // rays per work chunk, persistent grid (0 = default)
+    int32_t rmode;          // HP_RADIUS_*
+    float rddot;            // Eq. 3 kernel disc radius (unit focal length)
+    int32_t sampler;        // HP_SAMPLER_*
+    int32_t ms_steps;       // uniform positions of the multi-surface sampler
 };
 
 constexpr int BL_CAP = 128;
@@ -73,7 +77,14 @@ struct SearchLds {
 struct RayGeom {
     int vi, u, v;
     float dx, dy, dz, a, b, L, wn;
+    float kappa;  // Eq. 3 cone slope of this pixel (rho = kappa t), 0 in the linear mode
 };
+
+// Search radius of a ray at parameter t.
+__device__ __forceinline__ float rho_at(const SearchCtx &c, const RayGeom &g, float t)
+{
+    return c.rmode == HP_RADIUS_LINEAR ? search_radius(c.radius, c.inv_tref, t) : t * g.kappa;
+}
 
 // Orders this wave's LDS accesses.  A wave's LDS operations execute in program
 // order, so a compiler barrier is enough: lanes then see each other's writes.
@@ -186,6 +197,19 @@ __device__ __forceinline__ RayGeom ray_geometry(const SearchCtx &c, int64_t ray)
     r.v = local / V.W;
     ray_dir(V, r.u, r.v, r.dx, r.dy, r.dz, r.a, r.b, r.L);
     r.wn = __builtin_sqrtf(r.a * r.a + r.b * r.b);
+    // Eq. 3 on the unit-focal image plane: BF = rddot / L over AB, AF or AE
+    r.kappa = 0.0f;
+    if (c.rmode != HP_RADIUS_LINEAR) {
+        const float bf = c.rddot / r.L;
+        if (c.rmode == HP_RADIUS_EQ3) {
+            const float m = r.wn - c.rddot;
+            r.kappa = bf / __builtin_sqrtf(fma_rn(m, m, 1.0f));
+        } else if (c.rmode == HP_RADIUS_EQ3_AF) {
+            r.kappa = bf / fma_rn(-bf, r.wn, r.L);
+        } else {
+            r.kappa = bf / r.L;
+        }
+    }
     return r;
 }
 
@@ -243,13 +267,15 @@ __device__ __forceinline__ float cells_zmin(const CellWindow &w, const ViewK &V,
 
 // Window radius (pixels) for neighbours whose depth is at least zmin.
 __device__ __forceinline__ float radius_for_depth(const SearchCtx &c, const RayGeom &g, float f,
-                                                  float L2, float zmin, float dcap)
+                                                  float L2, float zmin, float dcap, float dinf)
 {
+    // a pure cone projects to a disc whose radius does not depend on depth
+    if (c.rmode != HP_RADIUS_LINEAR) return dinf < dcap ? dinf : dcap;
     const float k = c.radius * c.inv_tref;
     float t = (g.L * zmin - g.wn * c.radius) / (1.0f + g.wn * k);
     t = t * 0.9999f - 1e-6f;
     if (!(t > c.t_near)) t = c.t_near;
-    const float rho = search_radius(c.radius, c.inv_tref, t);
+    const float rho = rho_at(c, g, t);
     const float den = t - rho * g.wn;
     if (!(den > 0.0f)) return dcap;
     const float d = (f * rho * L2 / den) * 1.0001f + 0.01f;
@@ -266,16 +292,16 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
     const ViewK &V = c.views[g.vi];
     const float L2 = fma_rn(g.wn, g.wn, 1.0f);
     const float f = V.fx > V.fy ? V.fx : V.fy;
-    const float rho_n = search_radius(c.radius, c.inv_tref, c.t_near);
-    const float rho_f = search_radius(c.radius, c.inv_tref, c.t_far);
+    const float rho_n = rho_at(c, g, c.t_near);
+    const float rho_f = rho_at(c, g, c.t_far);
     const float z_lo = ((c.t_near - g.wn * rho_n) / g.L) * 0.999f - 1e-6f;
     const float z_hi = ((c.t_far + g.wn * rho_f) / g.L) * 1.001f + 1e-6f;
     // pixel offset bound once rho has reached its linear branch
     float dinf = 0.0f;
-    if (c.inv_tref > 0.0f) {
-        const float k = c.radius * c.inv_tref;
-        const float den = 1.0f - k * g.wn;
-        dinf = den > 0.0f ? (f * k * L2 / den) * 1.001f + 0.01f : __builtin_inff();
+    const float klin = c.rmode == HP_RADIUS_LINEAR ? c.radius * c.inv_tref : g.kappa;
+    if (klin > 0.0f) {
+        const float den = 1.0f - klin * g.wn;
+        dinf = den > 0.0f ? (f * klin * L2 / den) * 1.001f + 0.01f : __builtin_inff();
     }
     const float frL2 = f * c.radius * L2;
     const float two_rw = 2.0f * c.radius * g.wn;
@@ -293,7 +319,7 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
         for (int round = 0; round < 2; ++round) {
             const float zmin = cells_zmin(cw, V, gx, gy, h);
             if (!(zmin < __builtin_inff())) return;  // no point anywhere near this ray
-            Dmax = radius_for_depth(c, g, f, L2, zmin, Dmax);
+            Dmax = radius_for_depth(c, g, f, L2, zmin, Dmax, dinf);
             h = min((int)__builtin_floorf(Dmax + 0.5f), V.g);
         }
     }
@@ -352,7 +378,7 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
                 if (P.z <= sh.bl_zmax[own] && P.z >= z_lo) {
                     const float t = ray_param(P.x, P.y, P.z, g.dx, g.dy, g.dz);
                     const float e2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, t);
-                    const float rho = search_radius(c.radius, c.inv_tref, t);
+                    const float rho = rho_at(c, g, t);
                     pass = (P.z > 0.0f) & (t >= c.t_near) & (t <= c.t_far) & (e2 <= rho * rho);
                     key = ((uint64_t)__float_as_uint(t) << 32) | __float_as_uint(P.w);
                 }
@@ -448,19 +474,64 @@ __device__ __forceinline__ void merge_low(uint64_t (&a)[KT], const uint64_t (&b)
 // register list of (dist^2 bits << 32 | index) among entries within R_j, and
 // the quad then merges its four lists (DPP within the quad).  On return every
 // lane of the quad holds the candidate's KT smallest keys (~0 = none).
+// Quad-split nearest neighbours of the ray point at tq among the sorted-list
+// entries [lo, hi) within R2: lane q of each quad takes entries lo + q,
+// lo + q + 4, ... into an ascending register list of (dist^2 bits << 32 |
+// index); the quad then merges its four lists (DPP within the quad).
 template <int KT>
-__device__ __forceinline__ void knn_quad(const SearchCtx &c, const RayGeom &g, const SearchLds &sh,
-                                         int j, int m, uint64_t (&kd)[KT])
+__device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh, float tq, float R2,
+                                           int lo, int hi, uint64_t (&kd)[KT])
 {
     const int q = lane_id() & 3;
 #pragma unroll
     for (int k = 0; k < KT; ++k) kd[k] = ~0ull;
+    int n_it = (hi - lo - q + 3) >> 2;
+    n_it = n_it > 0 ? n_it : 0;
+#pragma unroll
+    for (int o = 4; o < WAVE; o <<= 1) {
+        const int y = __shfl_xor(n_it, o, WAVE);
+        n_it = n_it > y ? n_it : y;
+    }
+    for (int it = 0; it < n_it; ++it) {
+        const int i = lo + q + 4 * it;
+        uint64_t x = ~0ull;
+        if (i < hi) {
+            const float4 P = sh.nb_p[i];
+            const float d2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, tq);
+            if (d2 <= R2) x = ((uint64_t)__float_as_uint(d2) << 32) | __float_as_uint(P.w);
+        }
+        // branch-free insertion: a key of ~0 leaves the list unchanged
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            const uint64_t lo64 = umin64(kd[k], x);
+            x = umax64(kd[k], x);
+            kd[k] = lo64;
+        }
+    }
+    uint64_t other[KT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k) other[k] = xor_lane_u64<1>(kd[k]);
+    merge_low<KT>(kd, other);
+#pragma unroll
+    for (int k = 0; k < KT; ++k) other[k] = xor_lane_u64<2>(kd[k]);
+    merge_low<KT>(kd, other);
+}
+
+// Nearest neighbours of 16 candidates at once.  Lane l = 4 g + q serves
+// candidate c0 + g; its four lanes split the candidate's t-window of the
+// sorted list (entries within R_j in t), each keeping an ascending register
+// list, merged across the quad.  On return every lane of the quad holds the
+// candidate's KT smallest keys (~0 = none).
+template <int KT>
+__device__ __forceinline__ void knn_quad(const SearchCtx &c, const RayGeom &g, const SearchLds &sh,
+                                         int j, int m, uint64_t (&kd)[KT])
+{
     const bool active = j < m;
     float tj = 0.0f, R2 = 0.0f;
     int lo = 0, hi = 0;
     if (active) {
         tj = sh.nb_t[j];
-        const float Rj = search_radius(c.radius, c.inv_tref, tj);
+        const float Rj = rho_at(c, g, tj);
         R2 = Rj * Rj;
         // |t_i - t_j| > span implies dist^2 > R_j^2 (margins above rounding)
         const float span = Rj * 1.001f + tj * 4e-6f + 1e-7f;
@@ -481,36 +552,7 @@ __device__ __forceinline__ void knn_quad(const SearchCtx &c, const RayGeom &g, c
         }
         hi = a;
     }
-    int n_it = (hi - lo - q + 3) >> 2;
-    n_it = n_it > 0 ? n_it : 0;
-#pragma unroll
-    for (int o = 4; o < WAVE; o <<= 1) {
-        const int y = __shfl_xor(n_it, o, WAVE);
-        n_it = n_it > y ? n_it : y;
-    }
-    for (int it = 0; it < n_it; ++it) {
-        const int i = lo + q + 4 * it;
-        uint64_t x = ~0ull;
-        if (i < hi) {
-            const float4 P = sh.nb_p[i];
-            const float d2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, tj);
-            if (d2 <= R2) x = ((uint64_t)__float_as_uint(d2) << 32) | __float_as_uint(P.w);
-        }
-        // branch-free insertion: a key of ~0 leaves the list unchanged
-#pragma unroll
-        for (int k = 0; k < KT; ++k) {
-            const uint64_t lo64 = umin64(kd[k], x);
-            x = umax64(kd[k], x);
-            kd[k] = lo64;
-        }
-    }
-    uint64_t other[KT];
-#pragma unroll
-    for (int k = 0; k < KT; ++k) other[k] = xor_lane_u64<1>(kd[k]);
-    merge_low<KT>(kd, other);
-#pragma unroll
-    for (int k = 0; k < KT; ++k) other[k] = xor_lane_u64<2>(kd[k]);
-    merge_low<KT>(kd, other);
+    knn_window<KT>(g, sh, tj, R2, lo, hi, kd);
 }
 
 // Candidate walk.  Candidates (the neighbours in (t, index) order) are
@@ -544,7 +586,7 @@ __device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom
         int kc = 0;
         if (j < m) {
             tj = sh.nb_t[j];
-            const float Rj = search_radius(c.radius, c.inv_tref, tj);
+            const float Rj = rho_at(c, g, tj);
             float sum = 0.0f;
 #pragma unroll
             for (int k = 0; k < KT; ++k) {
@@ -583,6 +625,117 @@ __device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom
             if ((smask >> gl) & 1ull)
                 emit(sel0 + popc64(smask & ((1ull << gl) - 1ull)), l & 3, tj, kd, kc);
         }
+    }
+    return sel;
+}
+
+__device__ __forceinline__ int wave_min_i32(int v)
+{
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int y = __shfl_xor(v, o, WAVE);
+        v = v < y ? v : y;
+    }
+    return v;
+}
+
+// Uniform multi-surface sampling on the same neighbour list (the baseline of
+// Sec. 3.5): positions t_k = t_near + (k + 1/2) step, k < ms_steps; a position
+// is a sample when some listed point lies within R_k = rho(t_k) of it (the
+// exact test), in depth order up to S, with its K nearest listed points.
+// Only positions near a listed point can pass: |t_k - t_i| <= dist and
+// rho(t_k) <= rho(t_i) + s |t_k - t_i| (s: the slope of rho), so
+// |t_k - t_i| <= rho(t_i) / (1 - s); lane i turns that into a range of k
+// (one extra position on each side), and batches of 16 positions jump
+// from range to range.  emit() as for the candidate walk; first_idx is the
+// nearest point of the first sample.
+template <int KT, typename Emit>
+__device__ __forceinline__ int uniform_samples(const SearchCtx &c, const RayGeom &g, SearchLds &sh,
+                                               uint64_t top, int m, int &first_idx, Emit emit)
+{
+    const int l = lane_id();
+    lds_sync();
+    if (l < m) {
+        const int idxj = (int)(uint32_t)top;
+        const int slot = c.slot_of[(int64_t)g.vi * c.n_points + idxj];
+        sh.nb_p[l] = c.pts[slot];
+        sh.nb_t[l] = __uint_as_float((uint32_t)(top >> 32));
+    }
+    lds_sync();
+    first_idx = -1;
+    if (m == 0) return 0;
+    constexpr int NONE = 0x7fffffff;
+    const int nk = c.ms_steps;
+    const float step = (c.t_far - c.t_near) / (float)nk;
+    const float slope = c.rmode == HP_RADIUS_LINEAR ? c.radius * c.inv_tref : g.kappa;
+    int klo = NONE, khi = -1;
+    if (l < m) {
+        klo = 0;
+        khi = nk - 1;
+        if (slope < 0.999f) {
+            const float ti = sh.nb_t[l];
+            const float B = (rho_at(c, g, ti) / (1.0f - slope)) * 1.001f + ti * 4e-6f + 1e-6f;
+            float flo = (ti - B - c.t_near) / step - 0.5f;
+            float fhi = (ti + B - c.t_near) / step - 0.5f;
+            flo = __builtin_fminf(__builtin_fmaxf(flo, -2.0f), (float)nk + 2.0f);
+            fhi = __builtin_fminf(__builtin_fmaxf(fhi, -2.0f), (float)nk + 2.0f);
+            klo = max((int)__builtin_floorf(flo) - 1, 0);
+            khi = min((int)__builtin_ceilf(fhi) + 1, nk - 1);
+        }
+        if (klo > khi) {
+            klo = NONE;
+            khi = -1;
+        }
+    }
+    int sel = 0;
+    int b = wave_min_i32(klo);
+    const int gp = l >> 2;
+    while (b < nk && sel < c.S) {
+        const int k = b + gp;
+        const bool active = k < nk;
+        float tk = 0.0f, R2 = 0.0f;
+        int wlo = 0, whi = 0;
+        if (active) {
+            tk = fma_rn((float)k + 0.5f, step, c.t_near);
+            const float Rk = rho_at(c, g, tk);
+            R2 = Rk * Rk;
+            const float span = Rk * 1.001f + tk * 4e-6f + 1e-7f;
+            const float tlo = tk - span, thi = tk + span;
+            int a = 0, e = m;
+            while (a < e) {
+                const int mid = (a + e) >> 1;
+                if (sh.nb_t[mid] < tlo) a = mid + 1;
+                else e = mid;
+            }
+            wlo = a;
+            e = m;
+            while (a < e) {
+                const int mid = (a + e) >> 1;
+                if (sh.nb_t[mid] <= thi) a = mid + 1;
+                else e = mid;
+            }
+            whi = a;
+        }
+        uint64_t kd[KT];
+        knn_window<KT>(g, sh, tk, R2, wlo, whi, kd);
+        const bool kept = active && kd[0] != ~0ull;
+        const uint64_t km = ballot(kept && (l & 3) == 0);  // bit 4 p: position b + p kept
+        const int room = c.S - sel;
+        const int rank = popc64(km & ((1ull << (4 * gp)) - 1ull));
+        if (km) {
+            if (sel == 0) first_idx = readlane_i32((int)(uint32_t)kd[0], __builtin_ctzll(km));
+            if (kept && rank < room) {
+                int kc = 0;
+#pragma unroll
+                for (int q = 0; q < KT; ++q) kc += (q < c.K && kd[q] != ~0ull) ? 1 : 0;
+                emit(sel + rank, l & 3, tk, kd, kc);
+            }
+            const int nkept = popc64(km);
+            sel += nkept < room ? nkept : room;
+        }
+        // next batch: the first position >= b + 16 that some range covers
+        const int nb = b + 16;
+        b = wave_min_i32(khi >= nb ? (klo > nb ? klo : nb) : NONE);
     }
     return sel;
 }

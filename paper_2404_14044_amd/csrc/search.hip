@@ -7,7 +7,7 @@ namespace hp {
 // Persistent: each 64-lane workgroup takes chunks of c.chunk
 // consecutive rays (neighbouring pixels share table buckets), striding by the
 // grid size so that every workgroup sees a mix of empty and busy regions.
-template <int KT>
+template <int KT, bool MS>
 __device__ __forceinline__ void search_sample_body(const SearchCtx &c, const SampleOut &o)
 {
     __shared__ SearchLds sh;
@@ -23,9 +23,7 @@ __device__ __forceinline__ void search_sample_body(const SearchCtx &c, const Sam
             const int m = count < c.M ? count : c.M;
             const int64_t rbase = ray * c.S;
             int prim;
-            const int nsel = walk_candidates<KT>(
-                c, g, sh, top, m, prim,
-                [&](int s, int q, float tj, const uint64_t(&kd)[KT], int kc) {
+            auto emit = [&](int s, int q, float tj, const uint64_t(&kd)[KT], int kc) {
                     // the candidate's four lanes share the row: lane q writes k = q, q + 4, ...
                     const int64_t row = rbase + s;
                     if (q == 0) o.t[row] = tj;
@@ -38,7 +36,10 @@ __device__ __forceinline__ void search_sample_body(const SearchCtx &c, const Sam
                                 v ? __builtin_sqrtf(__uint_as_float((uint32_t)(kd[k] >> 32))) : 0.0f;
                         }
                     }
-                });
+                };
+            int nsel;
+            if constexpr (MS) nsel = uniform_samples<KT>(c, g, sh, top, m, prim, emit);
+            else nsel = walk_candidates<KT>(c, g, sh, top, m, prim, emit);
             if (l == 0) {
                 o.n_sel[ray] = nsel;
                 o.n_nbr[ray] = m;
@@ -59,14 +60,26 @@ __device__ __forceinline__ void search_sample_body(const SearchCtx &c, const Sam
 // The phases are latency bound, so occupancy matters more than registers:
 // ask for 8 waves per SIMD where the nearest-neighbour lists are short.
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)))
-k_search_sample_k4(SearchCtx c, SampleOut o) { search_sample_body<4>(c, o); }
+k_search_sample_k4(SearchCtx c, SampleOut o) { search_sample_body<4, false>(c, o); }
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)))
-k_search_sample_k8(SearchCtx c, SampleOut o) { search_sample_body<8>(c, o); }
+k_search_sample_k8(SearchCtx c, SampleOut o) { search_sample_body<8, false>(c, o); }
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)))
-k_search_sample_k16(SearchCtx c, SampleOut o) { search_sample_body<16>(c, o); }
+k_search_sample_k16(SearchCtx c, SampleOut o) { search_sample_body<16, false>(c, o); }
 __global__ void __launch_bounds__(WAVE) k_search_sample_k32(SearchCtx c, SampleOut o)
 {
-    search_sample_body<32>(c, o);
+    search_sample_body<32, false>(c, o);
+}
+
+// The same search with the uniform multi-surface sampler.
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_search_ms_k4(SearchCtx c, SampleOut o) { search_sample_body<4, true>(c, o); }
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_search_ms_k8(SearchCtx c, SampleOut o) { search_sample_body<8, true>(c, o); }
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_search_ms_k16(SearchCtx c, SampleOut o) { search_sample_body<16, true>(c, o); }
+__global__ void __launch_bounds__(WAVE) k_search_ms_k32(SearchCtx c, SampleOut o)
+{
+    search_sample_body<32, true>(c, o);
 }
 
 hipError_t launch_search_sample(const SearchCtx &c, const SampleOut &o, int kt, hipStream_t s)
@@ -76,6 +89,15 @@ hipError_t launch_search_sample(const SearchCtx &c, const SampleOut &o, int kt, 
     const int64_t blocks = chunks < cap ? chunks : cap;
     if (blocks == 0) return hipSuccess;
     const dim3 grid((unsigned)blocks), block(WAVE);
+    if (c.sampler == HP_SAMPLER_MS) {
+        switch (kt) {
+        case 4: k_search_ms_k4<<<grid, block, 0, s>>>(c, o); break;
+        case 8: k_search_ms_k8<<<grid, block, 0, s>>>(c, o); break;
+        case 16: k_search_ms_k16<<<grid, block, 0, s>>>(c, o); break;
+        default: k_search_ms_k32<<<grid, block, 0, s>>>(c, o); break;
+        }
+        return hipGetLastError();
+    }
     switch (kt) {
     case 4: k_search_sample_k4<<<grid, block, 0, s>>>(c, o); break;
     case 8: k_search_sample_k8<<<grid, block, 0, s>>>(c, o); break;

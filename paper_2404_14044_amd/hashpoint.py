@@ -18,11 +18,13 @@ LIB_PATH = os.path.join(_HERE, "libhashpoint.so")
 HP_OK, HP_E_INVALID, HP_E_WORKSPACE, HP_E_UNSUPPORTED, HP_E_CAPACITY, HP_E_HIP = range(6)
 HP_FP32, HP_BF16 = 0, 1
 HP_LAYOUT_ROWMAJOR, HP_LAYOUT_TILED = 0, 1
+HP_RADIUS_LINEAR, HP_RADIUS_EQ3, HP_RADIUS_EQ3_AF, HP_RADIUS_EQ3_AE = 0, 1, 2, 3
+HP_SAMPLER_PS, HP_SAMPLER_MS = 0, 1
 HP_MAX_VIEWS = 32
 FEAT_DIM = 32
 HIDDEN = 64
 
-EXPORTED = ["hp_table_workspace", "hp_view_bounds", "hp_build_table", "hp_search_sample",
+EXPORTED = ["hp_table_workspace", "hp_view_bounds", "hp_paper_kernel_size", "hp_build_table", "hp_search_sample",
             "hp_render", "hp_backward_workspace", "hp_render_backward",
             "hp_backward_samples_workspace", "hp_render_backward_samples", "hp_status_str",
             "hp_last_hip_error"]
@@ -47,7 +49,9 @@ class HPParams(ctypes.Structure):
                 ("eps_w", ctypes.c_float), ("eps_idw", ctypes.c_float),
                 ("delta_last", ctypes.c_float), ("bg", ctypes.c_float * 3),
                 ("layout", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("search_chunk", ctypes.c_int32), ("search_blocks", ctypes.c_int32)]
+                ("search_chunk", ctypes.c_int32), ("search_blocks", ctypes.c_int32),
+                ("radius_mode", ctypes.c_int32), ("rddot", ctypes.c_float),
+                ("sampler", ctypes.c_int32), ("ms_steps", ctypes.c_int32)]
 
 
 class HPViewInfo(ctypes.Structure):
@@ -93,6 +97,8 @@ def lib():
         L.hp_table_workspace.argtypes = [i64, P, i32, P, P]
         L.hp_view_bounds.restype = i32
         L.hp_view_bounds.argtypes = [P, P, P, P]
+        L.hp_paper_kernel_size.restype = i32
+        L.hp_paper_kernel_size.argtypes = [P, P, P]
         L.hp_build_table.restype = i32
         L.hp_build_table.argtypes = [P, i64, P, i32, P, P, ctypes.c_size_t, P, P]
         L.hp_search_sample.restype = i32
@@ -144,6 +150,10 @@ def make_params(p) -> HPParams:
     s.layout, s.flags = int(getattr(p, "layout", 0)), int(getattr(p, "flags", 0))
     s.search_chunk = int(getattr(p, "search_chunk", 0))
     s.search_blocks = int(getattr(p, "search_blocks", 0))
+    s.radius_mode = int(getattr(p, "radius_mode", 0))
+    s.rddot = float(getattr(p, "rddot", 0.0))
+    s.sampler = int(getattr(p, "sampler", 0))
+    s.ms_steps = int(getattr(p, "ms_steps", 0))
     return s
 
 
@@ -175,6 +185,15 @@ def view_bounds(cam, params):
     _check(lib().hp_view_bounds(ctypes.byref(c), ctypes.byref(p), ctypes.byref(g), ctypes.byref(d)),
            "hp_view_bounds")
     return g.value, d.value
+
+
+def paper_kernel_size(cam, params) -> int:
+    """The paper's search-kernel size s = 2 ceil(rddot / rdot) + 1 (Sec. 3.2)."""
+    out = ctypes.c_int32()
+    c, p = make_camera(cam), make_params(params)
+    _check(lib().hp_paper_kernel_size(ctypes.byref(c), ctypes.byref(p), ctypes.byref(out)),
+           "hp_paper_kernel_size")
+    return out.value
 
 
 def table_workspace(n: int, cams, params) -> int:

@@ -94,6 +94,10 @@ class Params:
         its two small-angle variants (AB replaced by AF, by AE); rho = t kappa
         with kappa per pixel.  `eq3_rddot` picks rddot so that the principal
         pixel's radius at t_near is `radius`.
+    sampler, ms_steps: sampler 0 is the adaptive primary-surface walk
+        (Sec. 3.3); sampler 1 the uniform multi-surface baseline (Sec. 3.5):
+        ms_steps uniform positions along [t_near, t_far], each kept when a
+        point of the ray's neighbour list lies within rho of it.
     t_near, t_far: sampling range along the ray (Sec. 3.2).
     K: neighbours per sample (Eq. 4).  n_samples: cap on samples per ray.
     m_cap: cap on the per-ray neighbour list.
@@ -122,6 +126,8 @@ class Params:
     search_blocks: int = 0
     radius_mode: int = 0
     rddot: float = 0.0
+    sampler: int = 0
+    ms_steps: int = 0
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

@@ -38,8 +38,8 @@ def gpu_table_lists(tab, view=0):
     return info, offs, perm
 
 
-def compare_table_rowmajor(sc, tab, view=0):
-    cam, p = sc.cams[view], sc.params
+def compare_table_rowmajor(sc, tab, view=0, params=None):
+    cam, p = sc.cams[view], params or sc.params
     g = oracle.guard(cam, p)
     info, offs, perm = gpu_table_lists(tab, view)
     assert info.g == g

@@ -35,7 +35,7 @@ def test_exports_every_declared_function():
 def test_struct_sizes_match_header():
     # pointer-sized fields and int64 alignment as the C compiler lays them out
     assert ctypes.sizeof(hp.HPCamera) == 4 * 18
-    assert ctypes.sizeof(hp.HPParams) == 4 * 19
+    assert ctypes.sizeof(hp.HPParams) == 4 * 23
     assert ctypes.sizeof(hp.HPViewInfo) == 32
     assert ctypes.sizeof(hp.HPSamples) == 8 * 9
     assert ctypes.sizeof(hp.HPMlp) == 8 * 6
@@ -166,3 +166,35 @@ def test_backward_workspace_holds_the_recomputed_samples():
         S, K = p.n_samples, p.K
         assert n >= part + R * (4 * 4 + S * 4 + 2 * S * K * 4)
         assert n <= part + R * (4 * 4 + S * 4 + 2 * S * K * 4) + 8 * 256
+
+
+def test_radius_modes_validated_and_bounded_like_the_oracle():
+    import oracle
+    sc = scenes.objects_1m(n=1000, res=64)
+    cam = sc.cams[0]
+    for mode in (1, 2, 3):
+        p = sc.params.replace(radius_mode=mode, rddot=scenes.eq3_rddot(mode, sc.params.radius,
+                                                                       sc.params.t_near))
+        g, _ = hp.view_bounds(cam, p)
+        assert g == oracle.guard(cam, p)
+        assert hp.paper_kernel_size(cam, p) == oracle.paper_s(cam, p)
+    assert hp.paper_kernel_size(cam, sc.params) == oracle.paper_s(cam, sc.params)
+    pp = hp.make_params(sc.params.replace(radius_mode=1, rddot=0.0))
+    c = hp.make_camera(cam)
+    g = ctypes.c_int32()
+    assert hp.lib().hp_view_bounds(ctypes.byref(c), ctypes.byref(pp), ctypes.byref(g), None) == hp.HP_E_INVALID
+    for mode, rdd in ((4, 0.01), (-1, 0.01), (0, 0.01), (2, 1.5), (3, float("nan"))):
+        pp = hp.make_params(sc.params.replace(radius_mode=mode, rddot=rdd))
+        assert hp.lib().hp_view_bounds(ctypes.byref(c), ctypes.byref(pp), ctypes.byref(g), None) == hp.HP_E_INVALID
+
+
+def test_sampler_parameters_validated():
+    sc = scenes.sphere_plane(n_sphere=10, n_plane=10)
+    c = hp.make_camera(sc.cams[0])
+    g = ctypes.c_int32()
+    ok = [(0, 0), (1, 1), (1, 4096), (1, 1 << 24)]
+    bad = [(0, 5), (1, 0), (1, -3), (1, (1 << 24) + 1), (2, 10), (-1, 0)]
+    for sampler, steps in ok + bad:
+        pp = hp.make_params(sc.params.replace(sampler=sampler, ms_steps=steps))
+        st = hp.lib().hp_view_bounds(ctypes.byref(c), ctypes.byref(pp), ctypes.byref(g), None)
+        assert st == (hp.HP_OK if (sampler, steps) in ok else hp.HP_E_INVALID), (sampler, steps)

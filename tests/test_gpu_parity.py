@@ -63,6 +63,68 @@ def test_sphere_plane_cone_radius(sphere_plane):
     compare_exact(sc, out["samples"], _all_pix(sc.cams[0]), params=p)
 
 
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_sphere_plane_eq3_radius(sphere_plane, mode):
+    """Per-pixel cone of Eq. 3 and its small-angle variants, full image."""
+    sc = sphere_plane
+    p = sc.params.replace(radius_mode=mode,
+                          rddot=scenes.eq3_rddot(mode, sc.params.radius, sc.params.t_near))
+    out = gpu_forward(sc, params=p)
+    compare_table_rowmajor(sc, out["table"], params=p)
+    ex = compare_exact(sc, out["samples"], _all_pix(sc.cams[0]), params=p)
+    assert (ex["n_sel"] > 0).sum() > 500
+
+
+@pytest.mark.parametrize("mode", [1, 3])
+def test_objects_eq3_radius_sampled_rays(objects, mode):
+    sc = objects
+    from paper_2404_14044_amd import hashpoint as hp
+    p = sc.params.replace(radius_mode=mode,
+                          rddot=scenes.eq3_rddot(mode, sc.params.radius, sc.params.t_near))
+    out = gpu_forward(sc, params=p, precision=hp.HP_FP32)
+    pix = sample_pixels(sc.cams[0], 2048, seed=23 + mode)
+    ex = compare_exact(sc, out["samples"], pix, params=p)
+    assert (ex["n_sel"] > 0).sum() > 200
+    err = render_error(sc, out["render"], ex, pix, params=p)
+    assert err["rgb"] <= FP32_TOL
+
+
+def test_sphere_plane_multi_surface(sphere_plane):
+    """Uniform multi-surface sampler, full image: both the sphere's surfaces
+    and the plane behind it."""
+    sc = sphere_plane
+    p = sc.params.replace(sampler=1, ms_steps=600, n_samples=32)
+    out = gpu_forward(sc, params=p)
+    ex = compare_exact(sc, out["samples"], _all_pix(sc.cams[0]), params=p)
+    assert (ex["n_sel"] > 4).sum() > 300
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_objects_multi_surface_sampled_rays(objects, mode):
+    sc = objects
+    from paper_2404_14044_amd import hashpoint as hp
+    p = sc.params.replace(sampler=1, ms_steps=400, n_samples=64)
+    if mode:
+        p = p.replace(radius_mode=mode, rddot=scenes.eq3_rddot(mode, p.radius, p.t_near))
+    out = gpu_forward(sc, params=p, precision=hp.HP_FP32)
+    pix = sample_pixels(sc.cams[0], 1024, seed=31 + mode)
+    ex = compare_exact(sc, out["samples"], pix, params=p)
+    assert (ex["n_sel"] > 0).sum() > 100
+    err = render_error(sc, out["render"], ex, pix, params=p)
+    assert err["rgb"] <= FP32_TOL
+
+
+@pytest.mark.parametrize("gamma", [0.5, 0.1, 0.01])
+def test_objects_gamma_sweep_sampled_rays(objects, gamma):
+    """Smaller gamma moves the walk from the primary surface towards several
+    surfaces (supplement's gamma sweep); the walk stays exact."""
+    sc = objects
+    p = sc.params.replace(gamma=float(np.float32(gamma)), n_samples=64)
+    out = gpu_forward(sc, params=p)
+    pix = sample_pixels(sc.cams[0], 1024, seed=41)
+    compare_exact(sc, out["samples"], pix, params=p)
+
+
 def test_sphere_plane_tiled_layout(sphere_plane):
     sc = sphere_plane
     p = sc.params.replace(layout=1)
