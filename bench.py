@@ -161,6 +161,8 @@ def main():
         result["train_4x400"] = train_leg(sc)
         result["radius_modes"] = radius_modes_leg(sc)
         result["samplers"] = sampler_leg(sc)
+        result["knp"] = knp_leg(sc)
+        result["complexity_sweep"] = scaling_leg()
 
     if args.cpu_seconds > 0:
         result.update(cpu_leg(sc, p, smp, outs, R, args.cpu_seconds))
@@ -297,6 +299,62 @@ def sampler_leg(sc, reps=5):
     for name in out:
         out[name]["speedup_vs_ms"] = ms / out[name]["total_ms"]
     return out
+
+
+def knp_leg(sc, reps=5):
+    """K-NP extraction + Eq. 1 blending (the image-based consumers of the same
+    table and search, NPLF-style K = 8 and Pointersect-style K = 40): build +
+    search + blend per step, no decoder."""
+    import torch
+    from paper_2404_14044_amd import hashpoint as hp
+    from paper_2404_14044_amd import scenes
+    dev = torch.device("cuda:0")
+    cam = sc.cams[0]
+    R = cam.W * cam.H
+    xyz = torch.from_numpy(sc.xyz).to(dev)
+    colors = torch.from_numpy(scenes.point_colors(sc.xyz.shape[0], 9)).to(dev)
+    p = sc.params
+    ws = torch.empty(hp.table_workspace(xyz.shape[0], [cam], p), dtype=torch.uint8, device=dev)
+    tab = hp.build_table(xyz, [cam], p, ws=ws)
+    t_build = _time_ms(lambda: hp.build_table(xyz, [cam], p, ws=ws), reps)
+    out = {}
+    for K in (8, 40):
+        o = {"rgb": torch.empty(R * 3, device=dev), "cnt": torch.empty(R, dtype=torch.int32, device=dev)}
+        t = _time_ms(lambda: hp.knp_blend(tab, p, K, colors, out=o), reps)
+        out[f"K{K}"] = {"knp_ms": t, "total_ms": t_build + t, "mrays_s": R / (t_build + t) / 1e3,
+                        "full_rays": int((o["cnt"] == K).sum().item())}
+    return out
+
+
+def scaling_leg(reps=3):
+    """Complexity check of Sec. 3.5 (build O(n), lookup O(m q)): the object
+    scene at n = 0.25M .. 4M points with one 800x800 view, then n = 1M with
+    views of 200^2 .. 1600^2 rays.  Reports build and search/sample times
+    and their per-point / per-ray costs."""
+    import torch
+    from paper_2404_14044_amd import hashpoint as hp
+    from paper_2404_14044_amd import scenes
+    dev = torch.device("cuda:0")
+
+    def run(n, res):
+        sc = scenes.objects_1m(n=n, res=res)
+        cam, p = sc.cams[0], sc.params
+        xyz = torch.from_numpy(sc.xyz).to(dev)
+        ws = torch.empty(hp.table_workspace(n, [cam], p), dtype=torch.uint8, device=dev)
+        tab = hp.build_table(xyz, [cam], p, ws=ws)
+        smp = hp.alloc_samples(tab.n_rays, p, dev)
+        tb = _time_ms(lambda: hp.build_table(xyz, [cam], p, ws=ws), reps)
+        tsr = _time_ms(lambda: hp.search_sample(tab, p, out=smp), reps)
+        nn = smp["n_nbr"].float()
+        res_d = {"n": n, "rays": tab.n_rays, "build_ms": tb, "search_ms": tsr,
+                 "build_ns_per_point": tb * 1e6 / n, "search_ns_per_ray": tsr * 1e6 / tab.n_rays,
+                 "mean_neighbours_per_ray": float(nn.mean().item())}
+        del ws, tab, smp, xyz
+        return res_d
+
+    by_n = [run(n, 800) for n in (250_000, 500_000, 1_000_000, 2_000_000, 4_000_000)]
+    by_m = [run(1_000_000, r) for r in (200, 400, 800, 1600)]
+    return {"by_points": by_n, "by_rays": by_m}
 
 
 def train_leg(sc, reps=5):

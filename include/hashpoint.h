@@ -20,6 +20,7 @@
  *   hp_render           - aggregation, MLP, compositing     (Sec. 3.4, Eq. 2)
  *   hp_render_backward  - gradient of the render            (Sec. 3.4, Eq. 2)
  *   hp_render_backward_samples - the same from kept samples
+ *   hp_knp_blend        - K nearest points to each ray, Eq. 1 blend (Sec. 3.1)
  *
  * General rules
  *  - All buffers are caller-owned.  Pointers documented "device" are HIP
@@ -248,6 +249,24 @@ hp_status hp_search_sample(const hp_table *tab, const hp_camera *cams, int32_t n
 hp_status hp_render(const hp_samples *smp, int64_t R, const float *feat, int32_t C,
                     const hp_mlp *mlp, int32_t precision, const hp_params *p, float *rgb,
                     float *depth, float *acc, void *stream);
+
+/* K-NP extraction and image-based blending (Sec. 3.1, Eq. 1) on the same
+ * table and search: for every ray, the K points nearest to the ray among its
+ * neighbours (points within rho(t) of it, t in [t_near, t_far]; all of them,
+ * m_cap does not apply), ordered by (binary32 squared distance to the ray,
+ * point index), and c(r) = sum_i w_i c_i / sum_i w_i with
+ * w_i = 1 / max(e_i, eps_idw), e_i = sqrt of that squared distance, in FP32;
+ * rays without a neighbour get bg.  The sampler fields of p are ignored.
+ *  cams, n_views, p: as given to hp_build_table.  K: 1..HP_MAX_MCAP.
+ *  colors: device, n_points x 3 FP32 per-point colours.
+ *  rgb: device, R x 3 FP32 output (R = tab->n_rays).
+ *  knp_cnt (R, nullable), knp_idx / knp_dist (R x K, both or neither):
+ *      device outputs, the count min(K, neighbours) and the list (padded with
+ *      -1 / 0).
+ * Errors: HP_E_INVALID, HP_E_UNSUPPORTED (K out of range). */
+hp_status hp_knp_blend(const hp_table *tab, const hp_camera *cams, int32_t n_views,
+                       const hp_params *p, int32_t K, const float *colors, float *rgb,
+                       int32_t *knp_cnt, int32_t *knp_idx, float *knp_dist, void *stream);
 
 /* Workspace bytes hp_render_backward needs for this table and these
  * parameters (host only): per-workgroup decoder-gradient slices plus the

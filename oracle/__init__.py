@@ -74,6 +74,7 @@ def lib():
         _lib.or_table.restype = i64
         _lib.or_table.argtypes = [P, i64, P, i32, P, P]
         _lib.or_ray_dir.argtypes = [P, i32, i32, P]
+        _lib.or_knp.argtypes = [P, i64, P, P, P, i64, i32, P, P, P, P, P]
         _lib.or_paper_s.restype = i32
         _lib.or_paper_s.argtypes = [P, P]
         _lib.or_kappa.restype = ctypes.c_float
@@ -175,6 +176,23 @@ def ray_dir(cam, u: int, v: int) -> np.ndarray:
     c = camera_struct(cam)
     lib().or_ray_dir(ctypes.byref(c), int(u), int(v), _ptr(d))
     return d
+
+
+def knp(pc: np.ndarray, cam, params, K: int, colors: np.ndarray,
+        pix: Optional[Sequence[int]] = None) -> Dict[str, np.ndarray]:
+    """K nearest points to each ray among its neighbours and their Eq. 1 blend."""
+    pc = np.ascontiguousarray(pc, np.float32)
+    colors = np.ascontiguousarray(colors, np.float32)
+    if pix is None:
+        pix = np.arange(cam.W * cam.H, dtype=np.int32)
+    pix = np.ascontiguousarray(pix, np.int32)
+    R = pix.size
+    out = {"cnt": np.empty(R, np.int32), "idx": np.empty((R, K), np.int32),
+           "dist": np.empty((R, K), np.float32), "rgb": np.empty((R, 3), np.float64)}
+    c, p = camera_struct(cam), params_struct(params)
+    lib().or_knp(_ptr(pc), pc.shape[0], ctypes.byref(c), ctypes.byref(p), _ptr(pix), R, int(K),
+                 _ptr(colors), _ptr(out["cnt"]), _ptr(out["idx"]), _ptr(out["dist"]), _ptr(out["rgb"]))
+    return out
 
 
 def exact(pc: np.ndarray, cam, params, pix: Optional[Sequence[int]] = None,

@@ -475,6 +475,71 @@ void or_exact(const float *pc, int64_t n, const orc_camera *cam, const orc_param
 }
 
 /* ------------------------------------------------------------------------ */
+/* K-NP extraction and image-based blending (Sec. 3.1, Eq. 1), the other    */
+/* consumer of the neighbour search: the K points nearest to the ray among  */
+/* its neighbours (points within rho(t) of it, t in [t_near, t_far]),        */
+/* ordered by (squared distance to the ray e^2, index), with geometric       */
+/* blending weights.  Reading: w_i = 1 / max(e_i, eps_idw), normalised, and  */
+/* per-point colours c_i; a ray without neighbours returns bg.  Selection   */
+/* is exact binary32 (e^2 as in the search); blending in binary64.          */
+/* Outputs per ray r: knp_cnt[r], knp_idx/knp_dist[r*K + k] (k < cnt;       */
+/* rest -1 / 0), rgb[3r..3r+2].                                              */
+/* ------------------------------------------------------------------------ */
+void or_knp(const float *pc, int64_t n, const orc_camera *cam, const orc_params *p,
+            const int32_t *pix, int64_t n_rays, int32_t K, const float *colors,
+            int32_t *knp_cnt, int32_t *knp_idx, float *knp_dist, double *rgb)
+{
+#pragma omp parallel
+    {
+        int64_t cap = 1024;
+        kv_ent *nb = (kv_ent *)malloc((size_t)cap * sizeof(kv_ent));
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t r = 0; r < n_rays; ++r) {
+            const int32_t u = pix[r] % cam->W, v = pix[r] / cam->W;
+            float d[3];
+            or_ray_dir(cam, u, v, d);
+            const float kap = or_ray_kappa(cam, p, u, v);
+            int64_t cnt = 0;
+            for (int64_t i = 0; i < n; ++i) {
+                const float *x = pc + 3 * i;
+                float t = ray_t(x, d);
+                float e2 = dist2_at(x, d, t);
+                float rho = rho_of(p, kap, t);
+                if (!((x[2] > 0.0f) & (t >= p->t_near) & (t <= p->t_far) & (e2 <= rho * rho))) continue;
+                if (cnt == cap) {
+                    cap *= 2;
+                    nb = (kv_ent *)realloc(nb, (size_t)cap * sizeof(kv_ent));
+                }
+                nb[cnt].key = e2;
+                nb[cnt].idx = (int32_t)i;
+                nb[cnt].aux = 0;
+                ++cnt;
+            }
+            qsort(nb, (size_t)cnt, sizeof(kv_ent), cmp_kv);
+            const int kk = (int)(cnt < K ? cnt : K);
+            knp_cnt[r] = kk;
+            double ws = 0.0, c0 = 0.0, c1 = 0.0, c2 = 0.0;
+            for (int k = 0; k < K; ++k) {
+                knp_idx[r * K + k] = k < kk ? nb[k].idx : -1;
+                knp_dist[r * K + k] = k < kk ? sqrtf(nb[k].key) : 0.0f;
+                if (k >= kk) continue;
+                const double e = sqrt((double)nb[k].key);
+                const double w = 1.0 / (e > p->eps_idw ? e : (double)p->eps_idw);
+                const float *c = colors + 3 * (int64_t)nb[k].idx;
+                ws += w;
+                c0 += w * c[0];
+                c1 += w * c[1];
+                c2 += w * c[2];
+            }
+            rgb[3 * r + 0] = kk ? c0 / ws : p->bg[0];
+            rgb[3 * r + 1] = kk ? c1 / ws : p->bg[1];
+            rgb[3 * r + 2] = kk ? c2 / ws : p->bg[2];
+        }
+        free(nb);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Continuous stage in binary64.                                             */
 /*                                                                           */
 /* Feature at a sample (Sec. 3.4: features of the sample's neighbouring      */

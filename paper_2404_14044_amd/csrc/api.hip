@@ -309,6 +309,28 @@ hp_status hp_search_sample(const hp_table *tab, const hp_camera *cams, int32_t n
     return e == hipSuccess ? HP_OK : hip_fail(e);
 }
 
+hp_status hp_knp_blend(const hp_table *tab, const hp_camera *cams, int32_t n_views,
+                       const hp_params *p, int32_t K, const float *colors, float *rgb,
+                       int32_t *knp_cnt, int32_t *knp_idx, float *knp_dist, void *stream)
+{
+    hp::SearchCtx c;
+    const hp_status st = make_ctx(tab, cams, n_views, p, c);
+    if (st != HP_OK) return st;
+    if (K < 1 || K > HP_MAX_MCAP) return HP_E_UNSUPPORTED;
+    if (!colors || !rgb || ((knp_idx == nullptr) != (knp_dist == nullptr))) return HP_E_INVALID;
+    hp::KnpArgs a;
+    a.colors = colors;
+    a.K = K;
+    a.eps_idw = p->eps_idw;
+    for (int i = 0; i < 3; ++i) a.bg[i] = p->bg[i];
+    a.rgb = rgb;
+    a.cnt = knp_cnt;
+    a.idx = knp_idx;
+    a.dist = knp_dist;
+    const hipError_t e = hp::launch_knp(c, a, (hipStream_t)stream);
+    return e == hipSuccess ? HP_OK : hip_fail(e);
+}
+
 hp_status hp_render(const hp_samples *smp, int64_t R, const float *feat, int32_t C,
                     const hp_mlp *mlp, int32_t precision, const hp_params *p, float *rgb,
                     float *depth, float *acc, void *stream)

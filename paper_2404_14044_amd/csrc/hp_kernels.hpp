@@ -46,4 +46,17 @@ hipError_t launch_search_sample(const SearchCtx &c, const SampleOut &o, int kt, 
 
 hipError_t launch_render(const RenderArgs &a, int precision, hipStream_t s);
 
+struct KnpArgs {
+    const float *colors;  // n x 3
+    int32_t K;
+    float eps_idw;
+    float bg[3];
+    float *rgb;     // R x 3
+    int32_t *cnt;   // R, nullable
+    int32_t *idx;   // R x K, nullable (with dist)
+    float *dist;    // R x K
+};
+
+hipError_t launch_knp(const SearchCtx &c, const KnpArgs &a, hipStream_t s);
+
 }  // namespace hp

@@ -73,6 +73,45 @@ struct SearchLds {
     float nb_t[WAVE];
 };
 
+// Rays per XCD band: about 16 image rows of an 800-pixel-wide view.
+constexpr int64_t BAND_RAYS = 12800;
+
+// Persistent iteration over the rays of a launch, one ray at a time per
+// workgroup.  Workgroups take chunks of c.chunk consecutive rays (neighbouring
+// pixels share table buckets).  They are dealt to the eight XCDs round-robin
+// (workgroup b runs on XCD b % 8), each with its own L2, so the chunks are
+// grouped into bands of BAND_RAYS consecutive rays and XCD x takes bands
+// x, x + 8, ...: the rays one XCD's workgroups search at a time are then
+// neighbours and share that L2's table lines.  Within its bands an XCD's
+// workgroups stride by their number, so each still sees a mix of empty and
+// busy regions.  The grid must be a multiple of 8.
+template <typename Body>
+__device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, Body body)
+{
+    const int64_t n_chunks = (c.n_rays + c.chunk - 1) / c.chunk;
+    const int64_t band = (BAND_RAYS + c.chunk - 1) / c.chunk;  // chunks per band
+    const int xcd = blockIdx.x & 7;
+    const int64_t slot = blockIdx.x >> 3, n_slots = gridDim.x >> 3;
+    const int64_t n_bands = (n_chunks + band - 1) / band;
+    const int64_t my_chunks = (n_bands > xcd ? (n_bands - xcd + 7) / 8 : 0) * band;
+    for (int64_t li = slot; li < my_chunks; li += n_slots) {
+        const int64_t ch = (xcd + 8 * (li / band)) * band + li % band;
+        if (ch >= n_chunks) continue;
+        const int64_t r1 = min((ch + 1) * c.chunk, c.n_rays);
+        for (int64_t ray = ch * c.chunk; ray < r1; ++ray) body(ray);
+    }
+}
+
+// Persistent grid for the banded launches: at most `cap` workgroups, a
+// multiple of 8.
+inline int64_t banded_grid(const SearchCtx &c, int64_t cap)
+{
+    const int64_t chunks = (c.n_rays + c.chunk - 1) / c.chunk;
+    int64_t blocks = chunks < cap ? chunks : cap;
+    if (blocks == 0) return 0;
+    return blocks < 8 ? 8 : (blocks & ~(int64_t)7);
+}
+
 // Ray geometry, uniform across the wave.
 struct RayGeom {
     int vi, u, v;
@@ -285,6 +324,9 @@ __device__ __forceinline__ float radius_for_depth(const SearchCtx &c, const RayG
 // Search one ray.  Returns, in `top` (one key per lane, ascending), the
 // 64 smallest (t, index) keys of the ray's neighbours (missing = ~0), and
 // the total neighbour count.
+// BY_E2 orders the kept neighbours by (squared distance to the ray, index)
+// instead of (t, index): the K nearest points to the ray (K-NP, Eq. 1).
+template <bool BY_E2 = false>
 __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayGeom &g,
                                                   SearchLds &sh, uint64_t &top, int &count)
 {
@@ -380,7 +422,7 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
                     const float e2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, t);
                     const float rho = rho_at(c, g, t);
                     pass = (P.z > 0.0f) & (t >= c.t_near) & (t <= c.t_far) & (e2 <= rho * rho);
-                    key = ((uint64_t)__float_as_uint(t) << 32) | __float_as_uint(P.w);
+                    key = ((uint64_t)__float_as_uint(BY_E2 ? e2 : t) << 32) | __float_as_uint(P.w);
                 }
             }
             count += popc64(ballot(pass));

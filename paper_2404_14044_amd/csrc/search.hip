@@ -1,60 +1,54 @@
-// Forward search + sampling kernel: one 64-lane workgroup per ray.
+// Forward search + sampling kernel: one 64-lane workgroup per ray, persistent
+// over XCD-banded chunks of rays (for_each_ray_banded).
 #include "hp_kernels.hpp"
 #include "hp_search.hpp"
 
 namespace hp {
 
-// Persistent: each 64-lane workgroup takes chunks of c.chunk
-// consecutive rays (neighbouring pixels share table buckets), striding by the
-// grid size so that every workgroup sees a mix of empty and busy regions.
 template <int KT, bool MS>
 __device__ __forceinline__ void search_sample_body(const SearchCtx &c, const SampleOut &o)
 {
     __shared__ SearchLds sh;
     const int l = lane_id();
-    const int64_t n_chunks = (c.n_rays + c.chunk - 1) / c.chunk;
-    for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
-        const int64_t r1 = min((ch + 1) * c.chunk, c.n_rays);
-        for (int64_t ray = ch * c.chunk; ray < r1; ++ray) {
-            const RayGeom g = ray_geometry(c, ray);
-            uint64_t top;
-            int count;
-            search_neighbours(c, g, sh, top, count);
-            const int m = count < c.M ? count : c.M;
-            const int64_t rbase = ray * c.S;
-            int prim;
-            auto emit = [&](int s, int q, float tj, const uint64_t(&kd)[KT], int kc) {
-                    // the candidate's four lanes share the row: lane q writes k = q, q + 4, ...
-                    const int64_t row = rbase + s;
-                    if (q == 0) o.t[row] = tj;
+    for_each_ray_banded(c, [&](int64_t ray) {
+        const RayGeom g = ray_geometry(c, ray);
+        uint64_t top;
+        int count;
+        search_neighbours(c, g, sh, top, count);
+        const int m = count < c.M ? count : c.M;
+        const int64_t rbase = ray * c.S;
+        int prim;
+        auto emit = [&](int s, int q, float tj, const uint64_t(&kd)[KT], int kc) {
+            // the candidate's four lanes share the row: lane q writes k = q, q + 4, ...
+            const int64_t row = rbase + s;
+            if (q == 0) o.t[row] = tj;
 #pragma unroll
-                    for (int k = 0; k < KT; ++k) {
-                        if ((k & 3) == q && k < c.K) {
-                            const bool v = k < kc;
-                            o.knn_idx[row * c.K + k] = v ? (int32_t)(uint32_t)kd[k] : -1;
-                            o.knn_dist[row * c.K + k] =
-                                v ? __builtin_sqrtf(__uint_as_float((uint32_t)(kd[k] >> 32))) : 0.0f;
-                        }
-                    }
-                };
-            int nsel;
-            if constexpr (MS) nsel = uniform_samples<KT>(c, g, sh, top, m, prim, emit);
-            else nsel = walk_candidates<KT>(c, g, sh, top, m, prim, emit);
-            if (l == 0) {
-                o.n_sel[ray] = nsel;
-                o.n_nbr[ray] = m;
-                o.flags[ray] = (count > c.M) ? 1u : 0u;
-                o.primary[ray] = prim;
+            for (int k = 0; k < KT; ++k) {
+                if ((k & 3) == q && k < c.K) {
+                    const bool v = k < kc;
+                    o.knn_idx[row * c.K + k] = v ? (int32_t)(uint32_t)kd[k] : -1;
+                    o.knn_dist[row * c.K + k] =
+                        v ? __builtin_sqrtf(__uint_as_float((uint32_t)(kd[k] >> 32))) : 0.0f;
+                }
             }
-            const float tj = __uint_as_float((uint32_t)(top >> 32));
-            const int idxj = (int)(uint32_t)top;
-            if (o.nbr_idx && l < c.M) {
-                o.nbr_idx[ray * c.M + l] = l < m ? idxj : -1;
-                o.nbr_t[ray * c.M + l] = l < m ? tj : 0.0f;
-            }
-            lds_sync();
+        };
+        int nsel;
+        if constexpr (MS) nsel = uniform_samples<KT>(c, g, sh, top, m, prim, emit);
+        else nsel = walk_candidates<KT>(c, g, sh, top, m, prim, emit);
+        if (l == 0) {
+            o.n_sel[ray] = nsel;
+            o.n_nbr[ray] = m;
+            o.flags[ray] = (count > c.M) ? 1u : 0u;
+            o.primary[ray] = prim;
         }
-    }
+        const float tj = __uint_as_float((uint32_t)(top >> 32));
+        const int idxj = (int)(uint32_t)top;
+        if (o.nbr_idx && l < c.M) {
+            o.nbr_idx[ray * c.M + l] = l < m ? idxj : -1;
+            o.nbr_t[ray * c.M + l] = l < m ? tj : 0.0f;
+        }
+        lds_sync();
+    });
 }
 
 // The phases are latency bound, so occupancy matters more than registers:
@@ -84,9 +78,7 @@ __global__ void __launch_bounds__(WAVE) k_search_ms_k32(SearchCtx c, SampleOut o
 
 hipError_t launch_search_sample(const SearchCtx &c, const SampleOut &o, int kt, hipStream_t s)
 {
-    const int64_t chunks = (c.n_rays + c.chunk - 1) / c.chunk;
-    const int64_t cap = c.blocks > 0 ? c.blocks : 8192;
-    const int64_t blocks = chunks < cap ? chunks : cap;
+    const int64_t blocks = banded_grid(c, c.blocks > 0 ? c.blocks : 8192);
     if (blocks == 0) return hipSuccess;
     const dim3 grid((unsigned)blocks), block(WAVE);
     if (c.sampler == HP_SAMPLER_MS) {

@@ -26,7 +26,8 @@ HIDDEN = 64
 
 EXPORTED = ["hp_table_workspace", "hp_view_bounds", "hp_paper_kernel_size", "hp_build_table", "hp_search_sample",
             "hp_render", "hp_backward_workspace", "hp_render_backward",
-            "hp_backward_samples_workspace", "hp_render_backward_samples", "hp_status_str",
+            "hp_backward_samples_workspace", "hp_render_backward_samples", "hp_knp_blend",
+            "hp_status_str",
             "hp_last_hip_error"]
 
 
@@ -109,6 +110,8 @@ def lib():
         L.hp_backward_workspace.argtypes = [P, P, P]
         L.hp_render_backward.restype = i32
         L.hp_render_backward.argtypes = [P, P, i32, P, i32, P, i32, P, P, P, P, P, ctypes.c_size_t, P]
+        L.hp_knp_blend.restype = i32
+        L.hp_knp_blend.argtypes = [P, P, i32, P, i32, P, P, P, P, P, P]
         L.hp_backward_samples_workspace.restype = ctypes.c_size_t
         L.hp_backward_samples_workspace.argtypes = [P, P]
         L.hp_render_backward_samples.restype = i32
@@ -309,6 +312,27 @@ def render(samples: Dict[str, torch.Tensor], n_rays: int, feat: torch.Tensor,
                            out["depth"].data_ptr() if out.get("depth") is not None else None,
                            out["acc"].data_ptr() if out.get("acc") is not None else None,
                            _stream(stream)), "hp_render")
+    return out
+
+
+def knp_blend(table: Table, params, K: int, colors: torch.Tensor, lists: bool = True,
+              out: Optional[Dict[str, torch.Tensor]] = None, stream=None) -> Dict[str, torch.Tensor]:
+    """K nearest points to every ray and their Eq. 1 blend of per-point colours."""
+    params = params or table.params
+    R, dev = table.n_rays, table.ws.device
+    if out is None:
+        out = {"rgb": torch.empty(R * 3, dtype=torch.float32, device=dev),
+               "cnt": torch.empty(R, dtype=torch.int32, device=dev)}
+        if lists:
+            out["idx"] = torch.empty(R * K, dtype=torch.int32, device=dev)
+            out["dist"] = torch.empty(R * K, dtype=torch.float32, device=dev)
+    arr, p = _cams_array(table.cams), make_params(params)
+    _check(lib().hp_knp_blend(ctypes.byref(table.tab), arr, len(table.cams), ctypes.byref(p), int(K),
+                              _dev(colors, torch.float32, "colors"), out["rgb"].data_ptr(),
+                              out["cnt"].data_ptr() if "cnt" in out else None,
+                              out["idx"].data_ptr() if "idx" in out else None,
+                              out["dist"].data_ptr() if "dist" in out else None, _stream(stream)),
+           "hp_knp_blend")
     return out
 
 

@@ -144,6 +144,11 @@ def eq3_rddot(mode: int, radius: float, t_near: float) -> float:
     return float(np.float32(r / tn))
 
 
+def point_colors(n: int, seed: int) -> np.ndarray:
+    """Per-point RGB in [0, 1] for image-based blending (Eq. 1), seeded."""
+    return np.random.default_rng(seed).random((n, 3)).astype(np.float32)
+
+
 def default_params(radius, t_near, t_far, K, S, inv_tref=0.0) -> Params:
     r = float(np.float32(radius))
     return Params(radius=r, inv_tref=float(np.float32(inv_tref)),

@@ -198,3 +198,15 @@ def test_sampler_parameters_validated():
         pp = hp.make_params(sc.params.replace(sampler=sampler, ms_steps=steps))
         st = hp.lib().hp_view_bounds(ctypes.byref(c), ctypes.byref(pp), ctypes.byref(g), None)
         assert st == (hp.HP_OK if (sampler, steps) in ok else hp.HP_E_INVALID), (sampler, steps)
+
+
+def test_knp_blend_rejects_bad_arguments_without_launching():
+    sc = scenes.sphere_plane(n_sphere=10, n_plane=10)
+    L = hp.lib()
+    arr, pp = hp._cams_array(sc.cams), hp.make_params(sc.params)
+    fake = ctypes.c_void_p(0x1000)
+    tab = hp.HPTable()
+    assert L.hp_knp_blend(ctypes.byref(tab), arr, 1, ctypes.byref(pp), 8, fake, fake, None, None, None,
+                          None) == hp.HP_E_INVALID
+    assert L.hp_knp_blend(None, arr, 1, ctypes.byref(pp), 8, fake, fake, None, None, None,
+                          None) == hp.HP_E_INVALID
