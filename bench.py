@@ -162,6 +162,7 @@ def main():
         result["radius_modes"] = radius_modes_leg(sc)
         result["samplers"] = sampler_leg(sc)
         result["knp"] = knp_leg(sc)
+        result["fused"] = fused_leg(sc)
         result["complexity_sweep"] = scaling_leg()
 
     if args.cpu_seconds > 0:
@@ -355,6 +356,35 @@ def scaling_leg(reps=3):
     by_n = [run(n, 800) for n in (250_000, 500_000, 1_000_000, 2_000_000, 4_000_000)]
     by_m = [run(1_000_000, r) for r in (200, 400, 800, 1600)]
     return {"by_points": by_n, "by_rays": by_m}
+
+
+def fused_leg(sc, reps=10):
+    """Search + sampling + render in one launch (samples stay on chip) vs the
+    two launches of the main step, BF16, same table."""
+    import torch
+    from paper_2404_14044_amd import hashpoint as hp
+    dev = torch.device("cuda:0")
+    cam, p = sc.cams[0], sc.params
+    R = cam.W * cam.H
+    xyz = torch.from_numpy(sc.xyz).to(dev)
+    feat = torch.from_numpy(sc.feat).to(dev)
+    mlp = hp.to_device_mlp(sc.mlp, dev)
+    tab = hp.build_table(xyz, [cam], p)
+    smp = hp.alloc_samples(R, p, dev)
+    o = {"rgb": torch.empty(R * 3, device=dev), "depth": torch.empty(R, device=dev),
+         "acc": torch.empty(R, device=dev)}
+    fo = {"rgb": torch.empty(R * 3, device=dev), "depth": torch.empty(R, device=dev),
+          "acc": torch.empty(R, device=dev), "n_sel": None}
+
+    def sep():
+        hp.search_sample(tab, p, out=smp)
+        hp.render(smp, R, feat, mlp, p, hp.HP_BF16, out=o)
+
+    t_sep = _time_ms(sep, reps)
+    t_fus = _time_ms(lambda: hp.search_render(tab, p, feat, mlp, hp.HP_BF16, out=fo), reps)
+    same = bool(torch.equal(o["rgb"], fo["rgb"]))
+    return {"separate_ms": t_sep, "fused_ms": t_fus, "fused_over_separate": t_fus / t_sep,
+            "identical_rgb": same}
 
 
 def train_leg(sc, reps=5):

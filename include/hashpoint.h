@@ -20,6 +20,7 @@
  *   hp_render           - aggregation, MLP, compositing     (Sec. 3.4, Eq. 2)
  *   hp_render_backward  - gradient of the render            (Sec. 3.4, Eq. 2)
  *   hp_render_backward_samples - the same from kept samples
+ *   hp_search_render    - search + sampling + render in one launch
  *   hp_knp_blend        - K nearest points to each ray, Eq. 1 blend (Sec. 3.1)
  *
  * General rules
@@ -249,6 +250,19 @@ hp_status hp_search_sample(const hp_table *tab, const hp_camera *cams, int32_t n
 hp_status hp_render(const hp_samples *smp, int64_t R, const float *feat, int32_t C,
                     const hp_mlp *mlp, int32_t precision, const hp_params *p, float *rgb,
                     float *depth, float *acc, void *stream);
+
+/* Search, sampling, aggregation, decoder and compositing in one launch
+ * (Sec. 3.2-3.4): the same operations in the same order as
+ * hp_search_sample followed by hp_render, so rgb, depth and acc are
+ * identical, without writing the samples.  Requires n_samples <= 16 and
+ * K <= 16 (the samples of a ray form one 16-wide decoder tile).
+ *  rgb (R x 3), depth, acc (R, nullable), n_sel (R, nullable): device.
+ * Errors: HP_E_INVALID, HP_E_UNSUPPORTED (C != HP_FEAT_DIM, n_samples > 16,
+ *      K > 16). */
+hp_status hp_search_render(const hp_table *tab, const hp_camera *cams, int32_t n_views,
+                           const hp_params *p, const float *feat, int32_t C, const hp_mlp *mlp,
+                           int32_t precision, float *rgb, float *depth, float *acc,
+                           int32_t *n_sel, void *stream);
 
 /* K-NP extraction and image-based blending (Sec. 3.1, Eq. 1) on the same
  * table and search: for every ray, the K points nearest to the ray among its

@@ -331,6 +331,35 @@ hp_status hp_knp_blend(const hp_table *tab, const hp_camera *cams, int32_t n_vie
     return e == hipSuccess ? HP_OK : hip_fail(e);
 }
 
+hp_status hp_search_render(const hp_table *tab, const hp_camera *cams, int32_t n_views,
+                           const hp_params *p, const float *feat, int32_t C, const hp_mlp *mlp,
+                           int32_t precision, float *rgb, float *depth, float *acc,
+                           int32_t *n_sel, void *stream)
+{
+    hp::SearchCtx c;
+    const hp_status st = make_ctx(tab, cams, n_views, p, c);
+    if (st != HP_OK) return st;
+    if (C != HP_FEAT_DIM) return HP_E_UNSUPPORTED;
+    if (p->n_samples > hp::fused_max_samples() || p->K > 16) return HP_E_UNSUPPORTED;
+    if (precision != HP_FP32 && precision != HP_BF16) return HP_E_INVALID;
+    if (!feat || !mlp || !rgb) return HP_E_INVALID;
+    if (!mlp->W1 || !mlp->b1 || !mlp->W2 || !mlp->b2 || !mlp->W3 || !mlp->b3) return HP_E_INVALID;
+    hp::FusedArgs a;
+    a.feat = feat;
+    a.w = hp::MlpWeights{mlp->W1, mlp->b1, mlp->W2, mlp->b2, mlp->W3, mlp->b3};
+    a.eps_idw = p->eps_idw;
+    a.delta_last = p->delta_last;
+    for (int i = 0; i < 3; ++i) a.bg[i] = p->bg[i];
+    a.rgb = rgb;
+    a.depth = depth;
+    a.acc = acc;
+    a.n_sel = n_sel;
+    a.K = p->K;
+    const hipError_t e =
+        hp::launch_fused(c, a, knn_template(p->K), precision, (hipStream_t)stream);
+    return e == hipSuccess ? HP_OK : hip_fail(e);
+}
+
 hp_status hp_render(const hp_samples *smp, int64_t R, const float *feat, int32_t C,
                     const hp_mlp *mlp, int32_t precision, const hp_params *p, float *rgb,
                     float *depth, float *acc, void *stream)

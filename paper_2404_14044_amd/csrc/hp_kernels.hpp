@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "hashpoint.h"
+#include "hp_mlp.hpp"
 
 namespace hp {
 
@@ -58,5 +59,18 @@ struct KnpArgs {
 };
 
 hipError_t launch_knp(const SearchCtx &c, const KnpArgs &a, hipStream_t s);
+
+struct FusedArgs {
+    const float *feat;
+    MlpWeights w;
+    float eps_idw, delta_last;
+    float bg[3];
+    float *rgb, *depth, *acc;  // depth, acc nullable
+    int32_t *n_sel;            // nullable
+    int32_t K;
+};
+
+int fused_max_samples();
+hipError_t launch_fused(const SearchCtx &c, const FusedArgs &a, int kt, int precision, hipStream_t s);
 
 }  // namespace hp

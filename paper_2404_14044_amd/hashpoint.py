@@ -27,6 +27,7 @@ HIDDEN = 64
 EXPORTED = ["hp_table_workspace", "hp_view_bounds", "hp_paper_kernel_size", "hp_build_table", "hp_search_sample",
             "hp_render", "hp_backward_workspace", "hp_render_backward",
             "hp_backward_samples_workspace", "hp_render_backward_samples", "hp_knp_blend",
+            "hp_search_render",
             "hp_status_str",
             "hp_last_hip_error"]
 
@@ -110,6 +111,8 @@ def lib():
         L.hp_backward_workspace.argtypes = [P, P, P]
         L.hp_render_backward.restype = i32
         L.hp_render_backward.argtypes = [P, P, i32, P, i32, P, i32, P, P, P, P, P, ctypes.c_size_t, P]
+        L.hp_search_render.restype = i32
+        L.hp_search_render.argtypes = [P, P, i32, P, P, i32, P, i32, P, P, P, P, P]
         L.hp_knp_blend.restype = i32
         L.hp_knp_blend.argtypes = [P, P, i32, P, i32, P, P, P, P, P, P]
         L.hp_backward_samples_workspace.restype = ctypes.c_size_t
@@ -312,6 +315,26 @@ def render(samples: Dict[str, torch.Tensor], n_rays: int, feat: torch.Tensor,
                            out["depth"].data_ptr() if out.get("depth") is not None else None,
                            out["acc"].data_ptr() if out.get("acc") is not None else None,
                            _stream(stream)), "hp_render")
+    return out
+
+
+def search_render(table: Table, params, feat: torch.Tensor, mlp: Dict[str, torch.Tensor],
+                  precision: int, out: Optional[Dict[str, torch.Tensor]] = None,
+                  stream=None) -> Dict[str, torch.Tensor]:
+    """search_sample + render in one launch (samples stay on chip)."""
+    params = params or table.params
+    R, dev = table.n_rays, feat.device
+    if out is None:
+        out = {"rgb": torch.empty(R * 3, device=dev), "depth": torch.empty(R, device=dev),
+               "acc": torch.empty(R, device=dev), "n_sel": torch.empty(R, dtype=torch.int32, device=dev)}
+    arr, p, m = _cams_array(table.cams), make_params(params), mlp_struct(mlp)
+    _check(lib().hp_search_render(ctypes.byref(table.tab), arr, len(table.cams), ctypes.byref(p),
+                                  _dev(feat, torch.float32, "feat"), int(feat.shape[1]),
+                                  ctypes.byref(m), int(precision), out["rgb"].data_ptr(),
+                                  out["depth"].data_ptr() if out.get("depth") is not None else None,
+                                  out["acc"].data_ptr() if out.get("acc") is not None else None,
+                                  out["n_sel"].data_ptr() if out.get("n_sel") is not None else None,
+                                  _stream(stream)), "hp_search_render")
     return out
 
 
