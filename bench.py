@@ -163,6 +163,7 @@ def main():
         result["samplers"] = sampler_leg(sc)
         result["knp"] = knp_leg(sc)
         result["fused"] = fused_leg(sc)
+        result["room_5m"] = room_leg()
         result["complexity_sweep"] = scaling_leg()
 
     if args.cpu_seconds > 0:
@@ -385,6 +386,37 @@ def fused_leg(sc, reps=10):
     same = bool(torch.equal(o["rgb"], fo["rgb"]))
     return {"separate_ms": t_sep, "fused_ms": t_fus, "fused_over_separate": t_fus / t_sep,
             "identical_rgb": same}
+
+
+def room_leg(reps=5):
+    """Scene-scale workload (5M points, 1008x756, K = 16, S = 16): build +
+    search/sample + render (BF16)."""
+    import torch
+    from paper_2404_14044_amd import hashpoint as hp
+    from paper_2404_14044_amd import scenes
+    dev = torch.device("cuda:0")
+    sc = scenes.room_5m()
+    cam, p = sc.cams[0], sc.params
+    R = cam.W * cam.H
+    xyz = torch.from_numpy(sc.xyz).to(dev)
+    feat = torch.from_numpy(sc.feat).to(dev)
+    mlp = hp.to_device_mlp(sc.mlp, dev)
+    ws = torch.empty(hp.table_workspace(xyz.shape[0], [cam], p), dtype=torch.uint8, device=dev)
+    smp = hp.alloc_samples(R, p, dev)
+    o = {"rgb": torch.empty(R * 3, device=dev)}
+    holder = {}
+
+    def build():
+        holder["tab"] = hp.build_table(xyz, [cam], p, ws=ws)
+
+    tb = _time_ms(build, reps)
+    tab = holder["tab"]
+    ts = _time_ms(lambda: hp.search_sample(tab, p, out=smp), reps)
+    tr = _time_ms(lambda: hp.render(smp, R, feat, mlp, p, hp.HP_BF16, out=o), reps)
+    return {"rays": R, "points": int(xyz.shape[0]), "build_ms": tb, "search_ms": ts, "render_ms": tr,
+            "mrays_s": R / (tb + ts + tr) / 1e3, "samples": int(smp["n_sel"].sum().item()),
+            "overflow_frac": float((smp["flags"] & 1).float().mean().item()),
+            "guard_g": hp.view_bounds(cam, p)[0]}
 
 
 def train_leg(sc, reps=5):

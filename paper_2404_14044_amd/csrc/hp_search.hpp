@@ -365,8 +365,6 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
             h = min((int)__builtin_floorf(Dmax + 0.5f), V.g);
         }
     }
-    const int Wd = 2 * h + 1;
-    const int total = Wd * Wd;
 
     uint64_t tau = ~0ull;
     int npend = 0;
@@ -435,28 +433,31 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
         }
     };
 
-    // one window bucket: returns whether it may hold a neighbour, and its slots
-    // (q + 0.5) / Wd is at least 0.5 / Wd from an integer, far more than the
-    // error of a float reciprocal, so the row index below is exact.
-    const float inv_wd = 1.0f / (float)Wd;
+    // one window bucket at offset (dxi, dyi) from the pixel's bucket: returns
+    // whether it may hold a neighbour, and its slots
     const float inv_L = 1.0f / g.L;
-    auto probe = [&](int q, int &st, int &cnt, float &zmax) -> bool {
-        zmax = z_hi;
-        st = cnt = 0;
-        if (q >= total) return false;
-        const int qy = (int)(((float)q + 0.5f) * inv_wd);
-        const int dyi = qy - h, dxi = q - qy * Wd - h;
-        const int bx = gx + dxi, by = gy + dyi;
-        const float ex = __builtin_fmaxf(0.0f, __builtin_fabsf((float)dxi) - 0.5f);
-        const float ey = __builtin_fmaxf(0.0f, __builtin_fabsf((float)dyi) - 0.5f);
+    auto zmax_at = [&](float D) -> float {
         // bounds only (margins of 1e-3 px and 0.1% dwarf 1-ulp approximations)
-        const float D = __builtin_amdgcn_sqrtf(ex * ex + ey * ey);
-        if (!(bx >= 0 && bx < V.Wg && by >= 0 && by < V.Hg && D <= Dmax)) return false;
         const float Dp = D - 0.01f;
         if (Dp > 0.0f && Dp > dinf) {
             const float zc = ((frL2 * __builtin_amdgcn_rcpf(Dp) + two_rw) * inv_L) * 1.001f + 1e-5f;
-            zmax = zc < z_hi ? zc : z_hi;
+            return zc < z_hi ? zc : z_hi;
         }
+        return z_hi;
+    };
+    auto offset_D = [](int adx, int ady) -> float {
+        const float ex = __builtin_fmaxf(0.0f, (float)adx - 0.5f);
+        const float ey = __builtin_fmaxf(0.0f, (float)ady - 0.5f);
+        return __builtin_amdgcn_sqrtf(ex * ex + ey * ey);
+    };
+    auto probe = [&](bool valid, int dxi, int dyi, int &st, int &cnt, float &zmax) -> bool {
+        zmax = z_hi;
+        st = cnt = 0;
+        if (!valid) return false;
+        const int bx = gx + dxi, by = gy + dyi;
+        const float D = offset_D(dxi < 0 ? -dxi : dxi, dyi < 0 ? -dyi : dyi);
+        if (!(bx >= 0 && bx < V.Wg && by >= 0 && by < V.Hg && D <= Dmax)) return false;
+        zmax = zmax_at(D);
         const int key = bucket_of(V, c.layout, bx, by);
         st = c.offsets[key];
         cnt = c.offsets[key + 1] - st;
@@ -476,14 +477,93 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
             nbl = 0;
         }
     };
-    // two chunks of window buckets per step so their loads overlap
-    for (int q0 = 0; q0 < total; q0 += 2 * WAVE) {
-        int stA, cntA, stB, cntB;
-        float zA, zB;
-        const bool okA = probe(q0 + l, stA, cntA, zA);
-        const bool okB = probe(q0 + WAVE + l, stB, cntB, zB);
-        append(okA, stA, cntA, zA);
-        append(okB, stB, cntB, zB);
+    // Larger windows: the buckets are culled by 8x8-bucket cells first: a cell whose
+    // nearest window bucket is at distance D is skipped when its minimum
+    // depth exceeds the depth bound at D (the bound only falls with D).
+    // Surviving cells are listed (up to 64 at a time, in the LDS the walk
+    // uses later) with the prefix of their window-bucket counts; lanes then
+    // probe two chunks of those buckets per step so their loads overlap.
+    // Small windows (most rays of object-scale scenes) skip the cell pass.
+    const int Wd = 2 * h + 1;
+    if (Wd * Wd <= 4 * WAVE) {
+        // (q + 0.5) / Wd is at least 0.5 / Wd from an integer, far more than
+        // the error of a float reciprocal, so the row index below is exact.
+        const float inv_wd = 1.0f / (float)Wd;
+        for (int q0 = 0; q0 < Wd * Wd; q0 += 2 * WAVE) {
+            const int qa = q0 + l, qb = q0 + WAVE + l;
+            const int ya = (int)(((float)qa + 0.5f) * inv_wd), yb = (int)(((float)qb + 0.5f) * inv_wd);
+            int stA, cntA, stB, cntB;
+            float zA, zB;
+            const bool okA = probe(qa < Wd * Wd, qa - ya * Wd - h, ya - h, stA, cntA, zA);
+            const bool okB = probe(qb < Wd * Wd, qb - yb * Wd - h, yb - h, stB, cntB, zB);
+            append(okA, stA, cntA, zA);
+            append(okB, stB, cntB, zB);
+        }
+        if (nbl > 0) sweep_points(nbl);
+        if (npend > 0) flush(npend);
+        return;
+    }
+    int4 *const cl = reinterpret_cast<int4 *>(sh.nb_p);  // (bx0, by0, width, prefix)
+    const int wx0 = max(gx - h, 0), wx1 = min(gx + h, V.Wg - 1);
+    const int wy0 = max(gy - h, 0), wy1 = min(gy + h, V.Hg - 1);
+    const int cx0 = wx0 >> CELL_SHIFT, cy0 = wy0 >> CELL_SHIFT;
+    const int ncw = (wx1 >> CELL_SHIFT) - cx0 + 1;
+    const int ncell = ncw * ((wy1 >> CELL_SHIFT) - cy0 + 1);
+    for (int c0 = 0; c0 < ncell; c0 += WAVE) {
+        const int ci = c0 + l;
+        bool keep = false;
+        int bx0 = 0, by0 = 0, bw = 0, nbk = 0;
+        if (ci < ncell) {
+            const int cyy = cy0 + ci / ncw, cxx = cx0 + ci % ncw;
+            bx0 = max(cxx << CELL_SHIFT, wx0);
+            by0 = max(cyy << CELL_SHIFT, wy0);
+            const int bx1 = min((cxx << CELL_SHIFT) + CELL - 1, wx1);
+            const int by1 = min((cyy << CELL_SHIFT) + CELL - 1, wy1);
+            bw = bx1 - bx0 + 1;
+            nbk = bw * (by1 - by0 + 1);
+            const int adx = gx < bx0 ? bx0 - gx : (gx > bx1 ? gx - bx1 : 0);
+            const int ady = gy < by0 ? by0 - gy : (gy > by1 ? gy - by1 : 0);
+            const float D = offset_D(adx, ady);
+            const float cz = __uint_as_float(c.cell_zmin[V.cell_base + cyy * V.ncx + cxx]);
+            keep = D <= Dmax && cz <= zmax_at(D);
+        }
+        const uint64_t km = ballot(keep);
+        if (km == 0) continue;
+        const int nk = keep ? nbk : 0;
+        const int inc = wave_incl_scan_i32(nk);
+        const int total = readlane_i32(inc, WAVE - 1);
+        lds_sync();
+        if (keep) cl[rank_below(km)] = make_int4(bx0, by0, bw, inc - nk);
+        lds_sync();
+        const int ncl = popc64(km);
+        auto locate = [&](int b, bool &valid, int &dxi, int &dyi) {
+            valid = b < total;
+            dxi = dyi = 0;
+            if (!valid) return;
+            int lo = 0, hi = ncl;  // last listed cell with prefix <= b
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (cl[mid].w <= b) lo = mid;
+                else hi = mid;
+            }
+            const int4 e = cl[lo];
+            const int li = b - e.w;
+            const int ry = (int)(((float)li + 0.5f) * __builtin_amdgcn_rcpf((float)e.z));
+            dxi = e.x + (li - ry * e.z) - gx;
+            dyi = e.y + ry - gy;
+        };
+        for (int b0 = 0; b0 < total; b0 += 2 * WAVE) {
+            bool vA, vB;
+            int dxA, dyA, dxB, dyB;
+            locate(b0 + l, vA, dxA, dyA);
+            locate(b0 + WAVE + l, vB, dxB, dyB);
+            int stA, cntA, stB, cntB;
+            float zA, zB;
+            const bool okA = probe(vA, dxA, dyA, stA, cntA, zA);
+            const bool okB = probe(vB, dxB, dyB, stB, cntB, zB);
+            append(okA, stA, cntA, zA);
+            append(okB, stB, cntB, zB);
+        }
     }
     if (nbl > 0) sweep_points(nbl);
     if (npend > 0) flush(npend);

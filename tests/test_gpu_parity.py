@@ -125,6 +125,20 @@ def test_objects_gamma_sweep_sampled_rays(objects, gamma):
     compare_exact(sc, out["samples"], pix, params=p)
 
 
+def test_room_sampled_rays():
+    """Scene-scale workload: 5M points (walls with two faces, boxes, 5%
+    outliers), 1008x756 view, K = 16; 512 sampled rays against the oracle's
+    brute force over all 5M points."""
+    sc = scenes.room_5m()
+    from paper_2404_14044_amd import hashpoint as hp
+    out = gpu_forward(sc, precision=hp.HP_FP32, debug=False)
+    pix = sample_pixels(sc.cams[0], 512, seed=71)
+    ex = compare_exact(sc, out["samples"], pix, check_lists=False)
+    assert (ex["n_sel"] > 0).sum() > 300
+    err = render_error(sc, out["render"], ex, pix)
+    assert err["rgb"] <= FP32_TOL, err
+
+
 def test_sphere_plane_tiled_layout(sphere_plane):
     sc = sphere_plane
     p = sc.params.replace(layout=1)
