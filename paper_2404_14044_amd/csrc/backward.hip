@@ -15,9 +15,10 @@
 //            gradient flows back through it on the VALU in FP32 (weights
 //            FP32) to the aggregated features, and through the aggregation
 //            to the point features with atomics.
-// Decoder-parameter gradients are summed per workgroup in LDS and written to
-// a per-workgroup slice of the workspace; a second kernel sums the slices in
-// workgroup order into the caller's gradient arrays.
+// Decoder-parameter gradients are accumulated per wave in a zeroed slice of
+// the workspace with global atomics (L2 atomics on whole lines are much faster
+// here than LDS float atomics); a second kernel sums the slices in order into
+// the caller's gradient arrays.
 #include <type_traits>
 
 #include "hp_backward.hpp"
@@ -105,11 +106,13 @@ template <int PREC>
 __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
 {
     __shared__ BwdWave waves[BWD_WAVES];
-    __shared__ float gpar[NPAR];  // this workgroup's decoder-parameter gradients
     // FP32 weights for the backward products, shared by the workgroup
     __shared__ float sW1[HP_HIDDEN * HP_FEAT_DIM], sW2[HP_HIDDEN * HP_HIDDEN], sW3[4 * HP_HIDDEN];
     const int wave = threadIdx.x >> 6;
     BwdWave &sh = waves[wave];
+    // this wave's decoder-parameter gradients: its own zeroed workspace slice,
+    // accumulated with global atomics (no other wave touches it)
+    float *const gpar = A.partial + ((int64_t)blockIdx.x * BWD_WAVES + wave) * NPAR;
     const int l = lane_id();
     const int r16 = l & 15, q = l >> 4;
 
@@ -118,7 +121,6 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
         if constexpr (PREC == HP_BF16) load_mlp_bf16(A.w, m);
         else load_mlp_f32(A.w, m);
     };
-    for (int i = threadIdx.x; i < NPAR; i += blockDim.x) gpar[i] = 0.0f;
     for (int i = threadIdx.x; i < HP_HIDDEN * HP_FEAT_DIM; i += blockDim.x) sW1[i] = A.w.W1[i];
     for (int i = threadIdx.x; i < HP_HIDDEN * HP_HIDDEN; i += blockDim.x) sW2[i] = A.w.W2[i];
     for (int i = threadIdx.x; i < 4 * HP_HIDDEN; i += blockDim.x) sW3[i] = A.w.W3[i];
@@ -418,12 +420,15 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
     atomicAdd(&gpar[OFF_B1 + l], gb1);
     atomicAdd(&gpar[OFF_B2 + l], gb2);
     if (l < 4) atomicAdd(&gpar[OFF_B3 + l], gb3);
-    __syncthreads();
-    float *P = A.partial + (int64_t)blockIdx.x * NPAR;
-    for (int i = threadIdx.x; i < NPAR; i += blockDim.x) P[i] = gpar[i];
 }
 
-// Sum the per-workgroup slices in workgroup order and add to the gradients.
+__global__ void __launch_bounds__(256) k_zero_f32(float *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+// Sum the per-wave slices in order and add to the gradients.
 __global__ void __launch_bounds__(256) k_reduce_partials(const float *__restrict__ partial, int nblk,
                                                          float *gW1, float *gb1, float *gW2,
                                                          float *gb2, float *gW3, float *gb3)
@@ -443,7 +448,7 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const float *__restrict
     dst[j] += s;
 }
 
-size_t backward_partial_bytes() { return (size_t)BWD_MAX_BLOCKS * NPAR * sizeof(float); }
+size_t backward_partial_bytes() { return (size_t)BWD_MAX_BLOCKS * BWD_WAVES * NPAR * sizeof(float); }
 
 int backward_rays_per_wave(int S)
 {
@@ -463,11 +468,14 @@ hipError_t launch_backward(const BwdArgs &A, int precision, const MlpGrad &gm, h
     if (nblk > cus) nblk = cus;
     if (nblk > BWD_MAX_BLOCKS) nblk = BWD_MAX_BLOCKS;
     if (nblk < 1) nblk = 1;
+    const int64_t nslice = nblk * BWD_WAVES;
+    const int64_t nzero = nslice * NPAR;
+    k_zero_f32<<<dim3((unsigned)((nzero + 255) / 256)), 256, 0, s>>>(A.partial, nzero);
     if (precision == HP_BF16)
         k_render_backward<HP_BF16><<<dim3((unsigned)nblk), dim3(WAVE * BWD_WAVES), 0, s>>>(A);
     else
         k_render_backward<HP_FP32><<<dim3((unsigned)nblk), dim3(WAVE * BWD_WAVES), 0, s>>>(A);
-    k_reduce_partials<<<(NPAR + 255) / 256, 256, 0, s>>>(A.partial, (int)nblk, gm.W1, gm.b1, gm.W2,
+    k_reduce_partials<<<(NPAR + 255) / 256, 256, 0, s>>>(A.partial, (int)nslice, gm.W1, gm.b1, gm.W2,
                                                         gm.b2, gm.W3, gm.b3);
     return hipGetLastError();
 }
