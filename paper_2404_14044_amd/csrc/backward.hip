@@ -34,15 +34,6 @@ constexpr int OFF_B2 = OFF_W2 + HP_HIDDEN * HP_HIDDEN;
 constexpr int OFF_W3 = OFF_B2 + HP_HIDDEN;
 constexpr int OFF_B3 = OFF_W3 + 4 * HP_HIDDEN;
 
-// Orders this wave's LDS accesses (a wave's LDS operations complete in
-// program order; this keeps the compiler from moving them across).
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // One wave's LDS.
 struct BwdWave {
     float4 o[BWD_CHUNK];            // raw decoder outputs, then their gradients

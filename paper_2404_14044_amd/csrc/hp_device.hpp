@@ -133,6 +133,17 @@ __device__ __forceinline__ float exp_neg(float x)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Orders this wave's LDS accesses.  A wave's LDS operations complete in
+// program order, so a compiler barrier is enough for its lanes to see each
+// other's writes; no workgroup barrier, as several independent waves may
+// share a workgroup.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
 {
     const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, WAVE);

@@ -125,15 +125,7 @@ __device__ __forceinline__ float rho_at(const SearchCtx &c, const RayGeom &g, fl
     return c.rmode == HP_RADIUS_LINEAR ? search_radius(c.radius, c.inv_tref, t) : t * g.kappa;
 }
 
-// Orders this wave's LDS accesses.  A wave's LDS operations execute in program
-// order, so a compiler barrier is enough: lanes then see each other's writes.
-// (No workgroup barrier: several independent waves may share a workgroup.)
-__device__ __forceinline__ void lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+__device__ __forceinline__ void lds_sync() { wave_lds_sync(); }
 
 // ---------------------------------------------------------------------------
 // cross-lane exchange: lane l receives lane l ^ j's value.  DPP for j < 16
