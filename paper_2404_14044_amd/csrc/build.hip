@@ -7,10 +7,12 @@
 //   k_scan_*       counts         -> exclusive offsets, three passes
 //   k_scatter      (view, point)  -> 64-bit key (z bits, point index) per slot
 //   k_sort_small   one lane per bucket of at most 16 points, register network
+//   k_sort_mid     one wave per bucket of 17..64 points, register bitonic
 //   k_sort_big     one workgroup per larger bucket, bitonic in LDS or global
 //   k_materialize  one lane per slot: camera-space point, perm, slot_of
 #include "hp_device.hpp"
 #include "hp_kernels.hpp"
+#include "hp_search.hpp"
 #include "hp_table_ws.hpp"
 
 namespace hp {
@@ -214,7 +216,7 @@ __global__ void __launch_bounds__(256) k_sort_small(const int32_t *__restrict__ 
     else if (cnt > 8 && cnt <= SMALL_MAX) first = sort_bucket_regs<16>(skey, start, cnt);
     else if (cnt > SMALL_MAX) {
         big_list[atomicAdd(big_n, 1)] = (int32_t)b;
-        return;  // k_sort_big writes bucket_z
+        return;  // k_sort_mid / k_sort_big write bucket_z
     }
     bucket_z[b] = cnt > 0 ? __uint_as_float((uint32_t)(first >> 32)) : __builtin_inff();
 }
@@ -257,6 +259,31 @@ __device__ void block_flip_bitonic(int cnt, Load ld, Store st)
     }
 }
 
+// Buckets of 17..64 points: one wave each, a register bitonic sort across
+// the wave (one key per lane), no LDS and no workgroup barrier.
+__global__ void __launch_bounds__(256) k_sort_mid(const int32_t *__restrict__ offsets,
+                                                  uint64_t *__restrict__ skey,
+                                                  const int32_t *__restrict__ big_list,
+                                                  const int32_t *__restrict__ big_n,
+                                                  float *__restrict__ bucket_z)
+{
+    const int nbig = *big_n;
+    const int l = lane_id();
+    const int waves = blockDim.x / WAVE;
+    for (int it = blockIdx.x * waves + (threadIdx.x >> 6); it < nbig; it += gridDim.x * waves) {
+        const int b = big_list[it];
+        const int start = offsets[b];
+        const int cnt = offsets[b + 1] - start;
+        if (cnt > WAVE) continue;  // left to k_sort_big
+        uint64_t x = l < cnt ? skey[start + l] : ~0ull;
+        x = wave_sort_fast(x);
+        if (l < cnt) skey[start + l] = x;
+        if (l == 0) bucket_z[b] = __uint_as_float((uint32_t)(x >> 32));
+    }
+}
+
+// Buckets of more than 64 points: one workgroup each, bitonic in LDS (in
+// global memory beyond BIG_LDS entries).
 __global__ void __launch_bounds__(BIG_T) k_sort_big(const int32_t *__restrict__ offsets,
                                                     uint64_t *__restrict__ skey,
                                                     const int32_t *__restrict__ big_list,
@@ -269,6 +296,7 @@ __global__ void __launch_bounds__(BIG_T) k_sort_big(const int32_t *__restrict__ 
         const int b = big_list[it];
         const int start = offsets[b];
         const int cnt = offsets[b + 1] - start;
+        if (cnt <= WAVE) continue;  // sorted by k_sort_mid (uniform across the workgroup)
         uint64_t *g = skey + start;
         if (cnt <= BIG_LDS) {
             for (int i = threadIdx.x; i < cnt; i += blockDim.x) sh[i] = g[i];
@@ -352,7 +380,8 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
     k_scan_apply<<<(unsigned)nblk, SCAN_T, 0, s>>>(tw.count, n_buckets, tw.block_sums, tw.offsets);
     if (nv > 0) k_scatter<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tw.kz, nv, n, tw.offsets, tw.count, tw.skey);
     k_sort_small<<<(unsigned)((n_buckets + 255) / 256), 256, 0, s>>>(tw.offsets, n_buckets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
-    k_sort_big<<<512, BIG_T, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
+    k_sort_mid<<<1024, 256, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
+    k_sort_big<<<256, BIG_T, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
     int max_cells = 0;
     for (int i = 0; i < V; ++i) {
         const ViewK &vk = vs.v[i];
