@@ -1,9 +1,12 @@
 // Pixel-table construction (Sec. 3.2, Fig. 2): project every point into every
-// view, count points per bucket, scan the counts into bucket offsets, scatter
-// the points into their bucket with atomics, and order each bucket by depth.
+// view, count points per bucket with atomics (the counter's old value is the
+// point's rank in its bucket), scan the counts into bucket offsets, place each
+// point at offset + rank, and order each bucket by depth.
 //
 // Passes (each a coalesced sweep except the scatter and the bucket sorts):
-//   k_project      (view, point)  -> (bucket, z) and a per-bucket count
+//   k_project      (view, point)  -> (bucket, z), a per-bucket count and the
+//                  point's arrival rank in its bucket (kept in slot_of until
+//                  k_materialize overwrites it)
 //   k_scan_*       counts         -> exclusive offsets, three passes
 //   k_scatter      (view, point)  -> 64-bit key (z bits, point index) per slot
 //   k_sort_small   one lane per bucket of at most 16 points, register network
@@ -33,7 +36,8 @@ __global__ void k_fill_i32(int32_t *p, int32_t val, int64_t n)
 // grid: (ceil(n / 256), n_views)
 __global__ void __launch_bounds__(256) k_project(const float *__restrict__ xyz, int64_t n,
                                                  const ViewK *__restrict__ views, int layout,
-                                                 int2 *__restrict__ kz, int32_t *__restrict__ count)
+                                                 int2 *__restrict__ kz, int32_t *__restrict__ count,
+                                                 int32_t *__restrict__ rank)
 {
     const int vi = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -41,7 +45,7 @@ __global__ void __launch_bounds__(256) k_project(const float *__restrict__ xyz, 
     const ViewK &V = views[vi];
     float x, y, z;
     to_camera(V, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], x, y, z);
-    int32_t key = -1;
+    int32_t key = -1, r = 0;
     if (z > 0.0f && __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z)) {
         const float uf = fma_rn(V.fx, x / z, V.cx);
         const float vf = fma_rn(V.fy, y / z, V.cy);
@@ -50,10 +54,11 @@ __global__ void __launch_bounds__(256) k_project(const float *__restrict__ xyz, 
             const int bx = (int)__builtin_floorf(uf) + V.g;
             const int by = (int)__builtin_floorf(vf) + V.g;
             key = bucket_of(V, layout, bx, by);
-            atomicAdd(&count[key], 1);
+            r = atomicAdd(&count[key], 1);  // arrival rank inside the bucket
         }
     }
     kz[(int64_t)vi * n + i] = make_int2(key, __float_as_int(z));
+    rank[(int64_t)vi * n + i] = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -137,18 +142,17 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_apply(const int32_t *__restrict
 // scatter: one 64-bit key per slot, (z bits) << 32 | point index.  z > 0, so
 // the bits of z order like z, and the key orders by (z, index).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_scatter(const int2 *__restrict__ kz, int64_t total,
+__global__ void __launch_bounds__(256) k_scatter(const int2 *__restrict__ kz,
+                                                 const int32_t *__restrict__ rank, int64_t total,
                                                  int64_t n, const int32_t *__restrict__ offsets,
-                                                 int32_t *__restrict__ count,
                                                  uint64_t *__restrict__ skey)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
     const int2 e = kz[i];
     if (e.x < 0) return;
-    const int pos = atomicSub(&count[e.x], 1) - 1;
     const int64_t p = i % n;
-    skey[offsets[e.x] + pos] = ((uint64_t)(uint32_t)e.y << 32) | (uint32_t)p;
+    skey[offsets[e.x] + rank[i]] = ((uint64_t)(uint32_t)e.y << 32) | (uint32_t)p;
 }
 
 // ---------------------------------------------------------------------------
@@ -373,12 +377,12 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
     k_init_views<<<1, HP_MAX_VIEWS, 0, s>>>(vs, tw.views);
     k_fill_i32<<<1024, 256, 0, s>>>(tw.count, 0, n_buckets);
     k_fill_i32<<<1, 64, 0, s>>>(tw.big_n, 0, 1);
-    if (n > 0) k_project<<<dim3((unsigned)((n + 255) / 256), V), 256, 0, s>>>(xyz, n, tw.views, vs.layout, tw.kz, tw.count);
+    if (n > 0) k_project<<<dim3((unsigned)((n + 255) / 256), V), 256, 0, s>>>(xyz, n, tw.views, vs.layout, tw.kz, tw.count, tw.slot_of);
     const int64_t nblk = (n_buckets + SCAN_TILE - 1) / SCAN_TILE;
     k_scan_reduce<<<(unsigned)nblk, SCAN_T, 0, s>>>(tw.count, n_buckets, tw.block_sums);
     k_scan_blocks<<<1, SCAN_T, 0, s>>>(tw.block_sums, nblk);
     k_scan_apply<<<(unsigned)nblk, SCAN_T, 0, s>>>(tw.count, n_buckets, tw.block_sums, tw.offsets);
-    if (nv > 0) k_scatter<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tw.kz, nv, n, tw.offsets, tw.count, tw.skey);
+    if (nv > 0) k_scatter<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tw.kz, tw.slot_of, nv, n, tw.offsets, tw.skey);
     k_sort_small<<<(unsigned)((n_buckets + 255) / 256), 256, 0, s>>>(tw.offsets, n_buckets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
     k_sort_mid<<<1024, 256, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
     k_sort_big<<<256, BIG_T, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
