@@ -22,27 +22,51 @@
 namespace hp {
 
 // Aggregated feature slice (8 floats) of sample `row` for lane slice q.
+// Neighbours are taken four at a time so that their index, distance and
+// feature loads are in flight together; the sums run in neighbour order (the
+// lists are padded with -1 only at their end).
 __device__ __forceinline__ void idw_slice(const RenderArgs &a, int64_t row, int q, float *f)
 {
 #pragma unroll
     for (int e = 0; e < 8; ++e) f[e] = 0.0f;
     float wsum = 0.0f;
-    for (int k = 0; k < a.K; ++k) {
-        const int idx = a.knn_idx[row * a.K + k];
-        if (idx < 0) break;
-        const float d = a.knn_dist[row * a.K + k];
-        const float w = 1.0f / (d > a.eps_idw ? d : a.eps_idw);
-        const float4 *src = reinterpret_cast<const float4 *>(a.feat + (int64_t)idx * HP_FEAT_DIM + 8 * q);
-        const float4 x0 = src[0], x1 = src[1];
-        f[0] = fma_rn(w, x0.x, f[0]);
-        f[1] = fma_rn(w, x0.y, f[1]);
-        f[2] = fma_rn(w, x0.z, f[2]);
-        f[3] = fma_rn(w, x0.w, f[3]);
-        f[4] = fma_rn(w, x1.x, f[4]);
-        f[5] = fma_rn(w, x1.y, f[5]);
-        f[6] = fma_rn(w, x1.z, f[6]);
-        f[7] = fma_rn(w, x1.w, f[7]);
-        wsum += w;
+    const int32_t *ki = a.knn_idx + row * a.K;
+    const float *kd = a.knn_dist + row * a.K;
+    for (int k0 = 0; k0 < a.K; k0 += 4) {
+        int idx[4];
+        float w[4];
+        float4 x0[4], x1[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool in = k0 + j < a.K;
+            idx[j] = in ? ki[k0 + j] : -1;
+            const float d = in ? kd[k0 + j] : 1.0f;
+            w[j] = 1.0f / (d > a.eps_idw ? d : a.eps_idw);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (idx[j] >= 0) {
+                const float4 *src =
+                    reinterpret_cast<const float4 *>(a.feat + (int64_t)idx[j] * HP_FEAT_DIM + 8 * q);
+                x0[j] = src[0];
+                x1[j] = src[1];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (idx[j] >= 0) {
+                f[0] = fma_rn(w[j], x0[j].x, f[0]);
+                f[1] = fma_rn(w[j], x0[j].y, f[1]);
+                f[2] = fma_rn(w[j], x0[j].z, f[2]);
+                f[3] = fma_rn(w[j], x0[j].w, f[3]);
+                f[4] = fma_rn(w[j], x1[j].x, f[4]);
+                f[5] = fma_rn(w[j], x1[j].y, f[5]);
+                f[6] = fma_rn(w[j], x1[j].z, f[6]);
+                f[7] = fma_rn(w[j], x1[j].w, f[7]);
+                wsum += w[j];
+            }
+        }
+        if (idx[3] < 0) break;
     }
     const float inv = wsum > 0.0f ? 1.0f / wsum : 0.0f;
 #pragma unroll
@@ -52,7 +76,7 @@ __device__ __forceinline__ void idw_slice(const RenderArgs &a, int64_t row, int 
 constexpr int RPW = 32;  // rays per wave
 
 template <int PREC>
-__global__ void __launch_bounds__(WAVE) k_render(RenderArgs a)
+__device__ __forceinline__ void render_body(const RenderArgs &a)
 {
     extern __shared__ float4 sh_out[];  // [RPW * S] (rgb, sigma) per sample
     __shared__ int sh_pre[RPW + 1];
@@ -129,15 +153,24 @@ __global__ void __launch_bounds__(WAVE) k_render(RenderArgs a)
     }
 }
 
+// BF16 fits three waves per SIMD; the FP32 decoder's operands need more registers.
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3, 8)))
+k_render_bf16(RenderArgs a)
+{
+    render_body<HP_BF16>(a);
+}
+
+__global__ void __launch_bounds__(WAVE) k_render_fp32(RenderArgs a) { render_body<HP_FP32>(a); }
+
 hipError_t launch_render(const RenderArgs &a, int precision, hipStream_t s)
 {
     const int64_t blocks = (a.n_rays + RPW - 1) / RPW;
     if (blocks == 0) return hipSuccess;
     const size_t shmem = (size_t)RPW * a.S * sizeof(float4);
     if (precision == HP_BF16)
-        k_render<HP_BF16><<<dim3((unsigned)blocks), dim3(WAVE), shmem, s>>>(a);
+        k_render_bf16<<<dim3((unsigned)blocks), dim3(WAVE), shmem, s>>>(a);
     else
-        k_render<HP_FP32><<<dim3((unsigned)blocks), dim3(WAVE), shmem, s>>>(a);
+        k_render_fp32<<<dim3((unsigned)blocks), dim3(WAVE), shmem, s>>>(a);
     return hipGetLastError();
 }
 
