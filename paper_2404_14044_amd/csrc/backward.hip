@@ -50,28 +50,50 @@ struct BwdWave {
 static_assert(2 * 16 * HP_MAX_K <= HP_HIDDEN * 16, "neighbour staging exceeds its LDS area");
 
 // Aggregated feature slice (features 8 q .. 8 q + 7) of sample row `row`;
-// the same arithmetic as the render.
+// the same arithmetic as the render (neighbours four at a time, summed in
+// order).  Returns 1 / sum of the weights.
 __device__ __forceinline__ float idw_slice_bwd(const BwdArgs &A, int64_t row, int q, float *f)
 {
 #pragma unroll
     for (int e = 0; e < 8; ++e) f[e] = 0.0f;
     float wsum = 0.0f;
-    for (int k = 0; k < A.K; ++k) {
-        const int idx = A.knn_idx[row * A.K + k];
-        if (idx < 0) break;
-        const float d = A.knn_dist[row * A.K + k];
-        const float w = 1.0f / (d > A.eps_idw ? d : A.eps_idw);
-        const float4 *src = reinterpret_cast<const float4 *>(A.feat + (int64_t)idx * HP_FEAT_DIM + 8 * q);
-        const float4 x0 = src[0], x1 = src[1];
-        f[0] = fma_rn(w, x0.x, f[0]);
-        f[1] = fma_rn(w, x0.y, f[1]);
-        f[2] = fma_rn(w, x0.z, f[2]);
-        f[3] = fma_rn(w, x0.w, f[3]);
-        f[4] = fma_rn(w, x1.x, f[4]);
-        f[5] = fma_rn(w, x1.y, f[5]);
-        f[6] = fma_rn(w, x1.z, f[6]);
-        f[7] = fma_rn(w, x1.w, f[7]);
-        wsum += w;
+    const int32_t *ki = A.knn_idx + row * A.K;
+    const float *kd = A.knn_dist + row * A.K;
+    for (int k0 = 0; k0 < A.K; k0 += 4) {
+        int idx[4];
+        float w[4];
+        float4 x0[4], x1[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool in = k0 + j < A.K;
+            idx[j] = in ? ki[k0 + j] : -1;
+            const float d = in ? kd[k0 + j] : 1.0f;
+            w[j] = 1.0f / (d > A.eps_idw ? d : A.eps_idw);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (idx[j] >= 0) {
+                const float4 *src =
+                    reinterpret_cast<const float4 *>(A.feat + (int64_t)idx[j] * HP_FEAT_DIM + 8 * q);
+                x0[j] = src[0];
+                x1[j] = src[1];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (idx[j] >= 0) {
+                f[0] = fma_rn(w[j], x0[j].x, f[0]);
+                f[1] = fma_rn(w[j], x0[j].y, f[1]);
+                f[2] = fma_rn(w[j], x0[j].z, f[2]);
+                f[3] = fma_rn(w[j], x0[j].w, f[3]);
+                f[4] = fma_rn(w[j], x1[j].x, f[4]);
+                f[5] = fma_rn(w[j], x1[j].y, f[5]);
+                f[6] = fma_rn(w[j], x1[j].z, f[6]);
+                f[7] = fma_rn(w[j], x1[j].w, f[7]);
+                wsum += w[j];
+            }
+        }
+        if (idx[3] < 0) break;
     }
     const float inv = wsum > 0.0f ? 1.0f / wsum : 0.0f;
 #pragma unroll

@@ -60,24 +60,43 @@ __device__ __forceinline__ void fused_body(const SearchCtx &c, const FusedArgs &
 #pragma unroll
             for (int e = 0; e < 8; ++e) f[e] = 0.0f;
             if (r16 < n) {
+                // neighbours four at a time, summed in order (as the render)
                 float wsum = 0.0f;
-                for (int k = 0; k < c.K; ++k) {
-                    const int idx = sh.idx[r16][k];
-                    if (idx < 0) break;
-                    const float d = sh.dist[r16][k];
-                    const float w = 1.0f / (d > a.eps_idw ? d : a.eps_idw);
-                    const float4 *src =
-                        reinterpret_cast<const float4 *>(a.feat + (int64_t)idx * HP_FEAT_DIM + 8 * q);
-                    const float4 x0 = src[0], x1 = src[1];
-                    f[0] = fma_rn(w, x0.x, f[0]);
-                    f[1] = fma_rn(w, x0.y, f[1]);
-                    f[2] = fma_rn(w, x0.z, f[2]);
-                    f[3] = fma_rn(w, x0.w, f[3]);
-                    f[4] = fma_rn(w, x1.x, f[4]);
-                    f[5] = fma_rn(w, x1.y, f[5]);
-                    f[6] = fma_rn(w, x1.z, f[6]);
-                    f[7] = fma_rn(w, x1.w, f[7]);
-                    wsum += w;
+                for (int k0 = 0; k0 < c.K; k0 += 4) {
+                    int idx[4];
+                    float w[4];
+                    float4 x0[4], x1[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const bool in = k0 + j < c.K;
+                        idx[j] = in ? sh.idx[r16][k0 + j] : -1;
+                        const float d = in ? sh.dist[r16][k0 + j] : 1.0f;
+                        w[j] = 1.0f / (d > a.eps_idw ? d : a.eps_idw);
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if (idx[j] >= 0) {
+                            const float4 *src = reinterpret_cast<const float4 *>(
+                                a.feat + (int64_t)idx[j] * HP_FEAT_DIM + 8 * q);
+                            x0[j] = src[0];
+                            x1[j] = src[1];
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if (idx[j] >= 0) {
+                            f[0] = fma_rn(w[j], x0[j].x, f[0]);
+                            f[1] = fma_rn(w[j], x0[j].y, f[1]);
+                            f[2] = fma_rn(w[j], x0[j].z, f[2]);
+                            f[3] = fma_rn(w[j], x0[j].w, f[3]);
+                            f[4] = fma_rn(w[j], x1[j].x, f[4]);
+                            f[5] = fma_rn(w[j], x1[j].y, f[5]);
+                            f[6] = fma_rn(w[j], x1[j].z, f[6]);
+                            f[7] = fma_rn(w[j], x1[j].w, f[7]);
+                            wsum += w[j];
+                        }
+                    }
+                    if (idx[3] < 0) break;
                 }
                 const float inv = wsum > 0.0f ? 1.0f / wsum : 0.0f;
 #pragma unroll
