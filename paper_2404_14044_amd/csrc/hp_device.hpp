@@ -144,51 +144,16 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
-{
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, WAVE);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, WAVE);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
-{
-    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, WAVE);
-    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, WAVE);
-    return ((uint64_t)hi << 32) | lo;
-}
-
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a < b ? b : a; }
 
-// Ascending bitonic sort of one 64-bit key per lane across the wave.
-__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t x)
+// (a, b) <- (min, max) of the pair, on one compare
+__device__ __forceinline__ void cswap64(uint64_t &a, uint64_t &b)
 {
-    const int l = lane_id();
-#pragma unroll
-    for (int k = 2; k <= WAVE; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint64_t y = shfl_xor_u64(x, j);
-            const bool up = (l & k) == 0;
-            const bool lower = (l & j) == 0;
-            x = (lower == up) ? umin64(x, y) : umax64(x, y);
-        }
-    }
-    return x;
-}
-
-// Keep the 64 smallest of two ascending wave-sorted lists, ascending.
-__device__ __forceinline__ uint64_t wave_merge_low_u64(uint64_t a, uint64_t b)
-{
-    const int l = lane_id();
-    uint64_t x = umin64(a, shfl_u64(b, WAVE - 1 - l));
-#pragma unroll
-    for (int j = WAVE >> 1; j > 0; j >>= 1) {
-        const uint64_t y = shfl_xor_u64(x, j);
-        x = ((l & j) == 0) ? umin64(x, y) : umax64(x, y);
-    }
-    return x;
+    const bool s = b < a;
+    const uint64_t lo = s ? b : a;
+    b = s ? a : b;
+    a = lo;
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
@@ -203,12 +168,14 @@ __device__ __forceinline__ int rank_below(uint64_t m)
 
 __device__ __forceinline__ int wave_incl_scan_i32(int v)
 {
-    const int l = lane_id();
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        const int y = __shfl_up(v, o, WAVE);
-        if (l >= o) v += y;
-    }
+    // inside rows of 16 (lanes shifted in from outside the row add 0), then
+    // the last lane of row 0 into rows 1, 3 and of row 1 into rows 2, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31
     return v;
 }
 

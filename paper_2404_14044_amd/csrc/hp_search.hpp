@@ -38,6 +38,9 @@
 // stops once no later candidate can pass eps_w (alpha <= gamma, so
 // w_j <= gamma T), which usually happens within the first sixteen.
 #pragma once
+#ifndef HP_XOR4_SWIZZLE
+#define HP_XOR4_SWIZZLE 0
+#endif
 
 #include "hp_device.hpp"
 
@@ -130,19 +133,26 @@ __device__ __forceinline__ void lds_sync() { wave_lds_sync(); }
 // ---------------------------------------------------------------------------
 // cross-lane exchange: lane l receives lane l ^ j's value.  DPP for j < 16
 // (row rotations act inside rows of 16 lanes), swizzle for 16, permute for 32.
+// The last two run on the LDS crossbar, off the vector ALU, which bounds the
+// search kernels (the gfx950 permlane swaps measured slower here for that).
 // ---------------------------------------------------------------------------
 template <int J>
 __device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v)
 {
+    // (mov_dpp with every row and bank enabled writes all lanes: no old value)
     const int x = (int)v;
-    if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);
-    if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);
+    if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);
+    if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);
     if constexpr (J == 4) {
-        const int down = __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false);  // from l - 4
-        const int up = __builtin_amdgcn_update_dpp(0, x, 0x12C, 0xF, 0xF, false);    // from l + 4
+#if HP_XOR4_SWIZZLE
+        return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x101F);
+#else
+        const int down = __builtin_amdgcn_mov_dpp(x, 0x124, 0xF, 0xF, false);  // from l - 4
+        const int up = __builtin_amdgcn_mov_dpp(x, 0x12C, 0xF, 0xF, false);    // from l + 4
         return (uint32_t)((lane_id() & 4) ? down : up);
+#endif
     }
-    if constexpr (J == 8) return (uint32_t)__builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);
+    if constexpr (J == 8) return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false);
     if constexpr (J == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x401F);
     return (uint32_t)__shfl_xor(x, J, WAVE);
 }
@@ -155,41 +165,74 @@ __device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v)
     return ((uint64_t)hi << 32) | lo;
 }
 
-template <int K, int J>
-__device__ __forceinline__ uint64_t sort_stage(uint64_t x, int l)
+// One compare-exchange stage in which every block ascends: lanes l and l ^ J
+// keep the minimum in the lower lane (one 64-bit compare, two selects).
+template <int J>
+__device__ __forceinline__ uint64_t cx_stage(uint64_t x, int l)
 {
     const uint64_t y = xor_lane_u64<J>(x);
-    const bool up = (l & K) == 0;
-    const bool lower = (l & J) == 0;
-    return (lower == up) ? umin64(x, y) : umax64(x, y);
+    const bool take = (y < x) != ((l & J) != 0);
+    return take ? y : x;
 }
 
-template <int K, int J>
-__device__ __forceinline__ uint64_t sort_merge_steps(uint64_t x, int l)
+template <int J>
+__device__ __forceinline__ uint64_t cx_merge(uint64_t x, int l)
 {
-    x = sort_stage<K, J>(x, l);
-    if constexpr (J > 1) x = sort_merge_steps<K, J / 2>(x, l);
+    x = cx_stage<J>(x, l);
+    if constexpr (J > 1) x = cx_merge<J / 2>(x, l);
     return x;
 }
 
-template <int K>
-__device__ __forceinline__ uint64_t sort_steps(uint64_t x, int l)
+// Inverts the keys of the lanes whose lane-index bits a and b differ (b = -1:
+// bit a alone): bitwise NOT reverses the order of keys.
+__device__ __forceinline__ uint64_t flip_keys(uint64_t x, int l, int a, int b)
 {
-    x = sort_merge_steps<K, K / 2>(x, l);
-    if constexpr (K < WAVE) x = sort_steps<K * 2>(x, l);
-    return x;
+    const int bits = (l >> a) ^ (b >= 0 ? (l >> b) : 0);
+    const uint32_t m = (uint32_t)(-(bits & 1));
+    return x ^ (((uint64_t)m << 32) | m);
 }
 
-// Ascending bitonic sort of one key per lane across the wave.
-__device__ __forceinline__ uint64_t wave_sort_fast(uint64_t x) { return sort_steps<2>(x, lane_id()); }
-
-// Keep the 64 smallest of two ascending wave-sorted lists, ascending.
-__device__ __forceinline__ uint64_t wave_merge_low_fast(uint64_t a, uint64_t b)
+// Bitonic sort of one key per lane across the wave.  In the merge of blocks
+// of K lanes, the blocks that must descend hold inverted keys, so that every
+// stage is the same ascending compare-exchange; the keys are re-inverted
+// between block sizes as the block directions change.
+template <bool DESC>
+__device__ __forceinline__ uint64_t wave_sort_dir(uint64_t x)
 {
     const int l = lane_id();
-    uint64_t x = umin64(a, shfl_u64(b, WAVE - 1 - l));
-    // half-cleaners: every stage keeps the minimum in the lower lane
-    return sort_merge_steps<2 * WAVE, WAVE / 2>(x, l);
+    x = flip_keys(x, l, 1, -1);  // K = 2 blocks descend where lane bit 1 is set
+    if constexpr (DESC) x = ~x;
+    x = cx_merge<1>(x, l);
+    x = flip_keys(x, l, 1, 2);
+    x = cx_merge<2>(x, l);
+    x = flip_keys(x, l, 2, 3);
+    x = cx_merge<4>(x, l);
+    x = flip_keys(x, l, 3, 4);
+    x = cx_merge<8>(x, l);
+    x = flip_keys(x, l, 4, 5);
+    x = cx_merge<16>(x, l);
+    x = flip_keys(x, l, 5, -1);  // one block of 64: ascends (descends with DESC)
+    x = cx_merge<32>(x, l);
+    if constexpr (DESC) x = ~x;
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sort_fast(uint64_t x) { return wave_sort_dir<false>(x); }
+__device__ __forceinline__ uint64_t wave_sort_desc(uint64_t x) { return wave_sort_dir<true>(x); }
+
+// Keep the 64 smallest of an ascending and a descending wave-sorted list,
+// ascending: their lane-wise minimum is bitonic and holds the 64 smallest;
+// half-cleaners then sort it.
+__device__ __forceinline__ uint64_t wave_merge_low_fast(uint64_t asc, uint64_t desc)
+{
+    return cx_merge<WAVE / 2>(umin64(asc, desc), lane_id());
+}
+
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ float wave_min_f32(float v)
@@ -371,9 +414,9 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
         lds_sync();
         if (l < rem) sh.pend[l] = y;
         npend = rem;
-        x = wave_sort_fast(x);
+        x = wave_sort_desc(x);
         top = wave_merge_low_fast(top, x);
-        tau = shfl_u64(top, WAVE - 1);
+        tau = readlane_u64(top, WAVE - 1);
         lds_sync();
     };
 
@@ -573,11 +616,7 @@ __device__ __forceinline__ void merge_low(uint64_t (&a)[KT], const uint64_t (&b)
     for (int j = KT / 2; j > 0; j >>= 1) {
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
-            if ((k & j) == 0) {
-                const uint64_t x = a[k], y = a[k + j];
-                a[k] = umin64(x, y);
-                a[k + j] = umax64(x, y);
-            }
+            if ((k & j) == 0) cswap64(a[k], a[k + j]);
         }
     }
 }
@@ -601,11 +640,10 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
     for (int k = 0; k < KT; ++k) kd[k] = ~0ull;
     int n_it = (hi - lo - q + 3) >> 2;
     n_it = n_it > 0 ? n_it : 0;
-#pragma unroll
-    for (int o = 4; o < WAVE; o <<= 1) {
-        const int y = __shfl_xor(n_it, o, WAVE);
-        n_it = n_it > y ? n_it : y;
-    }
+    n_it = max(n_it, (int)xor_lane_u32<4>((uint32_t)n_it));
+    n_it = max(n_it, (int)xor_lane_u32<8>((uint32_t)n_it));
+    n_it = max(n_it, (int)xor_lane_u32<16>((uint32_t)n_it));
+    n_it = max(n_it, (int)xor_lane_u32<32>((uint32_t)n_it));
     for (int it = 0; it < n_it; ++it) {
         const int i = lo + q + 4 * it;
         uint64_t x = ~0ull;
@@ -616,11 +654,7 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
         }
         // branch-free insertion: a key of ~0 leaves the list unchanged
 #pragma unroll
-        for (int k = 0; k < KT; ++k) {
-            const uint64_t lo64 = umin64(kd[k], x);
-            x = umax64(kd[k], x);
-            kd[k] = lo64;
-        }
+        for (int k = 0; k < KT; ++k) cswap64(kd[k], x);
     }
     uint64_t other[KT];
 #pragma unroll
@@ -745,11 +779,12 @@ __device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom
 
 __device__ __forceinline__ int wave_min_i32(int v)
 {
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        const int y = __shfl_xor(v, o, WAVE);
-        v = v < y ? v : y;
-    }
+    v = min(v, (int)xor_lane_u32<1>((uint32_t)v));
+    v = min(v, (int)xor_lane_u32<2>((uint32_t)v));
+    v = min(v, (int)xor_lane_u32<4>((uint32_t)v));
+    v = min(v, (int)xor_lane_u32<8>((uint32_t)v));
+    v = min(v, (int)xor_lane_u32<16>((uint32_t)v));
+    v = min(v, (int)xor_lane_u32<32>((uint32_t)v));
     return v;
 }
 
