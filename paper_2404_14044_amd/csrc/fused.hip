@@ -32,8 +32,7 @@ __device__ __forceinline__ void fused_body(const SearchCtx &c, const FusedArgs &
     __shared__ FusedLds<KT> sh;
     const int l = lane_id();
     const int r16 = l & 15, q = l >> 4;
-    for_each_ray_banded(c, [&](int64_t ray) {
-        const RayGeom g = ray_geometry(c, ray);
+    for_each_ray_banded(c, sh.s.rs, [&](int64_t ray, const RayGeom &g) {
         uint64_t top;
         int count;
         search_neighbours(c, g, sh.s, top, count);

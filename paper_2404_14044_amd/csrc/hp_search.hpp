@@ -64,9 +64,26 @@ struct SearchCtx {
     int32_t ms_steps;       // uniform positions of the multi-surface sampler
 };
 
+// One ray's geometry and search bounds, uniform across the wave that
+// searches it (computed once per ray by one lane, see ray_setup).
+struct RayGeom {
+    int32_t vi, gx, gy;  // view, pixel position in the padded bucket grid
+    int32_t h;           // window half-width in buckets; -1: nothing can be near
+    float dx, dy, dz;    // unit direction (camera frame)
+    float wn;            // |w|, the norm of the normalised image coordinate
+    float kappa;         // Eq. 3 cone slope of this pixel (rho = kappa t), 0 in the linear mode
+    float inv_L;         // 1 / L
+    float z_lo, z_hi;    // depth range of possible neighbours
+    float dinf;          // window radius once rho is on its linear branch
+    float frL2, two_rw;  // f r L^2 and 2 r |w| of the per-bucket depth bound
+    float Dmax;          // window radius in pixels
+};
+
 constexpr int BL_CAP = 128;
+constexpr int RS_CAP = 8;  // rays whose set-up one pass computes (lane per ray)
 
 struct SearchLds {
+    RayGeom rs[RS_CAP];
     int32_t bl_start[BL_CAP];
     int32_t bl_cnt[BL_CAP];
     int32_t bl_pre[BL_CAP];
@@ -79,32 +96,6 @@ struct SearchLds {
 // Rays per XCD band: about 16 image rows of an 800-pixel-wide view.
 constexpr int64_t BAND_RAYS = 12800;
 
-// Persistent iteration over the rays of a launch, one ray at a time per
-// workgroup.  Workgroups take chunks of c.chunk consecutive rays (neighbouring
-// pixels share table buckets).  They are dealt to the eight XCDs round-robin
-// (workgroup b runs on XCD b % 8), each with its own L2, so the chunks are
-// grouped into bands of BAND_RAYS consecutive rays and XCD x takes bands
-// x, x + 8, ...: the rays one XCD's workgroups search at a time are then
-// neighbours and share that L2's table lines.  Within its bands an XCD's
-// workgroups stride by their number, so each still sees a mix of empty and
-// busy regions.  The grid must be a multiple of 8.
-template <typename Body>
-__device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, Body body)
-{
-    const int64_t n_chunks = (c.n_rays + c.chunk - 1) / c.chunk;
-    const int64_t band = (BAND_RAYS + c.chunk - 1) / c.chunk;  // chunks per band
-    const int xcd = blockIdx.x & 7;
-    const int64_t slot = blockIdx.x >> 3, n_slots = gridDim.x >> 3;
-    const int64_t n_bands = (n_chunks + band - 1) / band;
-    const int64_t my_chunks = (n_bands > xcd ? (n_bands - xcd + 7) / 8 : 0) * band;
-    for (int64_t li = slot; li < my_chunks; li += n_slots) {
-        const int64_t ch = (xcd + 8 * (li / band)) * band + li % band;
-        if (ch >= n_chunks) continue;
-        const int64_t r1 = min((ch + 1) * c.chunk, c.n_rays);
-        for (int64_t ray = ch * c.chunk; ray < r1; ++ray) body(ray);
-    }
-}
-
 // Persistent grid for the banded launches: at most `cap` workgroups, a
 // multiple of 8.
 inline int64_t banded_grid(const SearchCtx &c, int64_t cap)
@@ -114,13 +105,6 @@ inline int64_t banded_grid(const SearchCtx &c, int64_t cap)
     if (blocks == 0) return 0;
     return blocks < 8 ? 8 : (blocks & ~(int64_t)7);
 }
-
-// Ray geometry, uniform across the wave.
-struct RayGeom {
-    int vi, u, v;
-    float dx, dy, dz, a, b, L, wn;
-    float kappa;  // Eq. 3 cone slope of this pixel (rho = kappa t), 0 in the linear mode
-};
 
 // Search radius of a ray at parameter t.
 __device__ __forceinline__ float rho_at(const SearchCtx &c, const RayGeom &g, float t)
@@ -259,101 +243,167 @@ __device__ __forceinline__ int wave_prefix_max_i32(int v)
     return v;
 }
 
-__device__ __forceinline__ RayGeom ray_geometry(const SearchCtx &c, int64_t ray)
-{
-    RayGeom r;
-    int vi = 0;
-    while (vi + 1 < c.n_views && c.views[vi + 1].ray_base <= ray) ++vi;
-    const ViewK &V = c.views[vi];
-    const int local = (int)(ray - V.ray_base);
-    r.vi = vi;
-    r.u = local % V.W;
-    r.v = local / V.W;
-    ray_dir(V, r.u, r.v, r.dx, r.dy, r.dz, r.a, r.b, r.L);
-    r.wn = __builtin_sqrtf(r.a * r.a + r.b * r.b);
-    // Eq. 3 on the unit-focal image plane: BF = rddot / L over AB, AF or AE
-    r.kappa = 0.0f;
-    if (c.rmode != HP_RADIUS_LINEAR) {
-        const float bf = c.rddot / r.L;
-        if (c.rmode == HP_RADIUS_EQ3) {
-            const float m = r.wn - c.rddot;
-            r.kappa = bf / __builtin_sqrtf(fma_rn(m, m, 1.0f));
-        } else if (c.rmode == HP_RADIUS_EQ3_AF) {
-            r.kappa = bf / fma_rn(-bf, r.wn, r.L);
-        } else {
-            r.kappa = bf / r.L;
-        }
-    }
-    return r;
-}
-
-// Minimum depth of the 8x8-bucket cells holding buckets within h of grid
-// position (gx, gy).  Lane-resident: lane q keeps cell q of the widest window
-// so narrower windows re-reduce without reloading (up to 64 cells; larger
-// windows loop).
-struct CellWindow {
-    int cx0, cy0, ncw, ncell;
-    float z;  // this lane's cell minimum (+inf if none)
-    int cxx, cyy;
-};
-
-__device__ __forceinline__ CellWindow load_cells(const SearchCtx &c, const ViewK &V, int gx, int gy,
+// Minimum depth over the depth cells holding the buckets within h of grid
+// position (gx, gy) (+inf if they are all empty).  One lane.
+__device__ __forceinline__ float lane_cells_zmin(const SearchCtx &c, const ViewK &V, int gx, int gy,
                                                  int h)
 {
-    const int l = lane_id();
-    CellWindow w;
-    w.cx0 = max(gx - h, 0) >> CELL_SHIFT;
-    w.cy0 = max(gy - h, 0) >> CELL_SHIFT;
-    const int cx1 = min(gx + h, V.Wg - 1) >> CELL_SHIFT, cy1 = min(gy + h, V.Hg - 1) >> CELL_SHIFT;
-    w.ncw = cx1 - w.cx0 + 1;
-    w.ncell = w.ncw * (cy1 - w.cy0 + 1);
-    w.z = __builtin_inff();
-    w.cxx = w.cyy = -1;
-    for (int q0 = 0; q0 < w.ncell; q0 += WAVE) {
-        const int q = q0 + l;
-        if (q < w.ncell) {
-            const int qy = q / w.ncw;
-            const int cxx = w.cx0 + (q - qy * w.ncw), cyy = w.cy0 + qy;
-            w.z = __builtin_fminf(w.z, __uint_as_float(c.cell_zmin[V.cell_base + cyy * V.ncx + cxx]));
-            if (q0 == 0) {
-                w.cxx = cxx;
-                w.cyy = cyy;
-            }
-        }
-    }
-    return w;
-}
-
-// Minimum over the cells of the narrower window h (exact when the widest
-// window had at most 64 cells; otherwise the wide minimum, still a bound).
-__device__ __forceinline__ float cells_zmin(const CellWindow &w, const ViewK &V, int gx, int gy, int h)
-{
-    float z = w.z;
-    if (w.ncell <= WAVE) {
-        const bool in = w.cxx >= (max(gx - h, 0) >> CELL_SHIFT) &&
-                        w.cxx <= (min(gx + h, V.Wg - 1) >> CELL_SHIFT) &&
-                        w.cyy >= (max(gy - h, 0) >> CELL_SHIFT) &&
-                        w.cyy <= (min(gy + h, V.Hg - 1) >> CELL_SHIFT);
-        z = in ? z : __builtin_inff();
-    }
-    return wave_min_f32(z);
+    const int cx0 = max(gx - h, 0) >> CELL_SHIFT, cx1 = min(gx + h, V.Wg - 1) >> CELL_SHIFT;
+    const int cy0 = max(gy - h, 0) >> CELL_SHIFT, cy1 = min(gy + h, V.Hg - 1) >> CELL_SHIFT;
+    float z = __builtin_inff();
+    for (int cy = cy0; cy <= cy1; ++cy)
+        for (int cx = cx0; cx <= cx1; ++cx)
+            z = __builtin_fminf(z, __uint_as_float(c.cell_zmin[V.cell_base + cy * V.ncx + cx]));
+    return z;
 }
 
 // Window radius (pixels) for neighbours whose depth is at least zmin.
-__device__ __forceinline__ float radius_for_depth(const SearchCtx &c, const RayGeom &g, float f,
-                                                  float L2, float zmin, float dcap, float dinf)
+__device__ __forceinline__ float radius_for_depth(const SearchCtx &c, float kappa, float L, float wn,
+                                                  float f, float L2, float zmin, float dcap,
+                                                  float dinf)
 {
     // a pure cone projects to a disc whose radius does not depend on depth
     if (c.rmode != HP_RADIUS_LINEAR) return dinf < dcap ? dinf : dcap;
     const float k = c.radius * c.inv_tref;
-    float t = (g.L * zmin - g.wn * c.radius) / (1.0f + g.wn * k);
+    float t = (L * zmin - wn * c.radius) / (1.0f + wn * k);
     t = t * 0.9999f - 1e-6f;
     if (!(t > c.t_near)) t = c.t_near;
-    const float rho = rho_at(c, g, t);
-    const float den = t - rho * g.wn;
+    const float rho = search_radius(c.radius, c.inv_tref, t);
+    const float den = t - rho * wn;
     if (!(den > 0.0f)) return dcap;
     const float d = (f * rho * L2 / den) * 1.0001f + 0.01f;
     return d < dcap ? d : dcap;
+}
+
+// Geometry and search bounds of one ray, computed by one lane.  The window:
+// a neighbour projects at most delta(t) = f rho L^2 / (t - rho |w|) pixels
+// from the pixel centre, and delta does not grow with t; the smallest depth
+// of the depth cells around the pixel bounds t from below, so two rounds
+// (each over the cells of the previous radius) shrink the window from the
+// view-wide bound.  If every such cell is empty, no point is near the ray.
+__device__ __forceinline__ RayGeom ray_setup(const SearchCtx &c, int64_t ray)
+{
+    RayGeom g;
+    int vi = 0;
+    while (vi + 1 < c.n_views && c.views[vi + 1].ray_base <= ray) ++vi;
+    const ViewK &V = c.views[vi];
+    const int local = (int)(ray - V.ray_base);
+    const int u = local % V.W, v = local / V.W;
+    float a, b, L;
+    ray_dir(V, u, v, g.dx, g.dy, g.dz, a, b, L);
+    g.vi = vi;
+    g.wn = __builtin_sqrtf(a * a + b * b);
+    // Eq. 3 on the unit-focal image plane: BF = rddot / L over AB, AF or AE
+    g.kappa = 0.0f;
+    if (c.rmode != HP_RADIUS_LINEAR) {
+        const float bf = c.rddot / L;
+        if (c.rmode == HP_RADIUS_EQ3) {
+            const float m = g.wn - c.rddot;
+            g.kappa = bf / __builtin_sqrtf(fma_rn(m, m, 1.0f));
+        } else if (c.rmode == HP_RADIUS_EQ3_AF) {
+            g.kappa = bf / fma_rn(-bf, g.wn, L);
+        } else {
+            g.kappa = bf / L;
+        }
+    }
+    const float L2 = fma_rn(g.wn, g.wn, 1.0f);
+    const float f = V.fx > V.fy ? V.fx : V.fy;
+    const float rho_n = rho_at(c, g, c.t_near);
+    const float rho_f = rho_at(c, g, c.t_far);
+    g.z_lo = ((c.t_near - g.wn * rho_n) / L) * 0.999f - 1e-6f;
+    g.z_hi = ((c.t_far + g.wn * rho_f) / L) * 1.001f + 1e-6f;
+    // pixel offset bound once rho has reached its linear branch
+    g.dinf = 0.0f;
+    const float klin = c.rmode == HP_RADIUS_LINEAR ? c.radius * c.inv_tref : g.kappa;
+    if (klin > 0.0f) {
+        const float den = 1.0f - klin * g.wn;
+        g.dinf = den > 0.0f ? (f * klin * L2 / den) * 1.001f + 0.01f : __builtin_inff();
+    }
+    g.frL2 = f * c.radius * L2;
+    g.two_rw = 2.0f * c.radius * g.wn;
+    g.inv_L = 1.0f / L;
+    g.gx = u + V.g;
+    g.gy = v + V.g;
+    float Dmax = V.dmax;
+    int h = min((int)__builtin_floorf(Dmax + 0.5f), V.g);
+    for (int round = 0; round < 2; ++round) {
+        const float zmin = lane_cells_zmin(c, V, g.gx, g.gy, h);
+        if (!(zmin < __builtin_inff())) {
+            h = -1;  // no point anywhere near this ray
+            break;
+        }
+        Dmax = radius_for_depth(c, g.kappa, L, g.wn, f, L2, zmin, Dmax, g.dinf);
+        h = min((int)__builtin_floorf(Dmax + 0.5f), V.g);
+    }
+    g.h = h;
+    g.Dmax = Dmax;
+    return g;
+}
+
+__device__ __forceinline__ float uniform_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// A ray's set-up as the whole wave reads it back from the LDS.
+__device__ __forceinline__ RayGeom load_ray(const RayGeom &src)
+{
+    RayGeom g;
+    g.vi = uniform_i32(src.vi);
+    g.gx = uniform_i32(src.gx);
+    g.gy = uniform_i32(src.gy);
+    g.h = uniform_i32(src.h);
+    g.dx = uniform_f32(src.dx);
+    g.dy = uniform_f32(src.dy);
+    g.dz = uniform_f32(src.dz);
+    g.wn = uniform_f32(src.wn);
+    g.kappa = uniform_f32(src.kappa);
+    g.inv_L = uniform_f32(src.inv_L);
+    g.z_lo = uniform_f32(src.z_lo);
+    g.z_hi = uniform_f32(src.z_hi);
+    g.dinf = uniform_f32(src.dinf);
+    g.frL2 = uniform_f32(src.frL2);
+    g.two_rw = uniform_f32(src.two_rw);
+    g.Dmax = uniform_f32(src.Dmax);
+    return g;
+}
+
+// Persistent iteration over the rays of a launch, one ray at a time per
+// workgroup, body(ray, geometry).  Workgroups take chunks of c.chunk
+// consecutive rays (neighbouring pixels share table buckets).  They are dealt
+// to the eight XCDs round-robin (workgroup b runs on XCD b % 8), each with its
+// own L2, so the chunks are grouped into bands of BAND_RAYS consecutive rays
+// and XCD x takes bands x, x + 8, ...: the rays one XCD's workgroups search at
+// a time are then neighbours and share that L2's table lines.  Within its
+// bands an XCD's workgroups stride by their number, so each still sees a mix
+// of empty and busy regions.  The grid must be a multiple of 8.
+// The per-ray set-up (divisions, square roots, the depth-cell rounds) is
+// uniform work that a whole wave would repeat on every lane; lanes instead
+// compute it for up to RS_CAP rays of the chunk at once into the LDS.
+template <typename Body>
+__device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, RayGeom *rs, Body body)
+{
+    const int l = lane_id();
+    const int64_t n_chunks = (c.n_rays + c.chunk - 1) / c.chunk;
+    const int64_t band = (BAND_RAYS + c.chunk - 1) / c.chunk;  // chunks per band
+    const int xcd = blockIdx.x & 7;
+    const int64_t slot = blockIdx.x >> 3, n_slots = gridDim.x >> 3;
+    const int64_t n_bands = (n_chunks + band - 1) / band;
+    const int64_t my_chunks = (n_bands > xcd ? (n_bands - xcd + 7) / 8 : 0) * band;
+    for (int64_t li = slot; li < my_chunks; li += n_slots) {
+        const int64_t ch = (xcd + 8 * (li / band)) * band + li % band;
+        if (ch >= n_chunks) continue;
+        const int64_t r1 = min((ch + 1) * c.chunk, c.n_rays);
+        for (int64_t s0 = ch * c.chunk; s0 < r1; s0 += RS_CAP) {
+            const int n = (int)min((int64_t)RS_CAP, r1 - s0);
+            lds_sync();
+            if (l < n) rs[l] = ray_setup(c, s0 + l);
+            lds_sync();
+            for (int k = 0; k < n; ++k) body(s0 + k, load_ray(rs[k]));
+        }
+    }
 }
 
 // Search one ray.  Returns, in `top` (one key per lane, ascending), the
@@ -367,39 +417,13 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
 {
     const int l = lane_id();
     const ViewK &V = c.views[g.vi];
-    const float L2 = fma_rn(g.wn, g.wn, 1.0f);
-    const float f = V.fx > V.fy ? V.fx : V.fy;
-    const float rho_n = rho_at(c, g, c.t_near);
-    const float rho_f = rho_at(c, g, c.t_far);
-    const float z_lo = ((c.t_near - g.wn * rho_n) / g.L) * 0.999f - 1e-6f;
-    const float z_hi = ((c.t_far + g.wn * rho_f) / g.L) * 1.001f + 1e-6f;
-    // pixel offset bound once rho has reached its linear branch
-    float dinf = 0.0f;
-    const float klin = c.rmode == HP_RADIUS_LINEAR ? c.radius * c.inv_tref : g.kappa;
-    if (klin > 0.0f) {
-        const float den = 1.0f - klin * g.wn;
-        dinf = den > 0.0f ? (f * klin * L2 / den) * 1.001f + 0.01f : __builtin_inff();
-    }
-    const float frL2 = f * c.radius * L2;
-    const float two_rw = 2.0f * c.radius * g.wn;
-    const int gx = g.u + V.g, gy = g.v + V.g;
+    const float z_lo = g.z_lo, z_hi = g.z_hi, dinf = g.dinf;
+    const float frL2 = g.frL2, two_rw = g.two_rw, inv_L = g.inv_L, Dmax = g.Dmax;
+    const int gx = g.gx, gy = g.gy, h = g.h;
 
     top = ~0ull;
     count = 0;
-
-    // window radius from the depth cells
-    float Dmax = V.dmax;
-    int h = min((int)__builtin_floorf(Dmax + 0.5f), V.g);
-    {
-        const CellWindow cw = load_cells(c, V, gx, gy, h);
-#pragma unroll
-        for (int round = 0; round < 2; ++round) {
-            const float zmin = cells_zmin(cw, V, gx, gy, h);
-            if (!(zmin < __builtin_inff())) return;  // no point anywhere near this ray
-            Dmax = radius_for_depth(c, g, f, L2, zmin, Dmax, dinf);
-            h = min((int)__builtin_floorf(Dmax + 0.5f), V.g);
-        }
-    }
+    if (h < 0) return;  // no point anywhere near this ray
 
     uint64_t tau = ~0ull;
     int npend = 0;
@@ -470,7 +494,6 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
 
     // one window bucket at offset (dxi, dyi) from the pixel's bucket: returns
     // whether it may hold a neighbour, and its slots
-    const float inv_L = 1.0f / g.L;
     auto zmax_at = [&](float D) -> float {
         // bounds only (margins of 1e-3 px and 0.1% dwarf 1-ulp approximations)
         const float Dp = D - 0.01f;

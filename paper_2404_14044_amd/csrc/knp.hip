@@ -23,8 +23,7 @@ k_knp(SearchCtx c, KnpArgs a)
 {
     __shared__ SearchLds sh;
     const int l = lane_id();
-    for_each_ray_banded(c, [&](int64_t ray) {
-        const RayGeom g = ray_geometry(c, ray);
+    for_each_ray_banded(c, sh.rs, [&](int64_t ray, const RayGeom &g) {
         uint64_t top;
         int count;
         search_neighbours<true>(c, g, sh, top, count);

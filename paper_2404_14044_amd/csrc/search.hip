@@ -10,8 +10,7 @@ __device__ __forceinline__ void search_sample_body(const SearchCtx &c, const Sam
 {
     __shared__ SearchLds sh;
     const int l = lane_id();
-    for_each_ray_banded(c, [&](int64_t ray) {
-        const RayGeom g = ray_geometry(c, ray);
+    for_each_ray_banded(c, sh.rs, [&](int64_t ray, const RayGeom &g) {
         uint64_t top;
         int count;
         search_neighbours(c, g, sh, top, count);
