@@ -644,12 +644,6 @@ __device__ __forceinline__ void merge_low(uint64_t (&a)[KT], const uint64_t (&b)
     }
 }
 
-// Nearest neighbours of 16 candidates at once.  Lane l = 4 g + q serves
-// candidate c0 + g; its four lanes split the candidate's t-window of the
-// sorted list (entries lo + q, lo + q + 4, ...), each keeping an ascending
-// register list of (dist^2 bits << 32 | index) among entries within R_j, and
-// the quad then merges its four lists (DPP within the quad).  On return every
-// lane of the quad holds the candidate's KT smallest keys (~0 = none).
 // Quad-split nearest neighbours of the ray point at tq among the sorted-list
 // entries [lo, hi) within R2: lane q of each quad takes entries lo + q,
 // lo + q + 4, ... into an ascending register list of (dist^2 bits << 32 |
@@ -667,17 +661,35 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
     n_it = max(n_it, (int)xor_lane_u32<8>((uint32_t)n_it));
     n_it = max(n_it, (int)xor_lane_u32<16>((uint32_t)n_it));
     n_it = max(n_it, (int)xor_lane_u32<32>((uint32_t)n_it));
-    for (int it = 0; it < n_it; ++it) {
-        const int i = lo + q + 4 * it;
-        uint64_t x = ~0ull;
-        if (i < hi) {
-            const float4 P = sh.nb_p[i];
-            const float d2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, tq);
-            if (d2 <= R2) x = ((uint64_t)__float_as_uint(d2) << 32) | __float_as_uint(P.w);
-        }
-        // branch-free insertion: a key of ~0 leaves the list unchanged
+    // entries four at a time: sort the four keys (five compare-exchanges),
+    // then merge them into the list as the upper half of a bitonic sequence
+    for (int it = 0; it < n_it; it += 4) {
+        uint64_t x[4];
 #pragma unroll
-        for (int k = 0; k < KT; ++k) cswap64(kd[k], x);
+        for (int e = 0; e < 4; ++e) {
+            const int i = lo + q + 4 * (it + e);
+            x[e] = ~0ull;
+            if (i < hi) {
+                const float4 P = sh.nb_p[i];
+                const float d2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, tq);
+                if (d2 <= R2) x[e] = ((uint64_t)__float_as_uint(d2) << 32) | __float_as_uint(P.w);
+            }
+        }
+        cswap64(x[0], x[1]);
+        cswap64(x[2], x[3]);
+        cswap64(x[0], x[2]);
+        cswap64(x[1], x[3]);
+        cswap64(x[1], x[2]);
+        static_assert(KT >= 4, "lists of at least four");
+#pragma unroll
+        for (int e = 0; e < 4; ++e) kd[KT - 4 + e] = umin64(kd[KT - 4 + e], x[3 - e]);
+        // kd is now bitonic and holds the KT smallest: half-cleaners sort it
+#pragma unroll
+        for (int j = KT / 2; j > 0; j >>= 1) {
+#pragma unroll
+            for (int k = 0; k < KT; ++k)
+                if ((k & j) == 0) cswap64(kd[k], kd[k + j]);
+        }
     }
     uint64_t other[KT];
 #pragma unroll
