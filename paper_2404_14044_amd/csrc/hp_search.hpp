@@ -80,7 +80,8 @@ struct RayGeom {
 };
 
 constexpr int BL_CAP = 128;
-constexpr int RS_CAP = 8;  // rays whose set-up one pass computes (lane per ray)
+constexpr int RS_CAP = 8;               // rays whose set-up one pass computes
+constexpr int RS_LANES = WAVE / RS_CAP;  // lanes per ray in that pass
 
 struct SearchLds {
     RayGeom rs[RS_CAP];
@@ -244,16 +245,21 @@ __device__ __forceinline__ int wave_prefix_max_i32(int v)
 }
 
 // Minimum depth over the depth cells holding the buckets within h of grid
-// position (gx, gy) (+inf if they are all empty).  One lane.
-__device__ __forceinline__ float lane_cells_zmin(const SearchCtx &c, const ViewK &V, int gx, int gy,
-                                                 int h)
+// position (gx, gy) (+inf if they are all empty), by the RS_LANES lanes of a
+// group (sub = lane within the group; every lane of the group returns it).
+__device__ __forceinline__ float group_cells_zmin(const SearchCtx &c, const ViewK &V, int gx, int gy,
+                                                  int h, int sub)
 {
     const int cx0 = max(gx - h, 0) >> CELL_SHIFT, cx1 = min(gx + h, V.Wg - 1) >> CELL_SHIFT;
     const int cy0 = max(gy - h, 0) >> CELL_SHIFT, cy1 = min(gy + h, V.Hg - 1) >> CELL_SHIFT;
     float z = __builtin_inff();
     for (int cy = cy0; cy <= cy1; ++cy)
-        for (int cx = cx0; cx <= cx1; ++cx)
+        for (int cx = cx0 + sub; cx <= cx1; cx += RS_LANES)
             z = __builtin_fminf(z, __uint_as_float(c.cell_zmin[V.cell_base + cy * V.ncx + cx]));
+    static_assert(RS_LANES == 8, "groups of eight lanes");
+    z = __builtin_fminf(z, __uint_as_float(xor_lane_u32<1>(__float_as_uint(z))));
+    z = __builtin_fminf(z, __uint_as_float(xor_lane_u32<2>(__float_as_uint(z))));
+    z = __builtin_fminf(z, __uint_as_float(xor_lane_u32<4>(__float_as_uint(z))));
     return z;
 }
 
@@ -275,13 +281,14 @@ __device__ __forceinline__ float radius_for_depth(const SearchCtx &c, float kapp
     return d < dcap ? d : dcap;
 }
 
-// Geometry and search bounds of one ray, computed by one lane.  The window:
+// Geometry and search bounds of one ray, computed by a group of RS_LANES
+// lanes (sub = lane within the group), which share the depth-cell rounds.  The window:
 // a neighbour projects at most delta(t) = f rho L^2 / (t - rho |w|) pixels
 // from the pixel centre, and delta does not grow with t; the smallest depth
 // of the depth cells around the pixel bounds t from below, so two rounds
 // (each over the cells of the previous radius) shrink the window from the
 // view-wide bound.  If every such cell is empty, no point is near the ray.
-__device__ __forceinline__ RayGeom ray_setup(const SearchCtx &c, int64_t ray)
+__device__ __forceinline__ RayGeom ray_setup(const SearchCtx &c, int64_t ray, int sub)
 {
     RayGeom g;
     int vi = 0;
@@ -327,7 +334,7 @@ __device__ __forceinline__ RayGeom ray_setup(const SearchCtx &c, int64_t ray)
     float Dmax = V.dmax;
     int h = min((int)__builtin_floorf(Dmax + 0.5f), V.g);
     for (int round = 0; round < 2; ++round) {
-        const float zmin = lane_cells_zmin(c, V, g.gx, g.gy, h);
+        const float zmin = group_cells_zmin(c, V, g.gx, g.gy, h, sub);
         if (!(zmin < __builtin_inff())) {
             h = -1;  // no point anywhere near this ray
             break;
@@ -380,8 +387,8 @@ __device__ __forceinline__ RayGeom load_ray(const RayGeom &src)
 // bands an XCD's workgroups stride by their number, so each still sees a mix
 // of empty and busy regions.  The grid must be a multiple of 8.
 // The per-ray set-up (divisions, square roots, the depth-cell rounds) is
-// uniform work that a whole wave would repeat on every lane; lanes instead
-// compute it for up to RS_CAP rays of the chunk at once into the LDS.
+// uniform work that a whole wave would repeat on every lane; groups of lanes
+// instead compute it for up to RS_CAP rays of the chunk at once into the LDS.
 template <typename Body>
 __device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, RayGeom *rs, Body body)
 {
@@ -399,7 +406,11 @@ __device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, RayGeom 
         for (int64_t s0 = ch * c.chunk; s0 < r1; s0 += RS_CAP) {
             const int n = (int)min((int64_t)RS_CAP, r1 - s0);
             lds_sync();
-            if (l < n) rs[l] = ray_setup(c, s0 + l);
+            // lanes 8 k .. 8 k + 7 set up ray s0 + k (lanes past the batch
+            // repeat its last ray)
+            const int k = l / RS_LANES;
+            const RayGeom gk = ray_setup(c, s0 + (k < n ? k : n - 1), l % RS_LANES);
+            if (l % RS_LANES == 0 && k < n) rs[k] = gk;
             lds_sync();
             for (int k = 0; k < n; ++k) body(s0 + k, load_ray(rs[k]));
         }
