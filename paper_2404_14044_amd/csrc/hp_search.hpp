@@ -399,20 +399,34 @@ __device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, RayGeom 
     const int64_t slot = blockIdx.x >> 3, n_slots = gridDim.x >> 3;
     const int64_t n_bands = (n_chunks + band - 1) / band;
     const int64_t my_chunks = (n_bands > xcd ? (n_bands - xcd + 7) / 8 : 0) * band;
-    for (int64_t li = slot; li < my_chunks; li += n_slots) {
+    // first ray and ray count of this workgroup's li-th chunk
+    auto chunk_rays = [&](int64_t li, int64_t &r0, int &n) {
+        n = 0;
+        r0 = 0;
+        if (li >= my_chunks) return;
         const int64_t ch = (xcd + 8 * (li / band)) * band + li % band;
-        if (ch >= n_chunks) continue;
-        const int64_t r1 = min((ch + 1) * c.chunk, c.n_rays);
-        for (int64_t s0 = ch * c.chunk; s0 < r1; s0 += RS_CAP) {
-            const int n = (int)min((int64_t)RS_CAP, r1 - s0);
+        if (ch >= n_chunks) return;
+        r0 = ch * c.chunk;
+        n = (int)min((int64_t)c.chunk, c.n_rays - r0);
+    };
+    // two chunks per set-up pass (the chunks themselves stay small, for balance)
+    for (int64_t li = slot; li < my_chunks; li += 2 * n_slots) {
+        int64_t ra, rb;
+        int na, nb;
+        chunk_rays(li, ra, na);
+        chunk_rays(li + n_slots, rb, nb);
+        const int ntot = na + nb;
+        auto ray_at = [&](int i) -> int64_t { return i < na ? ra + i : rb + (i - na); };
+        for (int s0 = 0; s0 < ntot; s0 += RS_CAP) {
+            const int n = min(RS_CAP, ntot - s0);
             lds_sync();
             // lanes 8 k .. 8 k + 7 set up ray s0 + k (lanes past the batch
             // repeat its last ray)
             const int k = l / RS_LANES;
-            const RayGeom gk = ray_setup(c, s0 + (k < n ? k : n - 1), l % RS_LANES);
+            const RayGeom gk = ray_setup(c, ray_at(s0 + (k < n ? k : n - 1)), l % RS_LANES);
             if (l % RS_LANES == 0 && k < n) rs[k] = gk;
             lds_sync();
-            for (int k = 0; k < n; ++k) body(s0 + k, load_ray(rs[k]));
+            for (int i = 0; i < n; ++i) body(ray_at(s0 + i), load_ray(rs[i]));
         }
     }
 }
@@ -435,6 +449,13 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
     top = ~0ull;
     count = 0;
     if (h < 0) return;  // no point anywhere near this ray
+    // the view's grid, read once (the loops below would reload it after
+    // every store they cannot prove unrelated)
+    ViewK Vg;
+    Vg.Wg = V.Wg;
+    Vg.Hg = V.Hg;
+    Vg.bucket_base = V.bucket_base;
+    const int Wg = Vg.Wg, Hg = Vg.Hg, cell_base = V.cell_base, ncx = V.ncx;
 
     uint64_t tau = ~0ull;
     int npend = 0;
@@ -525,9 +546,9 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
         if (!valid) return false;
         const int bx = gx + dxi, by = gy + dyi;
         const float D = offset_D(dxi < 0 ? -dxi : dxi, dyi < 0 ? -dyi : dyi);
-        if (!(bx >= 0 && bx < V.Wg && by >= 0 && by < V.Hg && D <= Dmax)) return false;
+        if (!(bx >= 0 && bx < Wg && by >= 0 && by < Hg && D <= Dmax)) return false;
         zmax = zmax_at(D);
-        const int key = bucket_of(V, c.layout, bx, by);
+        const int key = bucket_of(Vg, c.layout, bx, by);
         st = c.offsets[key];
         cnt = c.offsets[key + 1] - st;
         return cnt > 0 && c.bucket_z[key] <= zmax;
@@ -573,8 +594,8 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
         return;
     }
     int4 *const cl = reinterpret_cast<int4 *>(sh.nb_p);  // (bx0, by0, width, prefix)
-    const int wx0 = max(gx - h, 0), wx1 = min(gx + h, V.Wg - 1);
-    const int wy0 = max(gy - h, 0), wy1 = min(gy + h, V.Hg - 1);
+    const int wx0 = max(gx - h, 0), wx1 = min(gx + h, Wg - 1);
+    const int wy0 = max(gy - h, 0), wy1 = min(gy + h, Hg - 1);
     const int cx0 = wx0 >> CELL_SHIFT, cy0 = wy0 >> CELL_SHIFT;
     const int ncw = (wx1 >> CELL_SHIFT) - cx0 + 1;
     const int ncell = ncw * ((wy1 >> CELL_SHIFT) - cy0 + 1);
@@ -593,7 +614,7 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
             const int adx = gx < bx0 ? bx0 - gx : (gx > bx1 ? gx - bx1 : 0);
             const int ady = gy < by0 ? by0 - gy : (gy > by1 ? gy - by1 : 0);
             const float D = offset_D(adx, ady);
-            const float cz = __uint_as_float(c.cell_zmin[V.cell_base + cyy * V.ncx + cxx]);
+            const float cz = __uint_as_float(c.cell_zmin[cell_base + cyy * ncx + cxx]);
             keep = D <= Dmax && cz <= zmax_at(D);
         }
         const uint64_t km = ballot(keep);
