@@ -441,15 +441,34 @@ __global__ void __launch_bounds__(256) k_zero_f32(float *p, int64_t n)
     if (i < n) p[i] = 0.0f;
 }
 
-// Sum the per-wave slices in order and add to the gradients.
-__global__ void __launch_bounds__(256) k_reduce_partials(const float *__restrict__ partial, int nblk,
-                                                         float *gW1, float *gb1, float *gW2,
-                                                         float *gb2, float *gW3, float *gb3)
+// Sum the per-wave slices and add to the gradients, in a fixed order: each of
+// RED_G thread groups sums a contiguous range of slices in order, then the
+// group sums are added in group order.  (One thread per parameter walking
+// every slice would leave the chip idle: there are only 6,532 parameters.)
+constexpr int RED_P = 64;  // parameters per workgroup
+constexpr int RED_G = 16;  // slice ranges per parameter
+
+__global__ void __launch_bounds__(RED_P * RED_G) k_reduce_partials(const float *__restrict__ partial,
+                                                                  int nslice, float *gW1, float *gb1,
+                                                                  float *gW2, float *gb2, float *gW3,
+                                                                  float *gb3)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= NPAR) return;
+    __shared__ float sh[RED_G][RED_P];
+    const int p = threadIdx.x % RED_P, grp = threadIdx.x / RED_P;
+    const int i = blockIdx.x * RED_P + p;
+    const int per = (nslice + RED_G - 1) / RED_G;
+    const int b0 = grp * per, b1 = min(nslice, b0 + per);
     float s = 0.0f;
-    for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * NPAR + i];
+    if (i < NPAR) {
+#pragma unroll 8
+        for (int b = b0; b < b1; ++b) s += partial[(int64_t)b * NPAR + i];
+    }
+    sh[grp][p] = s;
+    __syncthreads();
+    if (grp != 0 || i >= NPAR) return;
+    float t = 0.0f;
+#pragma unroll
+    for (int k = 0; k < RED_G; ++k) t += sh[k][p];
     float *dst;
     int j;
     if (i < OFF_B1) { dst = gW1; j = i - OFF_W1; }
@@ -458,7 +477,7 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const float *__restrict
     else if (i < OFF_W3) { dst = gb2; j = i - OFF_B2; }
     else if (i < OFF_B3) { dst = gW3; j = i - OFF_W3; }
     else { dst = gb3; j = i - OFF_B3; }
-    dst[j] += s;
+    dst[j] += t;
 }
 
 size_t backward_partial_bytes() { return (size_t)BWD_MAX_BLOCKS * BWD_WAVES * NPAR * sizeof(float); }
@@ -488,8 +507,8 @@ hipError_t launch_backward(const BwdArgs &A, int precision, const MlpGrad &gm, h
         k_render_backward<HP_BF16><<<dim3((unsigned)nblk), dim3(WAVE * BWD_WAVES), 0, s>>>(A);
     else
         k_render_backward<HP_FP32><<<dim3((unsigned)nblk), dim3(WAVE * BWD_WAVES), 0, s>>>(A);
-    k_reduce_partials<<<(NPAR + 255) / 256, 256, 0, s>>>(A.partial, (int)nslice, gm.W1, gm.b1, gm.W2,
-                                                        gm.b2, gm.W3, gm.b3);
+    k_reduce_partials<<<(NPAR + RED_P - 1) / RED_P, RED_P * RED_G, 0, s>>>(
+        A.partial, (int)nslice, gm.W1, gm.b1, gm.W2, gm.b2, gm.W3, gm.b3);
     return hipGetLastError();
 }
 
