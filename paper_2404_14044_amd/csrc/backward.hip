@@ -12,7 +12,7 @@
 //            front of each sample forward, then the suffix sums of colour and
 //            transmittance backward -> dL/d(decoder outputs), in place;
 //   pass B   per tile: the decoder is replayed keeping its activations, the
-//            gradient flows back through it on the VALU in FP32 (weights
+//            gradient flows back through it on FP32 matrix cores (weights
 //            FP32) to the aggregated features, and through the aggregation
 //            to the point features with atomics.
 // Decoder-parameter gradients are accumulated per wave in a zeroed slice of
@@ -119,8 +119,12 @@ template <int PREC>
 __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
 {
     __shared__ BwdWave waves[BWD_WAVES];
-    // FP32 weights for the backward products, shared by the workgroup
-    __shared__ float sW1[HP_HIDDEN * HP_FEAT_DIM], sW2[HP_HIDDEN * HP_HIDDEN], sW3[4 * HP_HIDDEN];
+    // FP32 weight images for the backward products, shared by the workgroup:
+    // imgW2[(o1 4 + o2) 64 + lane].e = W2[16 o2 + 4 q + e][16 o1 + r],
+    // imgW1[(cb 4 + o1) 64 + lane].e = W1[16 o1 + 4 q + e][16 cb + r]
+    // (the A operands of dZ2 W2 and dZ1 W1 in the C layout's unit order)
+    __shared__ float4 imgW2[16 * WAVE], imgW1[8 * WAVE];
+    __shared__ float sW3[4 * HP_HIDDEN];
     const int wave = threadIdx.x >> 6;
     BwdWave &sh = waves[wave];
     // this wave's decoder-parameter gradients: its own zeroed workspace slice,
@@ -134,8 +138,18 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
         if constexpr (PREC == HP_BF16) load_mlp_bf16(A.w, m);
         else load_mlp_f32(A.w, m);
     };
-    for (int i = threadIdx.x; i < HP_HIDDEN * HP_FEAT_DIM; i += blockDim.x) sW1[i] = A.w.W1[i];
-    for (int i = threadIdx.x; i < HP_HIDDEN * HP_HIDDEN; i += blockDim.x) sW2[i] = A.w.W2[i];
+    for (int i = threadIdx.x; i < 16 * WAVE; i += blockDim.x) {
+        const int ln = i % WAVE, blk = i / WAVE, o1 = blk >> 2, o2 = blk & 3;
+        const int r = ln & 15, qq = ln >> 4;
+        const float *w = A.w.W2 + (16 * o2 + 4 * qq) * HP_HIDDEN + 16 * o1 + r;
+        imgW2[i] = make_float4(w[0], w[HP_HIDDEN], w[2 * HP_HIDDEN], w[3 * HP_HIDDEN]);
+    }
+    for (int i = threadIdx.x; i < 8 * WAVE; i += blockDim.x) {
+        const int ln = i % WAVE, blk = i / WAVE, cb = blk >> 2, o1 = blk & 3;
+        const int r = ln & 15, qq = ln >> 4;
+        const float *w = A.w.W1 + (16 * o1 + 4 * qq) * HP_FEAT_DIM + 16 * cb + r;
+        imgW1[i] = make_float4(w[0], w[HP_FEAT_DIM], w[2 * HP_FEAT_DIM], w[3 * HP_FEAT_DIM]);
+    }
     for (int i = threadIdx.x; i < 4 * HP_HIDDEN; i += blockDim.x) sW3[i] = A.w.W3[i];
     __syncthreads();
     // lane l: column l of dW3, entry l of db1 and db2, entry l < 4 of db3
@@ -226,16 +240,25 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
         }
         wave_lds_sync();
 
-        // pass B: per tile, replay the decoder keeping activations, then backward.
-        // Activations are stored unit-major (H?T[unit][sample]) so that a row
-        // of 16 samples is four 16-byte LDS reads; padding samples are zero.
+        // pass B: per tile, replay the decoder keeping its activations, then
+        // run the decoder backward on FP32 MFMA (v_mfma_f32_16x16x4f32, lane
+        // l = 16 q + r supplies A[r][q] and B[q][r] and holds D[4 q + e][r]).
+        // Activation gradients chain through the C layout like the forward
+        // (unit 16 b + 4 q + e of sample r), with the contraction index
+        // permuted in the weight images.  The weight gradients contract over
+        // the tile's samples, so their operands come from transposed LDS
+        // images [unit][TP(s)], TP(s) = 4 (s mod 4) + s / 4, where a lane's
+        // four samples q, q + 4, q + 8, q + 12 are one 16-byte read.
+        const int ps = 4 * (r16 & 3) + (r16 >> 2);  // TP(r16)
+        float *const FT = &sh.F[0][0];  // [feature][TP(s)], later [s][feature]
         for (int s0 = 0; s0 < total; s0 += 16) {
             const int nt = (total - s0) < 16 ? total - s0 : 16;
+            const int sidx = s0 + r16;
+            const bool valid = sidx < total;
+            f32x4 h1[4], h2[4];
+            int64_t row = -1;
             {
-                const int sidx = s0 + r16;
-                const bool valid = sidx < total;
                 float f[8];
-                int64_t row = -1;
                 float inv = 0.0f;
                 if (valid) {
                     row = sample_row(sh, A, ray0, nr, sidx);
@@ -244,7 +267,6 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
 #pragma unroll
                     for (int e = 0; e < 8; ++e) f[e] = 0.0f;
                 }
-                f32x4 h1[4], h2[4];
                 Mlp mlp;
                 // reload the weights here (cache hits) rather than keep them
                 // live across the whole backward
@@ -257,93 +279,27 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
                     sh.inv[r16] = inv;
                 }
 #pragma unroll
-                for (int e = 0; e < 8; ++e) sh.F[r16][8 * q + e] = f[e];
-#pragma unroll
                 for (int ob = 0; ob < 4; ++ob)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        sh.H1T[16 * ob + 4 * q + e][r16] = valid ? h1[ob][e] : 0.0f;
-                        sh.H2T[16 * ob + 4 * q + e][r16] = valid ? h2[ob][e] : 0.0f;
+                        if (!valid) {
+                            h1[ob][e] = 0.0f;
+                            h2[ob][e] = 0.0f;
+                        }
+                        sh.H1T[16 * ob + 4 * q + e][ps] = h1[ob][e];
+                        sh.H2T[16 * ob + 4 * q + e][ps] = h2[ob][e];
                     }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) FT[(8 * q + e) * 16 + ps] = f[e];
             }
-            wave_lds_sync();
-            // output layer: lane l is hidden unit l of layer 2
-            {
-                const float w30 = sW3[0 * HP_HIDDEN + l], w31 = sW3[1 * HP_HIDDEN + l],
-                            w32 = sW3[2 * HP_HIDDEN + l], w33 = sW3[3 * HP_HIDDEN + l];
-                for (int s = 0; s < nt; ++s) {
-                    const float4 d = sh.o[s0 + s];
-                    const float h = sh.H2T[l][s];
-                    gW3[0] = fma_rn(d.x, h, gW3[0]);
-                    gW3[1] = fma_rn(d.y, h, gW3[1]);
-                    gW3[2] = fma_rn(d.z, h, gW3[2]);
-                    gW3[3] = fma_rn(d.w, h, gW3[3]);
-                    float dp = w30 * d.x;
-                    dp = fma_rn(w31, d.y, dp);
-                    dp = fma_rn(w32, d.z, dp);
-                    dp = fma_rn(w33, d.w, dp);
-                    const float dh = h > 0.0f ? dp : 0.0f;
-                    sh.H2T[l][s] = dh;  // activation no longer needed
-                    gb2 += dh;
-                    if (l < 4) gb3 += (l == 0) ? d.x : (l == 1) ? d.y : (l == 2) ? d.z : d.w;
-                }
-            }
-            wave_lds_sync();
-            // hidden layer 2 -> 1: lane l is hidden unit l of layer 1
-            {
-                float acc[16], h1v[16];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const float4 v = *reinterpret_cast<const float4 *>(&sh.H1T[l][4 * k]);
-                    h1v[4 * k] = v.x;
-                    h1v[4 * k + 1] = v.y;
-                    h1v[4 * k + 2] = v.z;
-                    h1v[4 * k + 3] = v.w;
-                }
-#pragma unroll
-                for (int s = 0; s < 16; ++s) acc[s] = 0.0f;
-#pragma unroll 4
-                for (int o2 = 0; o2 < HP_HIDDEN; ++o2) {
-                    const float w = sW2[o2 * HP_HIDDEN + l];
-                    float gw = 0.0f;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const float4 d = *reinterpret_cast<const float4 *>(&sh.H2T[o2][4 * k]);
-                        acc[4 * k] = fma_rn(w, d.x, acc[4 * k]);
-                        acc[4 * k + 1] = fma_rn(w, d.y, acc[4 * k + 1]);
-                        acc[4 * k + 2] = fma_rn(w, d.z, acc[4 * k + 2]);
-                        acc[4 * k + 3] = fma_rn(w, d.w, acc[4 * k + 3]);
-                        gw = fma_rn(d.x, h1v[4 * k], gw);
-                        gw = fma_rn(d.y, h1v[4 * k + 1], gw);
-                        gw = fma_rn(d.z, h1v[4 * k + 2], gw);
-                        gw = fma_rn(d.w, h1v[4 * k + 3], gw);
-                    }
-                    atomicAdd(&gpar[OFF_W2 + o2 * HP_HIDDEN + l], gw);
-                }
-                float4 *dst = reinterpret_cast<float4 *>(&sh.H1T[l][0]);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    float4 v;
-                    v.x = h1v[4 * k] > 0.0f ? acc[4 * k] : 0.0f;
-                    v.y = h1v[4 * k + 1] > 0.0f ? acc[4 * k + 1] : 0.0f;
-                    v.z = h1v[4 * k + 2] > 0.0f ? acc[4 * k + 2] : 0.0f;
-                    v.w = h1v[4 * k + 3] > 0.0f ? acc[4 * k + 3] : 0.0f;
-                    gb1 += v.x;
-                    gb1 += v.y;
-                    gb1 += v.z;
-                    gb1 += v.w;
-                    dst[k] = v;
-                }
-            }
-            wave_lds_sync();
             // the tile's neighbour lists, fetched now (all loads independent,
-            // in flight during the layer-1 products) and staged in LDS after them
+            // in flight during the products) and staged in LDS after them
             // lane (r16, q): entries q, q + 4, ... of sample r16
             constexpr int PF = HP_MAX_K / 4;
             int32_t pf_i[PF];
             float pf_d[PF];
             {
-                const int64_t prow = sh.row[r16];
+                const int64_t prow = row;
 #pragma unroll
                 for (int m = 0; m < PF; ++m) {
                     const int k = q + 4 * m;
@@ -355,71 +311,190 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
                     }
                 }
             }
-            // layer 1 -> aggregated features, and dW1: lane l is feature l & 31
-            // of samples 8 (l >> 5) .. +7
+            wave_lds_sync();
+            // output layer: dW3 and db3 on the VALU, lane l = hidden unit l
+            {
+                float hrow[16];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float4 v = *reinterpret_cast<const float4 *>(&sh.H2T[l][4 * k]);
+                    hrow[4 * k] = v.x;
+                    hrow[4 * k + 1] = v.y;
+                    hrow[4 * k + 2] = v.z;
+                    hrow[4 * k + 3] = v.w;
+                }
+#pragma unroll
+                for (int s = 0; s < 16; ++s) {
+                    if (s < nt) {
+                        const float4 d = sh.o[s0 + s];
+                        const float h = hrow[4 * (s & 3) + (s >> 2)];
+                        gW3[0] = fma_rn(d.x, h, gW3[0]);
+                        gW3[1] = fma_rn(d.y, h, gW3[1]);
+                        gW3[2] = fma_rn(d.z, h, gW3[2]);
+                        gW3[3] = fma_rn(d.w, h, gW3[3]);
+                        if (l < 4) gb3 += (l == 0) ? d.x : (l == 1) ? d.y : (l == 2) ? d.z : d.w;
+                    }
+                }
+            }
+            // dZ2 = (dO W3) masked by layer 2's ReLU: A = W3[q][unit], B = dO[s][q]
+            f32x4 dz2[4];
+            {
+                float dOq = 0.0f;
+                if (valid) {
+                    const float4 d = sh.o[sidx];
+                    dOq = q == 0 ? d.x : (q == 1 ? d.y : (q == 2 ? d.z : d.w));
+                }
+#pragma unroll
+                for (int ob = 0; ob < 4; ++ob) {
+                    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(sW3[q * HP_HIDDEN + 16 * ob + r16], dOq, acc, 0, 0, 0);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) dz2[ob][e] = h2[ob][e] > 0.0f ? acc[e] : 0.0f;
+                }
+            }
+            wave_lds_sync();  // H2T (activations) fully read
+#pragma unroll
+            for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sh.H2T[16 * ob + 4 * q + e][ps] = dz2[ob][e];
+            wave_lds_sync();
+            // db2 (lane l = unit l) and dW2 += dZ2^T H1 over the tile's samples
+            {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float4 v = *reinterpret_cast<const float4 *>(&sh.H2T[l][4 * k]);
+                    gb2 += v.x;
+                    gb2 += v.y;
+                    gb2 += v.z;
+                    gb2 += v.w;
+                }
+                float4 b1[4];
+#pragma unroll
+                for (int ob = 0; ob < 4; ++ob)
+                    b1[ob] = *reinterpret_cast<const float4 *>(&sh.H1T[16 * ob + r16][4 * q]);
+                // block (o2, o1): lane holds dW2[16 o2 + 4 q + e][16 o1 + r16]
+#pragma unroll 1
+                for (int o2 = 0; o2 < 4; ++o2) {
+                    const float4 a2 = *reinterpret_cast<const float4 *>(&sh.H2T[16 * o2 + r16][4 * q]);
+#pragma unroll
+                    for (int o1 = 0; o1 < 4; ++o1) {
+                        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.x, b1[o1].x, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.y, b1[o1].y, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.z, b1[o1].z, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.w, b1[o1].w, acc, 0, 0, 0);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            atomicAdd(&gpar[OFF_W2 + (16 * o2 + 4 * q + e) * HP_HIDDEN + 16 * o1 + r16], acc[e]);
+                    }
+                }
+            }
+            // dZ1 = (dZ2 W2) masked by layer 1's ReLU; step (ob2, e) contracts
+            // unit 16 ob2 + 4 q + e of layer 2
+            f32x4 dz1[4];
+#pragma unroll
+            for (int o1 = 0; o1 < 4; ++o1) {
+                f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int o2 = 0; o2 < 4; ++o2) {
+                    const float4 w = imgW2[(o1 * 4 + o2) * WAVE + l];
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w.x, dz2[o2][0], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w.y, dz2[o2][1], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w.z, dz2[o2][2], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w, dz2[o2][3], acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dz1[o1][e] = h1[o1][e] > 0.0f ? acc[e] : 0.0f;
+            }
+            wave_lds_sync();  // H1T (activations) fully read
+#pragma unroll
+            for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) sh.H1T[16 * ob + 4 * q + e][ps] = dz1[ob][e];
+            wave_lds_sync();
+            // db1 (lane l = unit l) and dW1 += dZ1^T F over the tile's samples
+            {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float4 v = *reinterpret_cast<const float4 *>(&sh.H1T[l][4 * k]);
+                    gb1 += v.x;
+                    gb1 += v.y;
+                    gb1 += v.z;
+                    gb1 += v.w;
+                }
+                float4 bf[2];
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    bf[cb] = *reinterpret_cast<const float4 *>(&FT[(16 * cb + r16) * 16 + 4 * q]);
+                // block (o1, cb): lane holds dW1[16 o1 + 4 q + e][16 cb + r16]
+#pragma unroll 1
+                for (int o1 = 0; o1 < 4; ++o1) {
+                    const float4 a1 = *reinterpret_cast<const float4 *>(&sh.H1T[16 * o1 + r16][4 * q]);
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb) {
+                        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, bf[cb].x, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, bf[cb].y, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.z, bf[cb].z, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.w, bf[cb].w, acc, 0, 0, 0);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            atomicAdd(&gpar[OFF_W1 + (16 * o1 + 4 * q + e) * HP_FEAT_DIM + 16 * cb + r16], acc[e]);
+                    }
+                }
+            }
+            // dF = dZ1 W1 (gradient of the aggregated features), written as
+            // [sample][feature] over the feature image once dW1 has read it
+            f32x4 dF[2];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int o1 = 0; o1 < 4; ++o1) {
+                    const float4 w = imgW1[(cb * 4 + o1) * WAVE + l];
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w.x, dz1[o1][0], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w.y, dz1[o1][1], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w.z, dz1[o1][2], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w, dz1[o1][3], acc, 0, 0, 0);
+                }
+                dF[cb] = acc;
+            }
+            wave_lds_sync();  // the feature image fully read
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+                *reinterpret_cast<float4 *>(&sh.F[r16][16 * cb + 4 * q]) =
+                    make_float4(dF[cb][0], dF[cb][1], dF[cb][2], dF[cb][3]);
+            // stage (index, normalised weight) of every neighbour of the tile
+            // in the layer-2 area, now dead: [sample][K] each
+            int32_t *const s_idx = reinterpret_cast<int32_t *>(&sh.H2T[0][0]);
+            float *const s_w = &sh.H2T[0][0] + 16 * HP_MAX_K;
+            {
+                const float pinv = sh.inv[r16];
+#pragma unroll
+                for (int m = 0; m < PF; ++m) {
+                    const int k = q + 4 * m;
+                    if (k < A.K) {
+                        const float d = pf_d[m];
+                        s_idx[r16 * A.K + k] = pf_i[m];
+                        s_w[r16 * A.K + k] =
+                            pf_i[m] >= 0 ? (1.0f / (d > A.eps_idw ? d : A.eps_idw)) * pinv : 0.0f;
+                    }
+                }
+            }
+            wave_lds_sync();
+            // aggregation backward: d feat[idx_k][cc] += (w_k / sum w) dF[s][cc];
+            // lane l is feature l & 31 of samples 8 (l >> 5) .. +7
             {
                 const int cc = l & 31, half = l >> 5;
-                float df[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) df[i] = 0.0f;
-#pragma unroll 4
-                for (int i = 0; i < HP_HIDDEN; ++i) {
-                    const float w = sW1[i * HP_FEAT_DIM + cc];
-                    const float4 d0 = *reinterpret_cast<const float4 *>(&sh.H1T[i][8 * half]);
-                    const float4 d1 = *reinterpret_cast<const float4 *>(&sh.H1T[i][8 * half + 4]);
-                    df[0] = fma_rn(w, d0.x, df[0]);
-                    df[1] = fma_rn(w, d0.y, df[1]);
-                    df[2] = fma_rn(w, d0.z, df[2]);
-                    df[3] = fma_rn(w, d0.w, df[3]);
-                    df[4] = fma_rn(w, d1.x, df[4]);
-                    df[5] = fma_rn(w, d1.y, df[5]);
-                    df[6] = fma_rn(w, d1.z, df[6]);
-                    df[7] = fma_rn(w, d1.w, df[7]);
-                }
-                // dW1[i][cc] for i = 32 half .. +31: sum over the tile's samples
-                float fv[16];
-#pragma unroll
-                for (int s = 0; s < 16; ++s) fv[s] = sh.F[s][cc];
-#pragma unroll 4
-                for (int i = 32 * half; i < 32 * half + 32; ++i) {
-                    float gw = 0.0f;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const float4 d = *reinterpret_cast<const float4 *>(&sh.H1T[i][4 * k]);
-                        gw = fma_rn(d.x, fv[4 * k], gw);
-                        gw = fma_rn(d.y, fv[4 * k + 1], gw);
-                        gw = fma_rn(d.z, fv[4 * k + 2], gw);
-                        gw = fma_rn(d.w, fv[4 * k + 3], gw);
-                    }
-                    atomicAdd(&gpar[OFF_W1 + i * HP_FEAT_DIM + cc], gw);
-                }
-                // stage (index, normalised weight) of every neighbour of the tile
-                // in the layer-2 gradient area, now dead: [sample][K] each
-                int32_t *const s_idx = reinterpret_cast<int32_t *>(&sh.H2T[0][0]);
-                float *const s_w = &sh.H2T[0][0] + 16 * HP_MAX_K;
-                {
-                    const float pinv = sh.inv[r16];
-#pragma unroll
-                    for (int m = 0; m < PF; ++m) {
-                        const int k = q + 4 * m;
-                        if (k < A.K) {
-                            const float d = pf_d[m];
-                            s_idx[r16 * A.K + k] = pf_i[m];
-                            s_w[r16 * A.K + k] =
-                                pf_i[m] >= 0 ? (1.0f / (d > A.eps_idw ? d : A.eps_idw)) * pinv : 0.0f;
-                        }
-                    }
-                }
-                wave_lds_sync();
-                // aggregation backward: d feat[idx_k][cc] += (w_k / sum w) df
 #pragma unroll
                 for (int si = 0; si < 8; ++si) {
                     const int s = 8 * half + si;
                     if (s >= nt) break;
+                    const float df = sh.F[s][cc];
                     for (int k = 0; k < A.K; ++k) {
                         const int idx = s_idx[s * A.K + k];
                         if (idx < 0) break;
-                        atomicAdd(&A.grad_feat[(int64_t)idx * HP_FEAT_DIM + cc], s_w[s * A.K + k] * df[si]);
+                        atomicAdd(&A.grad_feat[(int64_t)idx * HP_FEAT_DIM + cc], s_w[s * A.K + k] * df);
                     }
                 }
             }
