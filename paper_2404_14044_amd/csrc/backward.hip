@@ -22,6 +22,7 @@
 #include <type_traits>
 
 #include "hp_backward.hpp"
+#include "hp_search.hpp"  // wave sorts
 
 namespace hp {
 
@@ -482,9 +483,72 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
                 }
             }
             wave_lds_sync();
-            // aggregation backward: d feat[idx_k][cc] += (w_k / sum w) dF[s][cc];
-            // lane l is feature l & 31 of samples 8 (l >> 5) .. +7
-            {
+            // aggregation backward: d feat[idx_k][cc] += (w_k / sum w) dF[s][cc].
+            // Consecutive samples share most neighbours, so with K <= 8 the
+            // tile's (neighbour, sample) pairs are sorted by neighbour and each
+            // distinct neighbour gets one atomic per channel (the atomics, not
+            // the arithmetic, bound this pass).
+            if (A.K <= 8) {
+                // key: neighbour index << 32 | s << 3 | k (~0: none); 128 pairs,
+                // elements l and 64 + l on lane l
+                uint64_t x0 = ~0ull, x1 = ~0ull;
+                {
+                    const int sa = l / A.K, ka = l - sa * A.K;
+                    const int sb = (l + WAVE) / A.K, kb = l + WAVE - sb * A.K;
+                    if (sa < nt) {
+                        const int idx = s_idx[sa * A.K + ka];
+                        if (idx >= 0) x0 = ((uint64_t)(uint32_t)idx << 32) | (uint32_t)(sa << 3 | ka);
+                    }
+                    if (sb < nt) {
+                        const int idx = s_idx[sb * A.K + kb];
+                        if (idx >= 0) x1 = ((uint64_t)(uint32_t)idx << 32) | (uint32_t)(sb << 3 | kb);
+                    }
+                }
+                // 128-key bitonic sort: ascending and descending halves, then
+                // the lane-wise half-cleaner and both halves sorted
+                x0 = wave_sort_fast(x0);
+                x1 = wave_sort_desc(x1);
+                {
+                    const uint64_t lo = umin64(x0, x1), hi = umax64(x0, x1);
+                    x0 = wave_merge_low_fast(lo, ~0ull);
+                    x1 = wave_merge_low_fast(hi, ~0ull);
+                }
+                // segment heads: the first pair of every distinct neighbour.
+                // Layer-2 area (1024 words): s_idx [0, 128), sorted keys
+                // [256, 512), s_w [512, 640), segment starts [640, 769)
+                static_assert(16 * HP_MAX_K >= 512 && HP_HIDDEN * 16 >= 769, "pair staging layout");
+                uint64_t *const srt = reinterpret_cast<uint64_t *>(&sh.H2T[0][0] + 256);
+                int32_t *const seg = reinterpret_cast<int32_t *>(&sh.H2T[0][0] + 640);
+                const uint32_t i0 = (uint32_t)(x0 >> 32), i1 = (uint32_t)(x1 >> 32);
+                const uint32_t p0 = (uint32_t)__shfl_up((int)i0, 1, WAVE);
+                const uint32_t p1 = l == 0 ? (uint32_t)readlane_i32((int)i0, WAVE - 1)
+                                           : (uint32_t)__shfl_up((int)i1, 1, WAVE);
+                const bool h0 = x0 != ~0ull && (l == 0 || p0 != i0);
+                const bool h1 = x1 != ~0ull && p1 != i1;
+                const uint64_t m0 = ballot(h0), m1 = ballot(h1);
+                const int nv = popc64(ballot(x0 != ~0ull)) + popc64(ballot(x1 != ~0ull));
+                const int u0 = popc64(m0), nu = u0 + popc64(m1);
+                srt[l] = x0;
+                srt[WAVE + l] = x1;
+                if (h0) seg[rank_below(m0)] = l;
+                if (h1) seg[u0 + rank_below(m1)] = WAVE + l;
+                if (l == 0) seg[nu] = nv;
+                wave_lds_sync();
+                // lane (cc, half): distinct neighbours half, half + 2, ...
+                const int cc = l & 31, half = l >> 5;
+                for (int j = half; j < nu; j += 2) {
+                    const int e0 = seg[j], e1 = seg[j + 1];
+                    float g = 0.0f;
+                    for (int e = e0; e < e1; ++e) {
+                        const uint32_t sk = (uint32_t)srt[e];
+                        const int ss = (int)(sk >> 3), kk = (int)(sk & 7u);
+                        g = fma_rn(s_w[ss * A.K + kk], sh.F[ss][cc], g);
+                    }
+                    const uint32_t idx = (uint32_t)(srt[e0] >> 32);
+                    atomicAdd(&A.grad_feat[(int64_t)idx * HP_FEAT_DIM + cc], g);
+                }
+            } else {
+                // lane l is feature l & 31 of samples 8 (l >> 5) .. +7
                 const int cc = l & 31, half = l >> 5;
 #pragma unroll
                 for (int si = 0; si < 8; ++si) {
