@@ -15,7 +15,7 @@
 //            gradient flows back through it on FP32 matrix cores (weights
 //            FP32) to the aggregated features, and through the aggregation
 //            to the point features with atomics.
-// Decoder-parameter gradients are accumulated per wave in a zeroed slice of
+// Decoder-parameter gradients are accumulated per workgroup in a zeroed slice of
 // the workspace with global atomics (L2 atomics on whole lines are much faster
 // here than LDS float atomics); a second kernel sums the slices in order into
 // the caller's gradient arrays.
@@ -34,6 +34,9 @@ constexpr int OFF_W2 = OFF_B1 + HP_HIDDEN;
 constexpr int OFF_B2 = OFF_W2 + HP_HIDDEN * HP_HIDDEN;
 constexpr int OFF_W3 = OFF_B2 + HP_HIDDEN;
 constexpr int OFF_B3 = OFF_W3 + 4 * HP_HIDDEN;
+// Floats between workgroup gradient slices: whole 128-byte lines, so that a
+// row's atomics never straddle a line (unaligned slices measured 1.3x slower).
+constexpr int SSTRIDE = (NPAR + 31) / 32 * 32;
 
 // One wave's LDS.
 struct BwdWave {
@@ -128,9 +131,10 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
     __shared__ float sW3[4 * HP_HIDDEN];
     const int wave = threadIdx.x >> 6;
     BwdWave &sh = waves[wave];
-    // this wave's decoder-parameter gradients: its own zeroed workspace slice,
-    // accumulated with global atomics (no other wave touches it)
-    float *const gpar = A.partial + ((int64_t)blockIdx.x * BWD_WAVES + wave) * NPAR;
+    // decoder-parameter gradients: the workgroup's zeroed workspace slice,
+    // accumulated with global atomics by its eight waves (one slice per
+    // workgroup is 0.84 MB per XCD, resident in its L2)
+    float *const gpar = A.partial + (int64_t)blockIdx.x * SSTRIDE;
     const int l = lane_id();
     const int r16 = l & 15, q = l >> 4;
 
@@ -580,7 +584,7 @@ __global__ void __launch_bounds__(256) k_zero_f32(float *p, int64_t n)
     if (i < n) p[i] = 0.0f;
 }
 
-// Sum the per-wave slices and add to the gradients, in a fixed order: each of
+// Sum the per-workgroup slices and add to the gradients, in a fixed order: each of
 // RED_G thread groups sums a contiguous range of slices in order, then the
 // group sums are added in group order.  (One thread per parameter walking
 // every slice would leave the chip idle: there are only 6,532 parameters.)
@@ -600,7 +604,7 @@ __global__ void __launch_bounds__(RED_P * RED_G) k_reduce_partials(const float *
     float s = 0.0f;
     if (i < NPAR) {
 #pragma unroll 8
-        for (int b = b0; b < b1; ++b) s += partial[(int64_t)b * NPAR + i];
+        for (int b = b0; b < b1; ++b) s += partial[(int64_t)b * SSTRIDE + i];
     }
     sh[grp][p] = s;
     __syncthreads();
@@ -619,7 +623,7 @@ __global__ void __launch_bounds__(RED_P * RED_G) k_reduce_partials(const float *
     dst[j] += t;
 }
 
-size_t backward_partial_bytes() { return (size_t)BWD_MAX_BLOCKS * BWD_WAVES * NPAR * sizeof(float); }
+size_t backward_partial_bytes() { return (size_t)BWD_MAX_BLOCKS * SSTRIDE * sizeof(float); }
 
 int backward_rays_per_wave(int S)
 {
@@ -639,8 +643,8 @@ hipError_t launch_backward(const BwdArgs &A, int precision, const MlpGrad &gm, h
     if (nblk > cus) nblk = cus;
     if (nblk > BWD_MAX_BLOCKS) nblk = BWD_MAX_BLOCKS;
     if (nblk < 1) nblk = 1;
-    const int64_t nslice = nblk * BWD_WAVES;
-    const int64_t nzero = nslice * NPAR;
+    const int64_t nslice = nblk;
+    const int64_t nzero = nslice * SSTRIDE;
     k_zero_f32<<<dim3((unsigned)((nzero + 255) / 256)), 256, 0, s>>>(A.partial, nzero);
     if (precision == HP_BF16)
         k_render_backward<HP_BF16><<<dim3((unsigned)nblk), dim3(WAVE * BWD_WAVES), 0, s>>>(A);

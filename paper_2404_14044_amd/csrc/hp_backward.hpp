@@ -8,7 +8,7 @@ namespace hp {
 
 constexpr int BWD_WAVES = 8;          // waves per workgroup (one workgroup per CU)
 constexpr int BWD_CHUNK = 256;        // samples one wave holds at once
-constexpr int BWD_MAX_BLOCKS = 256;   // bound on the persistent grid (8 gradient slices each)
+constexpr int BWD_MAX_BLOCKS = 256;   // bound on the persistent grid (one gradient slice each)
 
 struct MlpGrad {
     float *W1, *b1, *W2, *b2, *W3, *b3;
@@ -27,7 +27,7 @@ struct BwdArgs {
     float bg[3];
     const float *grad_rgb;
     float *grad_feat;
-    float *partial;  // per-wave decoder-gradient slices
+    float *partial;  // per-workgroup decoder-gradient slices
 };
 
 size_t backward_partial_bytes();
