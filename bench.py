@@ -50,7 +50,10 @@ def main():
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--layout", type=int, default=0)
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the batched-views and training-step legs")
+                    help="skip every extra leg (batched views, training step, ...)")
+    ap.add_argument("--legs", default="all",
+                    help="comma-separated extra legs to run (batched, train, radius, samplers, "
+                         "knp, fused, room, sweep) or 'all'")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -157,14 +160,22 @@ def main():
         torch.cuda.synchronize()
 
     if not args.no_extra:
-        result["batched_16"] = batched_leg(sc)
-        result["train_4x400"] = train_leg(sc)
-        result["radius_modes"] = radius_modes_leg(sc)
-        result["samplers"] = sampler_leg(sc)
-        result["knp"] = knp_leg(sc)
-        result["fused"] = fused_leg(sc)
-        result["room_5m"] = room_leg()
-        result["complexity_sweep"] = scaling_leg()
+        legs = [("batched", "batched_16", lambda: batched_leg(sc)),
+                ("train", "train_4x400", lambda: train_leg(sc)),
+                ("radius", "radius_modes", lambda: radius_modes_leg(sc)),
+                ("samplers", "samplers", lambda: sampler_leg(sc)),
+                ("knp", "knp", lambda: knp_leg(sc)),
+                ("fused", "fused", lambda: fused_leg(sc)),
+                ("room", "room_5m", room_leg),
+                ("sweep", "complexity_sweep", scaling_leg)]
+        wanted = set(l for l, _, _ in legs) if args.legs == "all" else set(args.legs.split(","))
+        unknown = wanted - set(l for l, _, _ in legs)
+        if unknown:
+            print(f"bench.py: unknown legs {sorted(unknown)}", file=sys.stderr)
+            sys.exit(2)
+        for name, key, fn in legs:
+            if name in wanted:
+                result[key] = fn()
 
     if args.cpu_seconds > 0:
         result.update(cpu_leg(sc, p, smp, outs, R, args.cpu_seconds))
