@@ -220,17 +220,6 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l)
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ float wave_min_f32(float v)
-{
-    v = __builtin_fminf(v, __uint_as_float(xor_lane_u32<1>(__float_as_uint(v))));
-    v = __builtin_fminf(v, __uint_as_float(xor_lane_u32<2>(__float_as_uint(v))));
-    v = __builtin_fminf(v, __uint_as_float(xor_lane_u32<4>(__float_as_uint(v))));
-    v = __builtin_fminf(v, __uint_as_float(xor_lane_u32<8>(__float_as_uint(v))));
-    v = __builtin_fminf(v, __uint_as_float(xor_lane_u32<16>(__float_as_uint(v))));
-    v = __builtin_fminf(v, __uint_as_float(xor_lane_u32<32>(__float_as_uint(v))));
-    return v;
-}
-
 // Inclusive prefix maximum across the wave (row shifts, then row broadcasts).
 __device__ __forceinline__ int wave_prefix_max_i32(int v)
 {
