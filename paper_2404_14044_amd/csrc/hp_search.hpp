@@ -1,6 +1,7 @@
 // Per-ray hashed-point search (Sec. 3.2) and adaptive primary-surface sampling
-// (Sec. 3.3, Eq. 4, Eq. 5), one wave per ray.  Shared by the forward kernel
-// and the backward kernel, which recomputes the samples instead of storing them.
+// (Sec. 3.3, Eq. 4, Eq. 5), one wave per ray.  Shared by the search + sampling
+// kernels (also run by the backward pass to recompute its samples), the K-NP
+// kernel and the fused search + render kernel.
 //
 // Search.  A neighbour of the ray is a point within rho(t) of it at its own
 // parameter t in [t_near, t_far].  Such a point projects at most
@@ -8,12 +9,13 @@
 // pixels from the ray's pixel centre (w: normalised image coordinate of the
 // ray, L^2 = 1 + |w|^2, f = max(fx, fy)), and delta does not grow with t.
 // Its depth z also bounds t from below, t >= (L z - |w| r) / (1 + |w| r
-// inv_tref).  So the wave
-//   1. reads the minimum depth of the 8x8-bucket cells around the pixel; if
+// inv_tref).  So
+//   1. the minimum depth of the 8x8-bucket cells around the pixel is read; if
 //      they are all empty the ray has no neighbour, else the smallest depth
 //      bounds t and thus the window radius delta(t) (two rounds, each over the
-//      cells of the previous radius);
-//   2. visits the buckets of that disc, and inside a bucket at distance D from
+//      cells of the previous radius; eight lanes per ray do this for up to
+//      eight rays at once, ray_setup);
+//   2. the wave visits the buckets of that disc, and inside a bucket at distance D from
 //      the pixel centre only needs points with t <= f r L^2 / D + r |w|, i.e.
 //      z <= (f r L^2 / D + 2 r |w|) / L (fixed-radius branch of rho); buckets
 //      are ordered by z, so a bucket whose first point is deeper is skipped.
@@ -22,8 +24,8 @@
 //
 // Lanes first sweep the window buckets (one bucket per lane), compact the
 // non-empty survivors into an LDS list, then sweep the points of the listed
-// buckets (one point per lane, located by binary search over the list's
-// prefix sums), apply the exact predicate and append the keys
+// buckets (one point per lane, its bucket found by a prefix maximum over the
+// bucket heads), apply the exact predicate and append the keys
 // (t bits << 32 | point index) of passing points to a pending buffer.  Every
 // 64 pending keys are sorted across the wave and merged into a running
 // ascending top-64, whose largest key then filters later appends.
