@@ -215,6 +215,23 @@ __device__ __forceinline__ uint64_t wave_merge_low_fast(uint64_t asc, uint64_t d
     return cx_merge<WAVE / 2>(umin64(asc, desc), lane_id());
 }
 
+// Lane p of each quad's value, on all four lanes (p a constant after unrolling).
+__device__ __forceinline__ uint32_t quad_bcast_u32(uint32_t v, int p)
+{
+    const int x = (int)v;
+    switch (p) {
+    case 0: return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x00, 0xF, 0xF, false);
+    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x55, 0xF, 0xF, false);
+    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0xAA, 0xF, 0xF, false);
+    default: return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0xFF, 0xF, 0xF, false);
+    }
+}
+
+__device__ __forceinline__ uint64_t quad_bcast_u64(uint64_t v, int p)
+{
+    return ((uint64_t)quad_bcast_u32((uint32_t)(v >> 32), p) << 32) | quad_bcast_u32((uint32_t)v, p);
+}
+
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l)
 {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
@@ -684,6 +701,70 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
     n_it = max(n_it, (int)xor_lane_u32<8>((uint32_t)n_it));
     n_it = max(n_it, (int)xor_lane_u32<16>((uint32_t)n_it));
     n_it = max(n_it, (int)xor_lane_u32<32>((uint32_t)n_it));
+    // (n_it is now the maximum over the lanes with this lane's q; the
+    // quad-gather path below reads the other lanes of the quad, so all lanes
+    // must take it together: its test uses the maximum over the whole wave)
+    if constexpr (KT >= 16) {
+        int n_all = max(n_it, (int)xor_lane_u32<1>((uint32_t)n_it));
+        n_all = max(n_all, (int)xor_lane_u32<2>((uint32_t)n_all));
+        if (n_all <= 4) {
+            // every lane holds at most four entries, so the quad's union fits
+            // sixteen: sort each lane's four, gather the quad's sixteen keys
+            // on every lane and merge the four sorted runs (no list merges)
+            uint64_t x[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = lo + q + 4 * e;
+                x[e] = ~0ull;
+                if (e < n_it && i < hi) {
+                    const float4 P = sh.nb_p[i];
+                    const float d2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, tq);
+                    if (d2 <= R2) x[e] = ((uint64_t)__float_as_uint(d2) << 32) | __float_as_uint(P.w);
+                }
+            }
+            cswap64(x[0], x[1]);
+            cswap64(x[2], x[3]);
+            cswap64(x[0], x[2]);
+            cswap64(x[1], x[3]);
+            cswap64(x[1], x[2]);
+            uint64_t v[16];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[4 * p + e] = quad_bcast_u64(x[e], p);
+            // runs of 4 -> 8 -> 16: the second run reversed makes a bitonic
+            // sequence, which half-cleaners sort
+#pragma unroll
+            for (int r0 = 0; r0 < 16; r0 += 8) {
+                uint64_t *w = v + r0;
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const uint64_t t = w[4 + k];
+                    w[4 + k] = w[7 - k];
+                    w[7 - k] = t;
+                }
+#pragma unroll
+                for (int j = 4; j > 0; j >>= 1)
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        if ((k & j) == 0) cswap64(w[k], w[k + j]);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint64_t t = v[8 + k];
+                v[8 + k] = v[15 - k];
+                v[15 - k] = t;
+            }
+#pragma unroll
+            for (int j = 8; j > 0; j >>= 1)
+#pragma unroll
+                for (int k = 0; k < 16; ++k)
+                    if ((k & j) == 0) cswap64(v[k], v[k + j]);
+#pragma unroll
+            for (int k = 0; k < KT; ++k) kd[k] = k < 16 ? v[k < 16 ? k : 0] : ~0ull;
+            return;
+        }
+    }
     // entries four at a time: sort the four keys (five compare-exchanges),
     // then merge them into the list as the upper half of a bitonic sequence
     for (int it = 0; it < n_it; it += 4) {
