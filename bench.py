@@ -152,6 +152,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "algorithmic_bytes": a_bytes},
     }
+    # achievable bandwidth on this machine: a plain 1 GiB device-to-device copy
+    copy_gbs = copy_bandwidth_gbs(dev)
+    result["roofline"]["copy_gbs"] = copy_gbs
+    result["roofline"]["frac_of_copy"] = achieved / copy_gbs
 
     if args.calibrate_copy:
         src = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
@@ -181,6 +185,26 @@ def main():
         result.update(cpu_leg(sc, p, smp, outs, R, args.cpu_seconds))
 
     print(json.dumps(result), flush=True)
+
+
+def copy_bandwidth_gbs(dev, nbytes=1 << 30, reps=5):
+    """Read + write bytes per second of a device-to-device copy (the box's
+    achievable HBM bandwidth), best of `reps`."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
 
 
 def _time_ms(fn, reps):
