@@ -38,15 +38,15 @@ __device__ __forceinline__ void fused_body(const SearchCtx &c, const FusedArgs &
         search_neighbours(c, g, sh.s, top, count);
         const int m = count < c.M ? count : c.M;
         int prim;
-        auto emit = [&](int s, int qq, float tj, const uint64_t(&kd)[KT], int kc) {
+        auto emit = [&](int s, int qq, float tj, const uint64_t(&kd)[KT], const float(&dq)[KT / 4],
+                        int kc) {
             if (qq == 0) sh.t[s] = tj;
 #pragma unroll
-            for (int k = 0; k < KT; ++k) {
-                if ((k & 3) == qq) {
-                    const bool v = k < kc && k < c.K;
-                    sh.idx[s][k] = v ? (int32_t)(uint32_t)kd[k] : -1;
-                    sh.dist[s][k] = v ? __builtin_sqrtf(__uint_as_float((uint32_t)(kd[k] >> 32))) : 0.0f;
-                }
+            for (int e = 0; e < KT / 4; ++e) {
+                const int k = 4 * e + qq;
+                const bool v = k < kc && k < c.K;
+                sh.idx[s][k] = v ? (int32_t)(uint32_t)quad_entry<KT>(kd, e) : -1;
+                sh.dist[s][k] = v ? dq[e] : 0.0f;
             }
         };
         int n;

@@ -842,12 +842,36 @@ __device__ __forceinline__ void knn_quad(const SearchCtx &c, const RayGeom &g, c
     knn_window<KT>(g, sh, tj, R2, lo, hi, kd);
 }
 
+// Distances of a quad's list entries split over its lanes: lane q takes the
+// correctly rounded square roots of entries k = q, q + 4, ... (dq[e] for
+// k = 4 e + q), so no lane computes more than KT / 4 of them.  Lane-local
+// (every lane of a quad holds the same list).
+template <int KT>
+__device__ __forceinline__ uint64_t quad_entry(const uint64_t (&kd)[KT], int e)
+{
+    const int q = lane_id() & 3;
+    uint64_t k0 = kd[4 * e], k1 = kd[4 * e + 1], k2 = kd[4 * e + 2], k3 = kd[4 * e + 3];
+    // (an empty asm hides where the values came from: a select between
+    // list elements would otherwise become a variable index into the list,
+    // which then lives in scratch memory instead of registers)
+    asm("" : "+v"(k0), "+v"(k1), "+v"(k2), "+v"(k3));
+    return (q & 2) ? ((q & 1) ? k3 : k2) : ((q & 1) ? k1 : k0);
+}
+
+template <int KT>
+__device__ __forceinline__ void quad_list_sqrt(const uint64_t (&kd)[KT], float (&dq)[KT / 4])
+{
+#pragma unroll
+    for (int e = 0; e < KT / 4; ++e)
+        dq[e] = __builtin_sqrtf(__uint_as_float((uint32_t)(quad_entry<KT>(kd, e) >> 32)));
+}
+
 // Candidate walk.  Candidates (the neighbours in (t, index) order) are
 // processed 16 at a time, candidate c0 + g on lanes 4 g .. 4 g + 3.  After a
 // chunk's transmittance walk, emit(s, q, tj, kd, kc) is called on the four
 // lanes (q = 0..3) of every candidate that became sample s, with its K nearest
-// neighbours kd (ascending (dist^2 bits, index), ~0 = none) and their number
-// kc.  Returns the sample count and sets first_idx to the primary point.
+// neighbours kd (ascending (dist^2 bits, index), ~0 = none), their number kc
+// and the lane's share dq of their distances (quad_list_sqrt).  Returns the sample count and sets first_idx to the primary point.
 template <int KT, typename Emit>
 __device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom &g, SearchLds &sh,
                                                uint64_t top, int m, int &first_idx, Emit emit)
@@ -869,6 +893,13 @@ __device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom
         const int j = c0 + (l >> 2);
         uint64_t kd[KT];
         knn_quad<KT>(c, g, sh, j, m, kd);
+        // each lane takes a quarter of the square roots; the quad then shares
+        // them so that every lane sums all of them in list order
+        float dq[KT / 4], dist[KT];
+        quad_list_sqrt<KT>(kd, dq);
+#pragma unroll
+        for (int k = 0; k < KT; ++k)
+            dist[k] = __uint_as_float(quad_bcast_u32(__float_as_uint(dq[k >> 2]), k & 3));
         float alpha = 0.0f, tj = 0.0f;
         int kc = 0;
         if (j < m) {
@@ -878,7 +909,7 @@ __device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom
 #pragma unroll
             for (int k = 0; k < KT; ++k) {
                 if (k < c.K && kd[k] != ~0ull) {
-                    sum = sum + __builtin_sqrtf(__uint_as_float((uint32_t)(kd[k] >> 32)));
+                    sum = sum + dist[k];
                     ++kc;
                 }
             }
@@ -910,7 +941,7 @@ __device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom
             }
             const int gl = l >> 2;
             if ((smask >> gl) & 1ull)
-                emit(sel0 + popc64(smask & ((1ull << gl) - 1ull)), l & 3, tj, kd, kc);
+                emit(sel0 + popc64(smask & ((1ull << gl) - 1ull)), l & 3, tj, kd, dq, kc);
         }
     }
     return sel;
@@ -1016,7 +1047,9 @@ __device__ __forceinline__ int uniform_samples(const SearchCtx &c, const RayGeom
                 int kc = 0;
 #pragma unroll
                 for (int q = 0; q < KT; ++q) kc += (q < c.K && kd[q] != ~0ull) ? 1 : 0;
-                emit(sel + rank, l & 3, tk, kd, kc);
+                float dq[KT / 4];
+                quad_list_sqrt<KT>(kd, dq);
+                emit(sel + rank, l & 3, tk, kd, dq, kc);
             }
             const int nkept = popc64(km);
             sel += nkept < room ? nkept : room;

@@ -17,17 +17,18 @@ __device__ __forceinline__ void search_sample_body(const SearchCtx &c, const Sam
         const int m = count < c.M ? count : c.M;
         const int64_t rbase = ray * c.S;
         int prim;
-        auto emit = [&](int s, int q, float tj, const uint64_t(&kd)[KT], int kc) {
+        auto emit = [&](int s, int q, float tj, const uint64_t(&kd)[KT], const float(&dq)[KT / 4],
+                        int kc) {
             // the candidate's four lanes share the row: lane q writes k = q, q + 4, ...
             const int64_t row = rbase + s;
             if (q == 0) o.t[row] = tj;
 #pragma unroll
-            for (int k = 0; k < KT; ++k) {
-                if ((k & 3) == q && k < c.K) {
+            for (int e = 0; e < KT / 4; ++e) {
+                const int k = 4 * e + q;
+                if (k < c.K) {
                     const bool v = k < kc;
-                    o.knn_idx[row * c.K + k] = v ? (int32_t)(uint32_t)kd[k] : -1;
-                    o.knn_dist[row * c.K + k] =
-                        v ? __builtin_sqrtf(__uint_as_float((uint32_t)(kd[k] >> 32))) : 0.0f;
+                    o.knn_idx[row * c.K + k] = v ? (int32_t)(uint32_t)quad_entry<KT>(kd, e) : -1;
+                    o.knn_dist[row * c.K + k] = v ? dq[e] : 0.0f;
                 }
             }
         };
