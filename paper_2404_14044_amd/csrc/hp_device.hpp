@@ -147,10 +147,12 @@ __device__ __forceinline__ void wave_lds_sync()
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a < b ? b : a; }
 
-// (a, b) <- (min, max) of the pair, on one compare
+// (a, b) <- (min, max) of the pair, on one compare: the empty asm keeps the
+// compiler from seeing a minimum and a maximum, each with its own compare
 __device__ __forceinline__ void cswap64(uint64_t &a, uint64_t &b)
 {
     const bool s = b < a;
+    asm("" : "+v"(a), "+v"(b));
     const uint64_t lo = s ? b : a;
     b = s ? a : b;
     a = lo;
