@@ -240,15 +240,18 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l)
 }
 
 // Inclusive prefix maximum across the wave (row shifts, then row broadcasts).
+// Lanes without a source read INT_MIN, the identity of max, which lets the
+// compiler fold each shift into its max instruction.
 __device__ __forceinline__ int wave_prefix_max_i32(int v)
 {
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xF, 0xF, false));  // row_shr:1
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xF, 0xF, false));  // row_shr:2
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x113, 0xF, 0xF, false));  // row_shr:3
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xF, 0xE, false));  // row_shr:4
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xF, 0xC, false));  // row_shr:8
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
-    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    constexpr int I = (int)0x80000000;
+    v = max(v, __builtin_amdgcn_update_dpp(I, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(I, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(I, v, 0x113, 0xF, 0xF, false));  // row_shr:3
+    v = max(v, __builtin_amdgcn_update_dpp(I, v, 0x114, 0xF, 0xE, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(I, v, 0x118, 0xF, 0xC, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(I, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(I, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
     return v;
 }
 
@@ -900,19 +903,18 @@ __device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom
 #pragma unroll
         for (int k = 0; k < KT; ++k)
             dist[k] = __uint_as_float(quad_bcast_u32(__float_as_uint(dq[k >> 2]), k & 3));
-        float alpha = 0.0f, tj = 0.0f;
+        // the list's valid entries (key != ~0) form a prefix; the first K count
         int kc = 0;
+#pragma unroll
+        for (int k = 0; k < KT; ++k) kc += kd[k] != ~0ull ? 1 : 0;
+        kc = min(kc, c.K);
+        float alpha = 0.0f, tj = 0.0f;
         if (j < m) {
             tj = sh.nb_t[j];
             const float Rj = rho_at(c, g, tj);
-            float sum = 0.0f;
+            float sum = 0.0f;  // (adding +0 past the prefix leaves it unchanged)
 #pragma unroll
-            for (int k = 0; k < KT; ++k) {
-                if (k < c.K && kd[k] != ~0ull) {
-                    sum = sum + dist[k];
-                    ++kc;
-                }
-            }
+            for (int k = 0; k < KT; ++k) sum = sum + (k < kc ? dist[k] : 0.0f);
             const float dj = (sum + (float)(c.K - kc) * Rj) / (float)c.K;
             const float uj = (dj * dj) * c.inv_beta2;
             alpha = c.gamma * exp_neg(-uj);
