@@ -687,6 +687,17 @@ __device__ __forceinline__ void merge_low(uint64_t (&a)[KT], const uint64_t (&b)
     }
 }
 
+// Ascending sort of eight keys on the 19-comparator network for n = 8.
+__device__ __forceinline__ void sort8(uint64_t (&x)[8])
+{
+    cswap64(x[0], x[2]); cswap64(x[1], x[3]); cswap64(x[4], x[6]); cswap64(x[5], x[7]);
+    cswap64(x[0], x[4]); cswap64(x[1], x[5]); cswap64(x[2], x[6]); cswap64(x[3], x[7]);
+    cswap64(x[0], x[1]); cswap64(x[2], x[3]); cswap64(x[4], x[5]); cswap64(x[6], x[7]);
+    cswap64(x[2], x[4]); cswap64(x[3], x[5]);
+    cswap64(x[1], x[4]); cswap64(x[3], x[6]);
+    cswap64(x[1], x[2]); cswap64(x[3], x[4]); cswap64(x[5], x[6]);
+}
+
 // Quad-split nearest neighbours of the ray point at tq among the sorted-list
 // entries [lo, hi) within R2: lane q of each quad takes entries lo + q,
 // lo + q + 4, ... into an ascending register list of (dist^2 bits << 32 |
@@ -707,9 +718,9 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
     // (n_it is now the maximum over the lanes with this lane's q; the
     // quad-gather path below reads the other lanes of the quad, so all lanes
     // must take it together: its test uses the maximum over the whole wave)
+    int n_all = max(n_it, (int)xor_lane_u32<1>((uint32_t)n_it));
+    n_all = max(n_all, (int)xor_lane_u32<2>((uint32_t)n_all));
     if constexpr (KT >= 16) {
-        int n_all = max(n_it, (int)xor_lane_u32<1>((uint32_t)n_it));
-        n_all = max(n_all, (int)xor_lane_u32<2>((uint32_t)n_all));
         if (n_all <= 4) {
             // every lane holds at most four entries, so the quad's union fits
             // sixteen: sort each lane's four, gather the quad's sixteen keys
@@ -768,9 +779,31 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
             return;
         }
     }
-    // entries four at a time: sort the four keys (five compare-exchanges),
-    // then merge them into the list as the upper half of a bitonic sequence
-    for (int it = 0; it < n_it; it += 4) {
+    // longer windows: the first eight entries are sorted outright (19
+    // compare-exchanges) and their smallest KT are the list (the test is
+    // wave-uniform: n_all is the maximum over the wave)
+    int it0 = 0;
+    if (n_all > 4) {
+        it0 = 8;
+        uint64_t x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int i = lo + q + 4 * e;
+            x[e] = ~0ull;
+            if (e < n_it && i < hi) {
+                const float4 P = sh.nb_p[i];
+                const float d2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, tq);
+                if (d2 <= R2) x[e] = ((uint64_t)__float_as_uint(d2) << 32) | __float_as_uint(P.w);
+            }
+        }
+        sort8(x);
+#pragma unroll
+        for (int k = 0; k < KT && k < 8; ++k) kd[k] = x[k];
+    }
+    // later entries four at a time: sort the four keys (five
+    // compare-exchanges), then merge them into the list as the upper half of
+    // a bitonic sequence
+    for (int it = it0; it < n_it; it += 4) {
         uint64_t x[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
