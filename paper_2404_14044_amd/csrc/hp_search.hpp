@@ -469,6 +469,7 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
     const int Wg = Vg.Wg, Hg = Vg.Hg, cell_base = V.cell_base, ncx = V.ncx;
 
     uint64_t tau = ~0ull;
+    bool have_top = false;
     int npend = 0;
     int nbl = 0;
 
@@ -481,8 +482,13 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
         lds_sync();
         if (l < rem) sh.pend[l] = y;
         npend = rem;
-        x = wave_sort_desc(x);
-        top = wave_merge_low_fast(top, x);
+        // the first flush sorts straight into the (empty) top list; later ones
+        // sort descending (ascending on inverted keys) and merge
+        const uint64_t inv = have_top ? ~0ull : 0ull;
+        x = wave_sort_fast(x ^ inv) ^ inv;
+        if (have_top) top = wave_merge_low_fast(top, x);
+        else top = x;
+        have_top = true;
         tau = readlane_u64(top, WAVE - 1);
         lds_sync();
     };
