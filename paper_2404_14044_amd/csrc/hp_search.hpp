@@ -365,14 +365,21 @@ __device__ __forceinline__ float uniform_f32(float v)
 
 __device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// A ray's set-up as the whole wave reads it back from the LDS.
+// A ray's set-up as the whole wave reads it back from the LDS.  A ray with
+// nothing near it (h < 0) needs no more than h.
 __device__ __forceinline__ RayGeom load_ray(const RayGeom &src)
 {
     RayGeom g;
+    g.h = uniform_i32(src.h);
+    if (g.h < 0) {
+        g.vi = g.gx = g.gy = 0;
+        g.dx = g.dy = g.dz = g.wn = g.kappa = g.inv_L = 0.0f;
+        g.z_lo = g.z_hi = g.dinf = g.frL2 = g.two_rw = g.Dmax = 0.0f;
+        return g;
+    }
     g.vi = uniform_i32(src.vi);
     g.gx = uniform_i32(src.gx);
     g.gy = uniform_i32(src.gy);
-    g.h = uniform_i32(src.h);
     g.dx = uniform_f32(src.dx);
     g.dy = uniform_f32(src.dy);
     g.dz = uniform_f32(src.dz);
