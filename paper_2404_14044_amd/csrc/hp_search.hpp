@@ -274,6 +274,10 @@ __device__ __forceinline__ float group_cells_zmin(const SearchCtx &c, const View
     return z;
 }
 
+// Reciprocal for the search bounds only (within a few ulp: every bound
+// carries a relative margin of at least 1e-4; the exact predicate decides).
+__device__ __forceinline__ float bound_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Window radius (pixels) for neighbours whose depth is at least zmin.
 __device__ __forceinline__ float radius_for_depth(const SearchCtx &c, float kappa, float L, float wn,
                                                   float f, float L2, float zmin, float dcap,
@@ -282,13 +286,13 @@ __device__ __forceinline__ float radius_for_depth(const SearchCtx &c, float kapp
     // a pure cone projects to a disc whose radius does not depend on depth
     if (c.rmode != HP_RADIUS_LINEAR) return dinf < dcap ? dinf : dcap;
     const float k = c.radius * c.inv_tref;
-    float t = (L * zmin - wn * c.radius) / (1.0f + wn * k);
+    float t = (L * zmin - wn * c.radius) * bound_rcp(1.0f + wn * k);
     t = t * 0.9999f - 1e-6f;
     if (!(t > c.t_near)) t = c.t_near;
     const float rho = search_radius(c.radius, c.inv_tref, t);
     const float den = t - rho * wn;
     if (!(den > 0.0f)) return dcap;
-    const float d = (f * rho * L2 / den) * 1.0001f + 0.01f;
+    const float d = (f * rho * L2 * bound_rcp(den)) * 1.0001f + 0.01f;
     return d < dcap ? d : dcap;
 }
 
@@ -328,18 +332,18 @@ __device__ __forceinline__ RayGeom ray_setup(const SearchCtx &c, int64_t ray, in
     const float f = V.fx > V.fy ? V.fx : V.fy;
     const float rho_n = rho_at(c, g, c.t_near);
     const float rho_f = rho_at(c, g, c.t_far);
-    g.z_lo = ((c.t_near - g.wn * rho_n) / L) * 0.999f - 1e-6f;
-    g.z_hi = ((c.t_far + g.wn * rho_f) / L) * 1.001f + 1e-6f;
+    g.inv_L = bound_rcp(L);
+    g.z_lo = ((c.t_near - g.wn * rho_n) * g.inv_L) * 0.999f - 1e-6f;
+    g.z_hi = ((c.t_far + g.wn * rho_f) * g.inv_L) * 1.001f + 1e-6f;
     // pixel offset bound once rho has reached its linear branch
     g.dinf = 0.0f;
     const float klin = c.rmode == HP_RADIUS_LINEAR ? c.radius * c.inv_tref : g.kappa;
     if (klin > 0.0f) {
         const float den = 1.0f - klin * g.wn;
-        g.dinf = den > 0.0f ? (f * klin * L2 / den) * 1.001f + 0.01f : __builtin_inff();
+        g.dinf = den > 0.0f ? (f * klin * L2 * bound_rcp(den)) * 1.001f + 0.01f : __builtin_inff();
     }
     g.frL2 = f * c.radius * L2;
     g.two_rw = 2.0f * c.radius * g.wn;
-    g.inv_L = 1.0f / L;
     g.gx = u + V.g;
     g.gy = v + V.g;
     float Dmax = V.dmax;
