@@ -99,6 +99,43 @@ def test_sphere_plane_multi_surface(sphere_plane):
     assert (ex["n_sel"] > 4).sum() > 300
 
 
+@pytest.mark.parametrize("K", [1, 3, 5, 12, 24, 32])
+def test_sphere_plane_list_lengths(sphere_plane, K):
+    """K away from the register-list lengths 4 / 8 / 16 / 32: only the first K
+    entries of a candidate's list are counted, summed (Eq. 4's mean distance)
+    and written."""
+    sc = sphere_plane
+    from paper_2404_14044_amd import hashpoint as hp
+    p = sc.params.replace(K=K)
+    out = gpu_forward(sc, params=p, precision=hp.HP_FP32)
+    pix = _all_pix(sc.cams[0])
+    ex = compare_exact(sc, out["samples"], pix, params=p)
+    err = render_error(sc, out["render"], ex, pix, params=p)
+    assert err["rgb"] <= FP32_TOL
+
+
+@pytest.mark.parametrize("K", [3, 24])
+def test_objects_list_lengths_sampled_rays(objects, K):
+    """Dense surfaces give t-windows of 20-40 list entries, so each lane of a
+    candidate's quad sorts a first batch of eight and then merges batches of
+    four; K = 3 keeps the low four of that batch, K = 24 fills 32-entry lists."""
+    sc = objects
+    p = sc.params.replace(K=K)
+    out = gpu_forward(sc, params=p)
+    pix = sample_pixels(sc.cams[0], 1024, seed=41 + K)
+    ex = compare_exact(sc, out["samples"], pix, params=p)
+    assert (ex["n_sel"] > 0).sum() > 100
+
+
+@pytest.mark.parametrize("K", [5, 24])
+def test_sphere_plane_multi_surface_list_lengths(sphere_plane, K):
+    sc = sphere_plane
+    p = sc.params.replace(sampler=1, ms_steps=600, n_samples=32, K=K)
+    out = gpu_forward(sc, params=p)
+    ex = compare_exact(sc, out["samples"], _all_pix(sc.cams[0]), params=p)
+    assert (ex["n_sel"] > 4).sum() > 300
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_objects_multi_surface_sampled_rays(objects, mode):
     sc = objects
