@@ -13,8 +13,8 @@
 //   1. the minimum depth of the 8x8-bucket cells around the pixel is read; if
 //      they are all empty the ray has no neighbour, else the smallest depth
 //      bounds t and thus the window radius delta(t) (two rounds, each over the
-//      cells of the previous radius; eight lanes per ray do this for up to
-//      eight rays at once, ray_setup);
+//      cells of the previous radius; four lanes per ray do this for up to
+//      sixteen rays at once, ray_setup);
 //   2. the wave visits the buckets of that disc, and inside a bucket at distance D from
 //      the pixel centre only needs points with t <= f r L^2 / D + r |w|, i.e.
 //      z <= (f r L^2 / D + 2 r |w|) / L (fixed-radius branch of rho); buckets
@@ -82,14 +82,14 @@ struct RayGeom {
 };
 
 constexpr int BL_CAP = 128;
-constexpr int RS_CAP = 8;               // rays whose set-up one pass computes
+constexpr int RS_CAP = 16;              // rays whose set-up one pass computes
 constexpr int RS_LANES = WAVE / RS_CAP;  // lanes per ray in that pass
 
 struct SearchLds {
     RayGeom rs[RS_CAP];
     int32_t bl_start[BL_CAP];
     int32_t bl_cnt[BL_CAP];
-    int32_t bl_pre[BL_CAP];
+    int32_t bl_pre[WAVE];  // (indexed by flat point offset within a sweep step)
     float bl_zmax[BL_CAP];
     uint64_t pend[2 * WAVE];
     float4 nb_p[WAVE];
@@ -267,10 +267,11 @@ __device__ __forceinline__ float group_cells_zmin(const SearchCtx &c, const View
     for (int cy = cy0; cy <= cy1; ++cy)
         for (int cx = cx0 + sub; cx <= cx1; cx += RS_LANES)
             z = __builtin_fminf(z, __uint_as_float(c.cell_zmin[V.cell_base + cy * V.ncx + cx]));
-    static_assert(RS_LANES == 8, "groups of eight lanes");
+    static_assert(RS_LANES == 4 || RS_LANES == 8, "groups of four or eight lanes");
     z = __builtin_fminf(z, __uint_as_float(xor_lane_u32<1>(__float_as_uint(z))));
     z = __builtin_fminf(z, __uint_as_float(xor_lane_u32<2>(__float_as_uint(z))));
-    z = __builtin_fminf(z, __uint_as_float(xor_lane_u32<4>(__float_as_uint(z))));
+    if constexpr (RS_LANES == 8)
+        z = __builtin_fminf(z, __uint_as_float(xor_lane_u32<4>(__float_as_uint(z))));
     return z;
 }
 
@@ -431,18 +432,22 @@ __device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, RayGeom 
         r0 = ch * c.chunk;
         n = (int)min((int64_t)c.chunk, c.n_rays - r0);
     };
-    // two chunks per set-up pass (the chunks themselves stay small, for balance)
-    for (int64_t li = slot; li < my_chunks; li += 2 * n_slots) {
-        int64_t ra, rb;
-        int na, nb;
+    // four chunks per set-up pass (the chunks themselves stay small, for balance)
+    for (int64_t li = slot; li < my_chunks; li += 4 * n_slots) {
+        int64_t ra, rb, rc, rd;
+        int na, nb, nc, nd;
         chunk_rays(li, ra, na);
         chunk_rays(li + n_slots, rb, nb);
-        const int ntot = na + nb;
-        auto ray_at = [&](int i) -> int64_t { return i < na ? ra + i : rb + (i - na); };
+        chunk_rays(li + 2 * n_slots, rc, nc);
+        chunk_rays(li + 3 * n_slots, rd, nd);
+        const int nab = na + nb, nabc = nab + nc, ntot = nabc + nd;
+        auto ray_at = [&](int i) -> int64_t {
+            return i < na ? ra + i : i < nab ? rb + (i - na) : i < nabc ? rc + (i - nab) : rd + (i - nabc);
+        };
         for (int s0 = 0; s0 < ntot; s0 += RS_CAP) {
             const int n = min(RS_CAP, ntot - s0);
             lds_sync();
-            // lanes 8 k .. 8 k + 7 set up ray s0 + k (lanes past the batch
+            // lanes 4 k .. 4 k + 3 set up ray s0 + k (lanes past the batch
             // repeat its last ray)
             const int k = l / RS_LANES;
             const RayGeom gk = ray_setup(c, ray_at(s0 + (k < n ? k : n - 1)), l % RS_LANES);
