@@ -95,6 +95,8 @@ struct SearchLds {
     float4 nb_p[WAVE];
     float nb_t[WAVE];
 };
+// 32 one-wave workgroups (8 waves per SIMD) share a CU's 160 KB of LDS
+static_assert(sizeof(SearchLds) <= 5120, "search LDS above 5120 B halves occupancy");
 
 // Rays per XCD band: about 16 image rows of an 800-pixel-wide view.
 constexpr int64_t BAND_RAYS = 12800;
