@@ -744,6 +744,58 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
     // must take it together: its test uses the maximum over the whole wave)
     int n_all = max(n_it, (int)xor_lane_u32<1>((uint32_t)n_it));
     n_all = max(n_all, (int)xor_lane_u32<2>((uint32_t)n_all));
+    if constexpr (KT >= 8) {
+        if (n_all <= 2) {
+            // at most two entries per lane: the quad's union fits eight; sort
+            // each lane's pair, gather the quad's four pairs on every lane and
+            // merge the sorted runs 2 -> 4 -> 8
+            uint64_t x[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int i = lo + q + 4 * e;
+                x[e] = ~0ull;
+                if (e < n_it && i < hi) {
+                    const float4 P = sh.nb_p[i];
+                    const float d2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, tq);
+                    if (d2 <= R2) x[e] = ((uint64_t)__float_as_uint(d2) << 32) | __float_as_uint(P.w);
+                }
+            }
+            cswap64(x[0], x[1]);
+            uint64_t v[8];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                v[2 * p] = quad_bcast_u64(x[0], p);
+                v[2 * p + 1] = quad_bcast_u64(x[1], p);
+            }
+            // (each merge reverses its second run, making the pair of runs
+            // bitonic, then half-cleaners sort it)
+#pragma unroll
+            for (int r0 = 0; r0 < 8; r0 += 4) {
+                uint64_t *w = v + r0;
+                const uint64_t t = w[2];
+                w[2] = w[3];
+                w[3] = t;
+                cswap64(w[0], w[2]);
+                cswap64(w[1], w[3]);
+                cswap64(w[0], w[1]);
+                cswap64(w[2], w[3]);
+            }
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const uint64_t t = v[4 + k];
+                v[4 + k] = v[7 - k];
+                v[7 - k] = t;
+            }
+#pragma unroll
+            for (int j = 4; j > 0; j >>= 1)
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if ((k & j) == 0) cswap64(v[k], v[k + j]);
+#pragma unroll
+            for (int k = 0; k < KT; ++k) kd[k] = k < 8 ? v[k < 8 ? k : 0] : ~0ull;
+            return;
+        }
+    }
     if constexpr (KT >= 16) {
         if (n_all <= 4) {
             // every lane holds at most four entries, so the quad's union fits
