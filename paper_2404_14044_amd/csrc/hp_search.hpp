@@ -1028,31 +1028,46 @@ __device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom
             const float uj = (dj * dj) * c.inv_beta2;
             alpha = c.gamma * exp_neg(-uj);
         }
-        // transmittance walk over this chunk (Eq. 5)
-        const int c1 = min(c0 + 16, m);
+        // transmittance walk over this chunk (Eq. 5).  The transmittance in
+        // front of each candidate is the running product of (1 - alpha) in
+        // candidate order, one binary32 multiply after another as a sequential
+        // walk takes them (candidates past the list have alpha = 0, a factor
+        // of exactly 1); each quad keeps the value in front of its candidate.
+        const int gl = l >> 2;
+        const int ncand = min(c0 + 16, m) - c0;
         const int sel0 = sel;
-        uint64_t smask = 0;  // bit g: candidate c0 + g selected
-        for (int jj = c0; jj < c1; ++jj) {
-            const float aj = readlane_f32(alpha, 4 * (jj - c0));
-            const float wj = aj * T;
-            if (wj > c.eps_w && sel < c.S) {
-                smask |= 1ull << (jj - c0);
-                ++sel;
-            }
+        float Tb = T;
+#pragma unroll
+        for (int gg = 0; gg < 16; ++gg) {
+            const float aj = readlane_f32(alpha, 4 * gg);
+            Tb = gl == gg ? T : Tb;
             T = T * (1.0f - aj);
-            if (sel == c.S || c.gamma * T <= c.eps_w) {
-                done = true;
-                break;
-            }
         }
+        // the sequential walk's decisions, one candidate per quad leader:
+        // selected when its weight passes eps_w while fewer than S samples
+        // are taken; it stops after the S-th sample or once gamma T <= eps_w
+        const float wq = alpha * Tb;
+        const float Ta = Tb * (1.0f - alpha);
+        const bool lead = (l & 3) == 0 && gl < ncand;
+        const uint64_t pm = ballot(lead && wq > c.eps_w);         // bit 4 g
+        const uint64_t dm = ballot(lead && c.gamma * Ta <= c.eps_w);
+        int stop = dm ? __builtin_ctzll(dm) : WAVE;
+        const int room = c.S - sel0;
+        if (popc64(pm) >= room) {
+            uint64_t x = pm;
+            for (int k = 1; k < room; ++k) x &= x - 1ull;
+            stop = min(stop, __builtin_ctzll(x));
+        }
+        if (stop < WAVE) done = true;
+        const uint64_t smask = stop < WAVE ? pm & ((2ull << stop) - 1ull) : pm;
+        sel += popc64(smask);
         if (smask) {
             if (sel0 == 0) {
-                const int gsel = __builtin_ctzll(smask);
+                const int gsel = __builtin_ctzll(smask) >> 2;
                 first_idx = __float_as_int(sh.nb_p[c0 + gsel].w);
             }
-            const int gl = l >> 2;
-            if ((smask >> gl) & 1ull)
-                emit(sel0 + popc64(smask & ((1ull << gl) - 1ull)), l & 3, tj, kd, dq, kc);
+            if ((smask >> (4 * gl)) & 1ull)
+                emit(sel0 + popc64(smask & ((1ull << (4 * gl)) - 1ull)), l & 3, tj, kd, dq, kc);
         }
     }
     return sel;
