@@ -1032,17 +1032,20 @@ __device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom
         // front of each candidate is the running product of (1 - alpha) in
         // candidate order, one binary32 multiply after another as a sequential
         // walk takes them (candidates past the list have alpha = 0, a factor
-        // of exactly 1); each quad keeps the value in front of its candidate.
+        // of exactly 1); the value in front of each candidate reaches its quad
+        // through the LDS.
         const int gl = l >> 2;
         const int ncand = min(c0 + 16, m) - c0;
         const int sel0 = sel;
-        float Tb = T;
+        float *const tb = reinterpret_cast<float *>(sh.pend);  // (free during the walk)
 #pragma unroll
         for (int gg = 0; gg < 16; ++gg) {
             const float aj = readlane_f32(alpha, 4 * gg);
-            Tb = gl == gg ? T : Tb;
+            if (l == 0) tb[gg] = T;
             T = T * (1.0f - aj);
         }
+        lds_sync();
+        const float Tb = tb[gl];
         // the sequential walk's decisions, one candidate per quad leader:
         // selected when its weight passes eps_w while fewer than S samples
         // are taken; it stops after the S-th sample or once gamma T <= eps_w
