@@ -176,6 +176,9 @@ __device__ __forceinline__ uint64_t cx_merge(uint64_t x, int l)
 // bit a alone): bitwise NOT reverses the order of keys.
 __device__ __forceinline__ uint64_t flip_keys(uint64_t x, int l, int a, int b)
 {
+    // (recomputed at each use: kept from the start of the kernel, the six
+    // masks would hold registers the whole time)
+    asm volatile("" : "+v"(l));
     const int bits = (l >> a) ^ (b >= 0 ? (l >> b) : 0);
     const uint32_t m = (uint32_t)(-(bits & 1));
     return x ^ (((uint64_t)m << 32) | m);
