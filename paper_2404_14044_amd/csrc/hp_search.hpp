@@ -1072,8 +1072,10 @@ __device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom
                 const int gsel = __builtin_ctzll(smask) >> 2;
                 first_idx = __float_as_int(sh.nb_p[c0 + gsel].w);
             }
-            if ((smask >> (4 * gl)) & 1ull)
-                emit(sel0 + popc64(smask & ((1ull << (4 * gl)) - 1ull)), l & 3, tj, kd, dq, kc);
+            // (the rank from the lane's own position: a per-lane mask would be
+            // kept, and spilled, for the whole kernel)
+            if ((smask >> (l & ~3)) & 1ull)
+                emit(sel0 + rank_below(smask) - ((l & 3) ? 1 : 0), l & 3, tj, kd, dq, kc);
         }
     }
     return sel;
