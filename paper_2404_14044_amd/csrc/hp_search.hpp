@@ -40,10 +40,6 @@
 // stops once no later candidate can pass eps_w (alpha <= gamma, so
 // w_j <= gamma T), which usually happens within the first sixteen.
 #pragma once
-#ifndef HP_XOR4_SWIZZLE
-#define HP_XOR4_SWIZZLE 0
-#endif
-
 #include "hp_device.hpp"
 
 namespace hp {
@@ -133,13 +129,9 @@ __device__ __forceinline__ uint32_t xor_lane_u32(uint32_t v)
     if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);
     if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);
     if constexpr (J == 4) {
-#if HP_XOR4_SWIZZLE
-        return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x101F);
-#else
         const int down = __builtin_amdgcn_mov_dpp(x, 0x124, 0xF, 0xF, false);  // from l - 4
         const int up = __builtin_amdgcn_mov_dpp(x, 0x12C, 0xF, 0xF, false);    // from l + 4
         return (uint32_t)((lane_id() & 4) ? down : up);
-#endif
     }
     if constexpr (J == 8) return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false);
     if constexpr (J == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x401F);
