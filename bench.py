@@ -487,6 +487,29 @@ def train_leg(sc, reps=5):
             "backward_ms": t_step - t_fwd, "step_mrays_s": tab.n_rays / t_step / 1e3}
 
 
+def exact_outputs_match(smp, ex, pix, p):
+    """Every exact output of the GPU search + sampling on rays `pix` equals the
+    oracle's bit for bit: neighbour counts, overflow flags, sample counts,
+    primary surface, sample t, nearest-neighbour indices and distances."""
+    S, K = p.n_samples, p.K
+    h = {k: smp[k].cpu().numpy() for k in ("n_nbr", "flags", "n_sel", "primary", "t",
+                                            "knn_idx", "knn_dist")}
+    res = {"n_nbr": np.array_equal(h["n_nbr"][pix], ex["n_nbr"]),
+           "flags": np.array_equal(h["flags"][pix].astype(np.uint32), ex["flags"]),
+           "n_sel": np.array_equal(h["n_sel"][pix], ex["n_sel"]),
+           "primary": np.array_equal(h["primary"][pix], ex["primary"])}
+    ns = ex["n_sel"]
+    mask = np.arange(S)[None, :] < ns[:, None]
+    t = h["t"].reshape(-1, S)[pix]
+    ki = h["knn_idx"].reshape(-1, S, K)[pix]
+    kd = h["knn_dist"].reshape(-1, S, K)[pix]
+    res["t_bits"] = np.array_equal(t[mask].view(np.int32), ex["t"][mask].view(np.int32))
+    res["knn_idx"] = np.array_equal(ki[mask], ex["knn_idx"][mask])
+    res["knn_dist_bits"] = np.array_equal(kd[mask].view(np.int32), ex["knn_dist"][mask].view(np.int32))
+    res["all"] = all(bool(v) for v in res.values())
+    return {k: bool(v) for k, v in res.items()}
+
+
 def cpu_leg(sc, p, smp, outs, R, seconds):
     """Oracle (brute-force search, candidate walk, binary64 render) on a
     bounded random sample of the same rays; also the GPU RGB error there."""
@@ -509,8 +532,7 @@ def cpu_leg(sc, p, smp, outs, R, seconds):
     for prec, name in ((hp.HP_BF16, "bf16"), (hp.HP_FP32, "fp32")):
         rgb = outs[prec]["rgb"].cpu().numpy().reshape(-1, 3)[pix].astype(np.float64)
         errs[f"rgb_err_{name}"] = float(np.abs(rgb - ref["rgb"]).max())
-    ns = smp["n_sel"].cpu().numpy()[pix]
-    errs["oracle_sample_match"] = bool(np.array_equal(ns, ex["n_sel"]))
+    errs["oracle_exact_match"] = exact_outputs_match(smp, ex, pix, p)
     return {"cpu_baseline": {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(),
                              "kind": "oracle",
                              "sample": f"{n} random rays of the 800x800 view (brute-force search "

@@ -198,6 +198,21 @@ typedef struct hp_mlp {
     float *W1, *b1, *W2, *b2, *W3, *b3;
 } hp_mlp;
 
+/* Element counts of the arrays of an hp_samples for R rays with these
+ * parameters (host only, no GPU needed): n_rays for n_sel, primary, n_nbr and
+ * flags; sample_rows = R * n_samples for t; knn_entries = sample_rows * K for
+ * knn_idx and knn_dist; nbr_entries = R * m_cap for the optional nbr_idx and
+ * nbr_t.  Returns HP_E_INVALID for R < 0 or invalid parameters and
+ * HP_E_CAPACITY when a count would not fit in int64. */
+typedef struct hp_shape {
+    int64_t n_rays;
+    int64_t sample_rows;
+    int64_t knn_entries;
+    int64_t nbr_entries;
+} hp_shape;
+
+hp_status hp_samples_shape(int64_t R, const hp_params *p, hp_shape *out);
+
 /* Workspace bytes hp_build_table needs for n points and these views (host
  * only, no GPU needed).  Returns 0 and sets *status on invalid input. */
 size_t hp_table_workspace(int64_t n, const hp_camera *cams, int32_t n_views,
@@ -322,6 +337,19 @@ hp_status hp_render_backward_samples(const hp_samples *smp, int64_t R, const flo
                                      int32_t C, const hp_mlp *mlp, int32_t precision,
                                      const hp_params *p, const float *grad_rgb, float *grad_feat,
                                      hp_mlp *grad_mlp, void *ws, size_t ws_bytes, void *stream);
+
+/* Evaluates on the device, element by element, the binary32 exponential
+ * that decides the candidate confidences alpha = gamma exp(-d^2 / beta^2)
+ * (Sec. 3.3): y[i] = E(x[i]) for the n values of x (device, FP32), written to
+ * y (device, FP32, n entries, may not overlap x).  E is the fixed operation
+ * sequence the search kernels use: x = k ln2 + r by a Cody-Waite reduction
+ * with a 16-bit head of ln2 (k = rint(x / ln2), so that k times the head is
+ * exact), the degree-7 Taylor polynomial of exp(r) in Horner form with fused
+ * multiply-adds, then scaling by 2^k; it returns 0 for x < -86 and NaN and is
+ * meant for x <= 0.  For tests of bit-reproducibility against other
+ * implementations of that sequence.  Asynchronous on `stream`.
+ * Errors: HP_E_INVALID (n < 0, null pointer with n > 0). */
+hp_status hp_exp32_eval(const float *x, float *y, int64_t n, void *stream);
 
 /* Status text, and the last HIP error code seen by this thread. */
 const char *hp_status_str(hp_status s);

@@ -84,6 +84,12 @@ def lib():
         _lib.or_exact.argtypes = [P, i64, P, P, P, i64] + [P] * 14
         _lib.or_render64.argtypes = [P, P, i32] + [P] * 6 + [P, P, P, i64, P, P, P, P, P, P]
         _lib.or_grad64.argtypes = [P, P, i32] + [P] * 6 + [P, P, P, i64, P, P, P, P, P] + [P] * 6
+        _lib.or_render64q.argtypes = ([P, P, i32] + [P] * 6 + [P, P, P, i64, P, P, P, i32, P, P]
+                                      + [P, P, P])
+        _lib.or_grad64q.argtypes = ([P, P, i32] + [P] * 6 + [P, P, P, i64, P, P, P, i32, P, P]
+                                    + [P, P] + [P] * 6)
+        _lib.or_bf16.restype = ctypes.c_double
+        _lib.or_bf16.argtypes = [ctypes.c_double]
         _lib.or_num_threads.restype = i32
     return _lib
 
@@ -230,8 +236,44 @@ def _mlp_ptrs(mlp):
     return arrs, [_ptr(a) for a in arrs]
 
 
-def render64(pc, feat, mlp, cam, params, ex) -> Dict[str, np.ndarray]:
-    """Binary64 render of the exact stage's samples ``ex`` (from :func:`exact`)."""
+QUANT_NONE, QUANT_BF16, QUANT_FROZEN = 0, 1, 2
+N_ACT_OFF = 32 + 2 * 64  # per-sample operand offsets: aggregated feature, h1, h2
+
+
+class QuantOffsets:
+    """Rounding offsets bf16(x) - x of the decoder operands, recorded by a
+    QUANT_BF16 call and replayed (held fixed) by QUANT_FROZEN calls on the
+    same rays: the weights' offsets and, per sample row, those of the
+    aggregated feature and the two hidden activations."""
+
+    def __init__(self, n_rays: int, params, C: int = 32):
+        n_w = 64 * C + 64 * 64 + 4 * 64
+        self.w = np.zeros(n_w, np.float64)
+        self.act = np.zeros(max(n_rays * params.n_samples, 1) * (C + 128), np.float64)
+
+
+def bf16(x):
+    """Round binary64 values to bfloat16 (8 significant bits, ties to even)."""
+    f = lib().or_bf16
+    return np.vectorize(lambda v: f(float(v)), otypes=[np.float64])(np.asarray(x, np.float64))
+
+
+def _quant_args(quant, offsets):
+    if quant == QUANT_NONE:
+        return [0, None, None]
+    if offsets is None:
+        if quant == QUANT_FROZEN:
+            raise ValueError("QUANT_FROZEN replays recorded offsets: pass offsets")
+        return [int(quant), None, None]
+    return [int(quant), _ptr(offsets.w), _ptr(offsets.act)]
+
+
+def render64(pc, feat, mlp, cam, params, ex, quant: int = QUANT_NONE,
+             offsets: Optional[QuantOffsets] = None) -> Dict[str, np.ndarray]:
+    """Binary64 render of the exact stage's samples ``ex`` (from :func:`exact`).
+    quant: QUANT_NONE, QUANT_BF16 (decoder operands rounded to bfloat16;
+    records their offsets into ``offsets`` when given) or QUANT_FROZEN (the
+    recorded offsets held fixed)."""
     pc = np.ascontiguousarray(pc, np.float32)
     feat = np.ascontiguousarray(feat, np.float32)
     keep, mp = _mlp_ptrs(mlp)
@@ -243,14 +285,17 @@ def render64(pc, feat, mlp, cam, params, ex) -> Dict[str, np.ndarray]:
     n_sel = np.ascontiguousarray(ex["n_sel"], np.int32)
     t = np.ascontiguousarray(ex["t"], np.float32)
     ki = np.ascontiguousarray(ex["knn_idx"], np.int32)
-    lib().or_render64(_ptr(pc), _ptr(feat), feat.shape[1], *mp, ctypes.byref(c), ctypes.byref(p),
-                      _ptr(ex["pix"]), R, _ptr(n_sel), _ptr(t), _ptr(ki),
-                      _ptr(rgb), _ptr(depth), _ptr(acc))
+    lib().or_render64q(_ptr(pc), _ptr(feat), feat.shape[1], *mp, ctypes.byref(c), ctypes.byref(p),
+                       _ptr(ex["pix"]), R, _ptr(n_sel), _ptr(t), _ptr(ki),
+                       *_quant_args(quant, offsets), _ptr(rgb), _ptr(depth), _ptr(acc))
     return {"rgb": rgb, "depth": depth, "acc": acc}
 
 
-def grad64(pc, feat, mlp, cam, params, ex, grad_rgb) -> Dict[str, np.ndarray]:
-    """Binary64 gradient of sum(grad_rgb * rgb) w.r.t. features and MLP parameters."""
+def grad64(pc, feat, mlp, cam, params, ex, grad_rgb, quant: int = QUANT_NONE,
+           offsets: Optional[QuantOffsets] = None) -> Dict[str, np.ndarray]:
+    """Binary64 gradient of sum(grad_rgb * rgb) w.r.t. features and MLP
+    parameters; quant as for :func:`render64` (roundings count as fixed
+    offsets)."""
     pc = np.ascontiguousarray(pc, np.float32)
     feat = np.ascontiguousarray(feat, np.float32)
     keep, mp = _mlp_ptrs(mlp)
@@ -263,7 +308,8 @@ def grad64(pc, feat, mlp, cam, params, ex, grad_rgb) -> Dict[str, np.ndarray]:
     n_sel = np.ascontiguousarray(ex["n_sel"], np.int32)
     t = np.ascontiguousarray(ex["t"], np.float32)
     ki = np.ascontiguousarray(ex["knn_idx"], np.int32)
-    lib().or_grad64(_ptr(pc), _ptr(feat), feat.shape[1], *mp, ctypes.byref(c), ctypes.byref(p),
-                    _ptr(ex["pix"]), R, _ptr(n_sel), _ptr(t), _ptr(ki), _ptr(g), _ptr(out["feat"]),
-                    *[_ptr(out[k]) for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+    lib().or_grad64q(_ptr(pc), _ptr(feat), feat.shape[1], *mp, ctypes.byref(c), ctypes.byref(p),
+                     _ptr(ex["pix"]), R, _ptr(n_sel), _ptr(t), _ptr(ki),
+                     *_quant_args(quant, offsets), _ptr(g), _ptr(out["feat"]),
+                     *[_ptr(out[k]) for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
     return out

@@ -560,13 +560,94 @@ typedef struct {
 static double sigm(double x) { return x >= 0 ? 1.0 / (1.0 + exp(-x)) : exp(x) / (1.0 + exp(x)); }
 static double softplus(double x) { return (x > 0 ? x : 0.0) + log1p(exp(-fabs(x))); }
 
+/* ------------------------------------------------------------------------ */
+/* Decoder precision (reading R22 of the BF16 decoder).  quant = 0: every   */
+/* operand is used as it is.  quant = 1: the decoder's operands -- the      */
+/* aggregated feature, the two hidden activations and the three weight      */
+/* matrices -- are rounded to bfloat16 (8 significant bits, round to         */
+/* nearest, ties to even); biases, the products' sums, the activations     */
+/* themselves, aggregation and compositing are not.  quant = 2: the same    */
+/* function with each rounding replaced by its offset bf16(x) - x recorded  */
+/* by a quant = 1 call, held fixed: x -> x + offset.  At the recording      */
+/* point the two agree exactly; quant = 2 is smooth in every input (away    */
+/* from ReLU kinks), so its central differences check the analytic         */
+/* gradient below, which for quant = 1 and 2 treats every rounding as       */
+/* x -> x + (fixed offset), i.e. as the identity.                           */
+/* ------------------------------------------------------------------------ */
+#define ORC_ACT_OFF(C) ((C) + 2 * ORC_HID) /* offsets per sample: f, h1, h2 */
+
+double or_bf16(double x)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    const double ax = fabs(x);
+    if (ax < 0x1p-126) return nearbyint(x * 0x1p133) * 0x1p-133; /* subnormal spacing 2^-133 */
+    int e;
+    frexp(x, &e); /* |x| = m 2^e, m in [0.5, 1) */
+    return ldexp(nearbyint(ldexp(x, 8 - e)), e - 8);
+}
+
+typedef struct {
+    int32_t mode;         /* 0, 1 or 2 (above)                                 */
+    double *w_off;        /* [n_w1 + n_w2 + n_w3] weight offsets: written by   */
+                          /* mode 1 when not NULL, read by mode 2              */
+    double *act_off;      /* [rays * S * ORC_ACT_OFF(C)] per-sample offsets of */
+                          /* (f, h1, h2): the same                             */
+} orc_quant;
+
+/* Effective decoder weights: W + offset (mode 1: the offset that rounds W). */
+typedef struct {
+    double *W1, *W2, *W3;
+} orc_wq;
+
+static int wq_make(const orc_mlp *mlp, int C, const orc_quant *q, orc_wq *w)
+{
+    const int n1 = ORC_HID * C, n2 = ORC_HID * ORC_HID, n3 = ORC_OUT * ORC_HID;
+    w->W1 = (double *)malloc((size_t)(n1 + n2 + n3) * sizeof(double));
+    if (!w->W1) return 0;
+    w->W2 = w->W1 + n1;
+    w->W3 = w->W2 + n2;
+    const float *src[3] = {mlp->W1, mlp->W2, mlp->W3};
+    double *dst[3] = {w->W1, w->W2, w->W3};
+    const int cnt[3] = {n1, n2, n3};
+    int base = 0;
+    for (int m = 0; m < 3; ++m) {
+        for (int i = 0; i < cnt[m]; ++i) {
+            const double x = src[m][i];
+            double off = 0.0;
+            if (q && q->mode == 1) {
+                off = or_bf16(x) - x;
+                if (q->w_off) q->w_off[base + i] = off;
+            } else if (q && q->mode == 2) {
+                off = q->w_off[base + i];
+            }
+            dst[m][i] = x + off;
+        }
+        base += cnt[m];
+    }
+    return 1;
+}
+
+/* x -> its decoder operand under q (off: this value's offset slot). */
+static double operand(const orc_quant *q, double x, double *off)
+{
+    if (!q || q->mode == 0) return x;
+    if (q->mode == 1) {
+        const double o = or_bf16(x) - x;
+        if (off) *off = o;
+        return x + o;
+    }
+    return x + *off;
+}
+
 /* per-sample forward; keeps activations for the backward pass */
 typedef struct {
-    double f[64], h1[ORC_HID], h2[ORC_HID], o[ORC_OUT];
+    double f[64], fq[64];          /* aggregated feature, its decoder operand */
+    double z1[ORC_HID], h1q[ORC_HID], z2[ORC_HID], h2q[ORC_HID], o[ORC_OUT];
     double wsum, w[64];
 } smp_state;
 
 static void sample_forward(const float *pc, const float *feat, int C, const orc_mlp *mlp,
+                           const orc_wq *wq, const orc_quant *q, double *off,
                            const float *d, float t, const int32_t *idx, int K, float eps_idw,
                            smp_state *st)
 {
@@ -584,32 +665,49 @@ static void sample_forward(const float *pc, const float *feat, int C, const orc_
         st->wsum += wk;
         for (int c = 0; c < C; ++c) st->f[c] += wk * feat[(int64_t)idx[k] * C + c];
     }
-    for (int c = 0; c < C; ++c) st->f[c] /= st->wsum;
+    for (int c = 0; c < C; ++c) {
+        st->f[c] /= st->wsum;
+        st->fq[c] = operand(q, st->f[c], off ? off + c : NULL);
+    }
     for (int o = 0; o < ORC_HID; ++o) {
         double a = mlp->b1[o];
-        for (int c = 0; c < C; ++c) a += (double)mlp->W1[o * C + c] * st->f[c];
-        st->h1[o] = a > 0 ? a : 0.0;
+        for (int c = 0; c < C; ++c) a += wq->W1[o * C + c] * st->fq[c];
+        st->z1[o] = a;
+        st->h1q[o] = operand(q, a > 0 ? a : 0.0, off ? off + C + o : NULL);
     }
     for (int o = 0; o < ORC_HID; ++o) {
         double a = mlp->b2[o];
-        for (int c = 0; c < ORC_HID; ++c) a += (double)mlp->W2[o * ORC_HID + c] * st->h1[c];
-        st->h2[o] = a > 0 ? a : 0.0;
+        for (int c = 0; c < ORC_HID; ++c) a += wq->W2[o * ORC_HID + c] * st->h1q[c];
+        st->z2[o] = a;
+        st->h2q[o] = operand(q, a > 0 ? a : 0.0, off ? off + C + ORC_HID + o : NULL);
     }
     for (int o = 0; o < ORC_OUT; ++o) {
         double a = mlp->b3[o];
-        for (int c = 0; c < ORC_HID; ++c) a += (double)mlp->W3[o * ORC_HID + c] * st->h2[c];
+        for (int c = 0; c < ORC_HID; ++c) a += wq->W3[o * ORC_HID + c] * st->h2q[c];
         st->o[o] = a;
     }
 }
 
-void or_render64(const float *pc, const float *feat, int32_t C,
-                 const float *W1, const float *b1, const float *W2, const float *b2,
-                 const float *W3, const float *b3,
-                 const orc_camera *cam, const orc_params *p, const int32_t *pix, int64_t n_rays,
-                 const int32_t *n_sel, const float *smp_t, const int32_t *knn_idx,
-                 double *rgb, double *depth, double *acc)
+static double *sample_offsets(const orc_quant *q, int64_t row, int C)
+{
+    if (!q || q->mode == 0 || !q->act_off) return NULL;
+    return q->act_off + row * ORC_ACT_OFF(C);
+}
+
+/* Render (Eq. 2) of the exact stage's samples, binary64; decoder operands */
+/* under quant (0: none, 1: bfloat16, 2: recorded offsets; see above).     */
+void or_render64q(const float *pc, const float *feat, int32_t C,
+                  const float *W1, const float *b1, const float *W2, const float *b2,
+                  const float *W3, const float *b3,
+                  const orc_camera *cam, const orc_params *p, const int32_t *pix, int64_t n_rays,
+                  const int32_t *n_sel, const float *smp_t, const int32_t *knn_idx,
+                  int32_t quant, double *w_off, double *act_off,
+                  double *rgb, double *depth, double *acc)
 {
     const orc_mlp mlp = {W1, b1, W2, b2, W3, b3};
+    const orc_quant q = {quant, w_off, act_off};
+    orc_wq wq;
+    if (!wq_make(&mlp, C, &q, &wq)) return;
     const int S = p->n_samples, K = p->K;
 #pragma omp parallel
     {
@@ -622,8 +720,8 @@ void or_render64(const float *pc, const float *feat, int32_t C,
             const int ns = n_sel[r];
             for (int s = 0; s < ns; ++s) {
                 const int64_t row = r * S + s;
-                sample_forward(pc, feat, C, &mlp, d, smp_t[row], knn_idx + row * K, K,
-                               p->eps_idw, st);
+                sample_forward(pc, feat, C, &mlp, &wq, &q, sample_offsets(&q, row, C), d,
+                               smp_t[row], knn_idx + row * K, K, p->eps_idw, st);
                 double sigma = softplus(st->o[3]);
                 double delta = (s + 1 < ns) ? (double)smp_t[row + 1] - (double)smp_t[row]
                                             : (double)p->delta_last;
@@ -640,23 +738,42 @@ void or_render64(const float *pc, const float *feat, int32_t C,
         }
         free(st);
     }
+    free(wq.W1);
+}
+
+void or_render64(const float *pc, const float *feat, int32_t C,
+                 const float *W1, const float *b1, const float *W2, const float *b2,
+                 const float *W3, const float *b3,
+                 const orc_camera *cam, const orc_params *p, const int32_t *pix, int64_t n_rays,
+                 const int32_t *n_sel, const float *smp_t, const int32_t *knn_idx,
+                 double *rgb, double *depth, double *acc)
+{
+    or_render64q(pc, feat, C, W1, b1, W2, b2, W3, b3, cam, p, pix, n_rays, n_sel, smp_t, knn_idx,
+                 0, NULL, NULL, rgb, depth, acc);
 }
 
 /* ------------------------------------------------------------------------ */
 /* Gradient of sum_r grad_rgb[r] . rgb[r] with respect to the features and  */
 /* the MLP parameters, for the render above (analytic, binary64).  The      */
-/* samples are functions of geometry only, so they stay fixed.  Results are */
-/* ADDED to g_feat (n x C) and g_W1..g_b3.                                  */
+/* samples are functions of geometry only, so they stay fixed.  With quant  */
+/* 1 or 2 every rounding of a decoder operand counts as x -> x + (fixed     */
+/* offset): the products use the rounded operands (weights and activations) */
+/* and the ReLU masks the unrounded pre-activations.  Results are ADDED to  */
+/* g_feat (n x C) and g_W1..g_b3.                                           */
 /* ------------------------------------------------------------------------ */
-void or_grad64(const float *pc, const float *feat, int32_t C,
-               const float *W1, const float *b1, const float *W2, const float *b2,
-               const float *W3, const float *b3,
-               const orc_camera *cam, const orc_params *p, const int32_t *pix, int64_t n_rays,
-               const int32_t *n_sel, const float *smp_t, const int32_t *knn_idx,
-               const double *grad_rgb, double *g_feat,
-               double *g_W1, double *g_b1, double *g_W2, double *g_b2, double *g_W3, double *g_b3)
+void or_grad64q(const float *pc, const float *feat, int32_t C,
+                const float *W1, const float *b1, const float *W2, const float *b2,
+                const float *W3, const float *b3,
+                const orc_camera *cam, const orc_params *p, const int32_t *pix, int64_t n_rays,
+                const int32_t *n_sel, const float *smp_t, const int32_t *knn_idx,
+                int32_t quant, double *w_off, double *act_off,
+                const double *grad_rgb, double *g_feat,
+                double *g_W1, double *g_b1, double *g_W2, double *g_b2, double *g_W3, double *g_b3)
 {
     const orc_mlp mlp = {W1, b1, W2, b2, W3, b3};
+    const orc_quant q = {quant, w_off, act_off};
+    orc_wq wq;
+    if (!wq_make(&mlp, C, &q, &wq)) return;
     const int S = p->n_samples, K = p->K;
     const int n_w1 = ORC_HID * C, n_w2 = ORC_HID * ORC_HID, n_w3 = ORC_OUT * ORC_HID;
     const int n_par = n_w1 + ORC_HID + n_w2 + ORC_HID + n_w3 + ORC_OUT;
@@ -688,8 +805,8 @@ void or_grad64(const float *pc, const float *feat, int32_t C,
             double T = 1.0;
             for (int s = 0; s < ns; ++s) {
                 const int64_t row = r * S + s;
-                sample_forward(pc, feat, C, &mlp, d, smp_t[row], knn_idx + row * K, K,
-                               p->eps_idw, &st[s]);
+                sample_forward(pc, feat, C, &mlp, &wq, &q, sample_offsets(&q, row, C), d,
+                               smp_t[row], knn_idx + row * K, K, p->eps_idw, &st[s]);
                 sigma[s] = softplus(st[s].o[3]);
                 delta[s] = (s + 1 < ns) ? (double)smp_t[row + 1] - (double)smp_t[row]
                                         : (double)p->delta_last;
@@ -711,32 +828,32 @@ void or_grad64(const float *pc, const float *feat, int32_t C,
                 for (int k = 0; k < 3; ++k) U[k] = a[s] * c[k] + (1.0 - a[s]) * U[k];
                 P = (1.0 - a[s]) * P;
                 /* MLP backward */
-                double gh2[ORC_HID], gh1[ORC_HID], gf[64];
+                double gz2[ORC_HID], gz1[ORC_HID], gf[64];
                 for (int o = 0; o < ORC_OUT; ++o) {
                     gb3[o] += go[o];
-                    for (int c2 = 0; c2 < ORC_HID; ++c2) gw3[o * ORC_HID + c2] += go[o] * st[s].h2[c2];
+                    for (int c2 = 0; c2 < ORC_HID; ++c2) gw3[o * ORC_HID + c2] += go[o] * st[s].h2q[c2];
                 }
                 for (int c2 = 0; c2 < ORC_HID; ++c2) {
                     double acc2 = 0.0;
-                    for (int o = 0; o < ORC_OUT; ++o) acc2 += (double)W3[o * ORC_HID + c2] * go[o];
-                    gh2[c2] = st[s].h2[c2] > 0 ? acc2 : 0.0;
+                    for (int o = 0; o < ORC_OUT; ++o) acc2 += wq.W3[o * ORC_HID + c2] * go[o];
+                    gz2[c2] = st[s].z2[c2] > 0 ? acc2 : 0.0;
                 }
                 for (int o = 0; o < ORC_HID; ++o) {
-                    gb2[o] += gh2[o];
-                    for (int c1 = 0; c1 < ORC_HID; ++c1) gw2[o * ORC_HID + c1] += gh2[o] * st[s].h1[c1];
+                    gb2[o] += gz2[o];
+                    for (int c1 = 0; c1 < ORC_HID; ++c1) gw2[o * ORC_HID + c1] += gz2[o] * st[s].h1q[c1];
                 }
                 for (int c1 = 0; c1 < ORC_HID; ++c1) {
                     double acc1 = 0.0;
-                    for (int o = 0; o < ORC_HID; ++o) acc1 += (double)W2[o * ORC_HID + c1] * gh2[o];
-                    gh1[c1] = st[s].h1[c1] > 0 ? acc1 : 0.0;
+                    for (int o = 0; o < ORC_HID; ++o) acc1 += wq.W2[o * ORC_HID + c1] * gz2[o];
+                    gz1[c1] = st[s].z1[c1] > 0 ? acc1 : 0.0;
                 }
                 for (int o = 0; o < ORC_HID; ++o) {
-                    gb1[o] += gh1[o];
-                    for (int c0 = 0; c0 < C; ++c0) gw1[o * C + c0] += gh1[o] * st[s].f[c0];
+                    gb1[o] += gz1[o];
+                    for (int c0 = 0; c0 < C; ++c0) gw1[o * C + c0] += gz1[o] * st[s].fq[c0];
                 }
                 for (int c0 = 0; c0 < C; ++c0) {
                     double acc0 = 0.0;
-                    for (int o = 0; o < ORC_HID; ++o) acc0 += (double)W1[o * C + c0] * gh1[o];
+                    for (int o = 0; o < ORC_HID; ++o) acc0 += wq.W1[o * C + c0] * gz1[o];
                     gf[c0] = acc0;
                 }
                 /* inverse-distance aggregation backward */
@@ -768,6 +885,19 @@ void or_grad64(const float *pc, const float *feat, int32_t C,
         for (int i = 0; i < ORC_OUT; ++i) g_b3[i] += gb3[i];
     }
     free(gpar);
+    free(wq.W1);
+}
+
+void or_grad64(const float *pc, const float *feat, int32_t C,
+               const float *W1, const float *b1, const float *W2, const float *b2,
+               const float *W3, const float *b3,
+               const orc_camera *cam, const orc_params *p, const int32_t *pix, int64_t n_rays,
+               const int32_t *n_sel, const float *smp_t, const int32_t *knn_idx,
+               const double *grad_rgb, double *g_feat,
+               double *g_W1, double *g_b1, double *g_W2, double *g_b2, double *g_W3, double *g_b3)
+{
+    or_grad64q(pc, feat, C, W1, b1, W2, b2, W3, b3, cam, p, pix, n_rays, n_sel, smp_t, knn_idx,
+               0, NULL, NULL, grad_rgb, g_feat, g_W1, g_b1, g_W2, g_b2, g_W3, g_b3);
 }
 
 int32_t or_num_threads(void)

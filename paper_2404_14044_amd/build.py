@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJ_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(HERE, "libhashpoint.so")
-SOURCES = ["api.hip", "build.hip", "search.hip", "render.hip", "backward.hip", "knp.hip", "fused.hip"]
+SOURCES = ["api.hip", "build.hip", "search.hip", "render.hip", "backward.hip", "knp.hip", "fused.hip", "diag.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -198,6 +198,19 @@ hp_status hp_paper_kernel_size(const hp_camera *cam, const hp_params *p, int32_t
     return HP_OK;
 }
 
+hp_status hp_samples_shape(int64_t R, const hp_params *p, hp_shape *out)
+{
+    if (!p || !out || R < 0 || !valid_params(*p)) return HP_E_INVALID;
+    const int64_t lim = (int64_t)1 << 62;
+    const int64_t S = p->n_samples, K = p->K, M = p->m_cap;
+    if (R > lim / S || R * S > lim / K || R > lim / M) return HP_E_CAPACITY;
+    out->n_rays = R;
+    out->sample_rows = R * S;
+    out->knn_entries = R * S * K;
+    out->nbr_entries = R * M;
+    return HP_OK;
+}
+
 size_t hp_table_workspace(int64_t n, const hp_camera *cams, int32_t n_views, const hp_params *p,
                           hp_status *status)
 {
@@ -357,6 +370,13 @@ hp_status hp_search_render(const hp_table *tab, const hp_camera *cams, int32_t n
     a.K = p->K;
     const hipError_t e =
         hp::launch_fused(c, a, knn_template(p->K), precision, (hipStream_t)stream);
+    return e == hipSuccess ? HP_OK : hip_fail(e);
+}
+
+hp_status hp_exp32_eval(const float *x, float *y, int64_t n, void *stream)
+{
+    if (n < 0 || (n > 0 && (!x || !y))) return HP_E_INVALID;
+    const hipError_t e = hp::launch_exp_neg(x, y, n, (hipStream_t)stream);
     return e == hipSuccess ? HP_OK : hip_fail(e);
 }
 

@@ -12,9 +12,14 @@
 //            front of each sample forward, then the suffix sums of colour and
 //            transmittance backward -> dL/d(decoder outputs), in place;
 //   pass B   per tile: the decoder is replayed keeping its activations, the
-//            gradient flows back through it on FP32 matrix cores (weights
-//            FP32) to the aggregated features, and through the aggregation
-//            to the point features with atomics.
+//            gradient flows back through it on FP32 matrix cores to the
+//            aggregated features, and through the aggregation to the point
+//            features with atomics.
+// With the BF16 decoder every rounding of a decoder operand (weights,
+// aggregated feature, hidden activations) counts as adding a fixed offset:
+// the backward products use the rounded operands (as FP32 values) and the
+// ReLU masks use the unrounded pre-activations, so the result is the exact
+// gradient of the BF16 forward with its rounding offsets held fixed.
 // Decoder-parameter gradients are accumulated per workgroup in a zeroed slice of
 // the workspace with global atomics (L2 atomics on whole lines are much faster
 // here than LDS float atomics); a second kernel sums the slices in order into
@@ -143,19 +148,22 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
         if constexpr (PREC == HP_BF16) load_mlp_bf16(A.w, m);
         else load_mlp_f32(A.w, m);
     };
+    // a value as the decoder consumes it (bfloat16-rounded with the BF16 decoder)
+    auto opnd = [](float w) { return PREC == HP_BF16 ? bf16_round(w) : w; };
     for (int i = threadIdx.x; i < 16 * WAVE; i += blockDim.x) {
         const int ln = i % WAVE, blk = i / WAVE, o1 = blk >> 2, o2 = blk & 3;
         const int r = ln & 15, qq = ln >> 4;
         const float *w = A.w.W2 + (16 * o2 + 4 * qq) * HP_HIDDEN + 16 * o1 + r;
-        imgW2[i] = make_float4(w[0], w[HP_HIDDEN], w[2 * HP_HIDDEN], w[3 * HP_HIDDEN]);
+        imgW2[i] = make_float4(opnd(w[0]), opnd(w[HP_HIDDEN]), opnd(w[2 * HP_HIDDEN]), opnd(w[3 * HP_HIDDEN]));
     }
     for (int i = threadIdx.x; i < 8 * WAVE; i += blockDim.x) {
         const int ln = i % WAVE, blk = i / WAVE, cb = blk >> 2, o1 = blk & 3;
         const int r = ln & 15, qq = ln >> 4;
         const float *w = A.w.W1 + (16 * o1 + 4 * qq) * HP_FEAT_DIM + 16 * cb + r;
-        imgW1[i] = make_float4(w[0], w[HP_FEAT_DIM], w[2 * HP_FEAT_DIM], w[3 * HP_FEAT_DIM]);
+        imgW1[i] = make_float4(opnd(w[0]), opnd(w[HP_FEAT_DIM]), opnd(w[2 * HP_FEAT_DIM]),
+                               opnd(w[3 * HP_FEAT_DIM]));
     }
-    for (int i = threadIdx.x; i < 4 * HP_HIDDEN; i += blockDim.x) sW3[i] = A.w.W3[i];
+    for (int i = threadIdx.x; i < 4 * HP_HIDDEN; i += blockDim.x) sW3[i] = opnd(A.w.W3[i]);
     __syncthreads();
     // lane l: column l of dW3, entry l of db1 and db2, entry l < 4 of db3
     float gW3[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -283,6 +291,9 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
                     sh.row[r16] = row;
                     sh.inv[r16] = inv;
                 }
+                // the weight gradients contract the activations as the next
+                // layer consumed them (bfloat16-rounded with the BF16 decoder);
+                // the registers keep the unrounded values for the ReLU masks
 #pragma unroll
                 for (int ob = 0; ob < 4; ++ob)
 #pragma unroll
@@ -291,11 +302,11 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
                             h1[ob][e] = 0.0f;
                             h2[ob][e] = 0.0f;
                         }
-                        sh.H1T[16 * ob + 4 * q + e][ps] = h1[ob][e];
-                        sh.H2T[16 * ob + 4 * q + e][ps] = h2[ob][e];
+                        sh.H1T[16 * ob + 4 * q + e][ps] = opnd(h1[ob][e]);
+                        sh.H2T[16 * ob + 4 * q + e][ps] = opnd(h2[ob][e]);
                     }
 #pragma unroll
-                for (int e = 0; e < 8; ++e) FT[(8 * q + e) * 16 + ps] = f[e];
+                for (int e = 0; e < 8; ++e) FT[(8 * q + e) * 16 + ps] = opnd(f[e]);
             }
             // the tile's neighbour lists, fetched now (all loads independent,
             // in flight during the products) and staged in LDS after them

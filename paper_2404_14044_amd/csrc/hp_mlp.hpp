@@ -23,6 +23,9 @@ __device__ __forceinline__ uint32_t bf16_bits_rne(float x)
     return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
 }
 
+// x rounded to bfloat16 (round to nearest, ties to even), as a float
+__device__ __forceinline__ float bf16_round(float x) { return __uint_as_float(bf16_bits_rne(x) << 16); }
+
 __device__ __forceinline__ bf16x8 pack_bf16x8(const float *v)
 {
     union {

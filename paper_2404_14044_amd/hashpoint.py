@@ -27,7 +27,7 @@ HIDDEN = 64
 EXPORTED = ["hp_table_workspace", "hp_view_bounds", "hp_paper_kernel_size", "hp_build_table", "hp_search_sample",
             "hp_render", "hp_backward_workspace", "hp_render_backward",
             "hp_backward_samples_workspace", "hp_render_backward_samples", "hp_knp_blend",
-            "hp_search_render",
+            "hp_search_render", "hp_samples_shape", "hp_exp32_eval",
             "hp_status_str",
             "hp_last_hip_error"]
 
@@ -80,6 +80,11 @@ class HPSamples(ctypes.Structure):
                  "nbr_idx", "nbr_t")]
 
 
+class HPShape(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in
+                ("n_rays", "sample_rows", "knn_entries", "nbr_entries")]
+
+
 class HPMlp(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in ("W1", "b1", "W2", "b2", "W3", "b3")]
 
@@ -119,6 +124,10 @@ def lib():
         L.hp_backward_samples_workspace.argtypes = [P, P]
         L.hp_render_backward_samples.restype = i32
         L.hp_render_backward_samples.argtypes = [P, i64, P, i32, P, i32, P, P, P, P, P, ctypes.c_size_t, P]
+        L.hp_samples_shape.restype = i32
+        L.hp_samples_shape.argtypes = [i64, P, P]
+        L.hp_exp32_eval.restype = i32
+        L.hp_exp32_eval.argtypes = [P, P, i64, P]
         L.hp_status_str.restype = ctypes.c_char_p
         L.hp_status_str.argtypes = [i32]
         L.hp_last_hip_error.restype = i32
@@ -255,20 +264,38 @@ def build_table(xyz: torch.Tensor, cams, params, ws: Optional[torch.Tensor] = No
     return Table(ws, tab, list(cams), params, xyz)
 
 
+def samples_shape(n_rays: int, params) -> HPShape:
+    """Element counts of the sample arrays for n_rays rays (hp_samples_shape)."""
+    sh = HPShape()
+    p = make_params(params)
+    _check(lib().hp_samples_shape(int(n_rays), ctypes.byref(p), ctypes.byref(sh)), "hp_samples_shape")
+    return sh
+
+
 def alloc_samples(n_rays: int, params, device, debug: bool = False) -> Dict[str, torch.Tensor]:
-    R, S, K, M = n_rays, params.n_samples, params.K, params.m_cap
+    sh = samples_shape(n_rays, params)
+    R = sh.n_rays
     out = {
         "n_sel": torch.empty(R, dtype=torch.int32, device=device),
         "primary": torch.empty(R, dtype=torch.int32, device=device),
         "n_nbr": torch.empty(R, dtype=torch.int32, device=device),
         "flags": torch.empty(R, dtype=torch.int32, device=device),
-        "t": torch.empty(R * S, dtype=torch.float32, device=device),
-        "knn_idx": torch.empty(R * S * K, dtype=torch.int32, device=device),
-        "knn_dist": torch.empty(R * S * K, dtype=torch.float32, device=device),
+        "t": torch.empty(sh.sample_rows, dtype=torch.float32, device=device),
+        "knn_idx": torch.empty(sh.knn_entries, dtype=torch.int32, device=device),
+        "knn_dist": torch.empty(sh.knn_entries, dtype=torch.float32, device=device),
     }
     if debug:
-        out["nbr_idx"] = torch.empty(R * M, dtype=torch.int32, device=device)
-        out["nbr_t"] = torch.empty(R * M, dtype=torch.float32, device=device)
+        out["nbr_idx"] = torch.empty(sh.nbr_entries, dtype=torch.int32, device=device)
+        out["nbr_t"] = torch.empty(sh.nbr_entries, dtype=torch.float32, device=device)
+    return out
+
+
+def exp32_eval(x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """The device's binary32 exp of the candidate confidences, element-wise."""
+    if out is None:
+        out = torch.empty_like(x)
+    _check(lib().hp_exp32_eval(_dev(x, torch.float32, "x"), _dev(out, torch.float32, "out"),
+                               int(x.numel()), _stream(stream)), "hp_exp32_eval")
     return out
 
 

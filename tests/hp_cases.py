@@ -83,6 +83,22 @@ def compare_exact(sc, smp, pix, params=None, view=0, ray_base=0, check_lists=Tru
     return ex
 
 
+# Render tolerances (max abs vs the oracle's binary64 render).  RGB and
+# acc = sum of the compositing weights are in [0, 1]; depth = sum of weight x t
+# moves by at most t_far times the weights' error, so its bound is the RGB
+# bound scaled by t_far.
+FP32_TOL = 1e-5
+BF16_TOL = 2e-3
+
+
+def assert_render_error(err, precision, params):
+    """rgb, acc within the precision's bound; depth within bound * t_far."""
+    tol = FP32_TOL if precision == 0 else BF16_TOL
+    assert err["rgb"] <= tol, ("rgb", err)
+    assert err["acc"] <= tol, ("acc", err)
+    assert err["depth"] <= tol * float(params.t_far), ("depth", err)
+
+
 def render_error(sc, out, ex, pix, params=None, view=0, ray_base=0):
     cam = sc.cams[view]
     p = params or sc.params

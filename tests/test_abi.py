@@ -210,3 +210,25 @@ def test_knp_blend_rejects_bad_arguments_without_launching():
                           None) == hp.HP_E_INVALID
     assert L.hp_knp_blend(None, arr, 1, ctypes.byref(pp), 8, fake, fake, None, None, None,
                           None) == hp.HP_E_INVALID
+
+
+def test_samples_shape_counts():
+    sc = scenes.sphere_plane(n_sphere=10, n_plane=10)
+    p = sc.params.replace(K=5, n_samples=7, m_cap=33)
+    sh = hp.samples_shape(1000, p)
+    assert (sh.n_rays, sh.sample_rows, sh.knn_entries, sh.nbr_entries) == (1000, 7000, 35000, 33000)
+    assert hp.samples_shape(0, p).knn_entries == 0
+    L = hp.lib()
+    out = hp.HPShape()
+    pp = hp.make_params(p)
+    assert L.hp_samples_shape(-1, ctypes.byref(pp), ctypes.byref(out)) == hp.HP_E_INVALID
+    assert L.hp_samples_shape(1 << 60, ctypes.byref(pp), ctypes.byref(out)) == hp.HP_E_CAPACITY
+    bad = hp.make_params(p.replace(K=0))
+    assert L.hp_samples_shape(10, ctypes.byref(bad), ctypes.byref(out)) == hp.HP_E_INVALID
+
+
+def test_exp32_eval_rejects_bad_arguments():
+    L = hp.lib()
+    assert L.hp_exp32_eval(None, None, -1, None) == hp.HP_E_INVALID
+    assert L.hp_exp32_eval(None, None, 4, None) == hp.HP_E_INVALID
+    assert L.hp_exp32_eval(None, None, 0, None) == hp.HP_OK

@@ -6,20 +6,23 @@ inverse-distance aggregation; samples are recomputed from the table.
 FP32 forward: max abs error over each tensor, relative to its largest entry,
 within 1e-4 of the binary64 gradient (FP32 accumulation and atomics).
 
-BF16 forward: the decoder's activations carry bfloat16 rounding, which flips
-the sign of ReLU units near zero, so the gradient differs from the unrounded
-binary64 one by up to ~20% of the largest entry (relative L2 ~5%).  That part
-is checked against a binary64 reference with the same bfloat16 roundings
-(tests/bf16_emul.py) to 1e-3, and against the oracle within a relative L2 of
-0.1.
+BF16 forward: the reference is the oracle's binary64 gradient of the same
+BF16 decoder (operands rounded to bfloat16, each rounding counted as a fixed
+offset; pinned on the CPU by tests/test_oracle_bf16.py), within 1e-3 max
+over max.  The GPU forms its activations in FP32 and the oracle in binary64,
+so now and then one activation lands on the other side of a bfloat16
+rounding boundary (its operand then differs by one bfloat16 step, 2^-8
+relative) or a pre-activation within FP32 rounding of zero flips its ReLU
+mask; each such event moves one sample's contribution by about that much,
+which keeps the summed gradients well inside 1e-3 of their largest entry.
+The distance to the unrounded binary64 gradient (the cost of the rounding
+itself, about 5% relative L2) is reported and bounded by 0.1.
 """
 import numpy as np
 import pytest
 
 import oracle
 from paper_2404_14044_amd import scenes
-
-from bf16_emul import grad_bf16
 
 pytestmark = pytest.mark.gpu
 
@@ -40,7 +43,7 @@ def _gpu(sc, grad_rgb, precision):
     return gf.cpu().numpy(), {k: v.cpu().numpy() for k, v in gm.items()}, tab
 
 
-def _oracle(sc, grad_rgb, rays_per_view, fn=None):
+def _oracle(sc, grad_rgb, rays_per_view, quant=0):
     """binary64 gradient of sum(grad_rgb * rgb) over the given rays of each view."""
     out = {"feat": np.zeros(sc.feat.shape)}
     for k in KEYS:
@@ -52,7 +55,7 @@ def _oracle(sc, grad_rgb, rays_per_view, fn=None):
             pc = oracle.to_camera(sc.xyz, cam)
             ex = oracle.exact(pc, cam, sc.params, pix)
             gr = grad_rgb[base + np.asarray(pix, np.int64)].astype(np.float64)
-            g = (fn or oracle.grad64)(pc, sc.feat, sc.mlp, cam, sc.params, ex, gr)
+            g = oracle.grad64(pc, sc.feat, sc.mlp, cam, sc.params, ex, gr, quant=quant)
             for k in out:
                 out[k] += g[k]
         base += cam.W * cam.H
@@ -79,11 +82,15 @@ def _check(gpu_f, gpu_m, ref, tol, rel_l2=None):
         assert all(e[1] <= rel_l2 for e in errs.values()), errs
 
 
+FP32_GRAD_TOL = 1e-4
+BF16_GRAD_TOL = 1e-3
+
+
 def _check_precision(sc, grad_rgb, rays, prec_name, gf, gm):
     if prec_name == "fp32":
-        _check(gf, gm, _oracle(sc, grad_rgb, rays), 1e-4)
+        _check(gf, gm, _oracle(sc, grad_rgb, rays), FP32_GRAD_TOL)
     else:
-        _check(gf, gm, _oracle(sc, grad_rgb, rays, grad_bf16), 1e-3)
+        _check(gf, gm, _oracle(sc, grad_rgb, rays, quant=oracle.QUANT_BF16), BF16_GRAD_TOL)
         _check(gf, gm, _oracle(sc, grad_rgb, rays), None, rel_l2=0.1)
 
 
@@ -188,6 +195,83 @@ def test_backward_matches_central_differences():
         an = float(gf[ij]) if name == "feat" else float(gm[name][ij])
         err = abs(fd - an) / max(1e-3, abs(fd))
         worst = max(worst, err)
+        assert abs(fd - an) <= 2e-3 * max(1e-2, abs(fd)), (name, ij, fd, an)
+    print("worst relative FD error", worst)
+
+
+def test_backward_diff_4x400_full_size():
+    """The differentiable workload as stated: 1M points, 4 views of 400x400,
+    BF16 forward, FP32 gradients.  The loss gradient reaches 2048 random rays
+    of each view.  Per tensor, the GPU gradient is compared with the oracle's
+    binary64 gradient of the BF16 decoder; on 64 coordinates (48 feature
+    entries of points the samples use, 16 decoder parameters) with binary64
+    central differences of the oracle's BF16 render with its rounding offsets
+    held fixed (the function whose exact gradient that is)."""
+    from paper_2404_14044_amd import hashpoint as hp
+    sc = scenes.diff_4x400()
+    assert sc.xyz.shape[0] == 1_000_000 and all(c.W == 400 and c.H == 400 for c in sc.cams)
+    sizes = [c.W * c.H for c in sc.cams]
+    rng = np.random.default_rng(55)
+    grad_rgb = np.zeros((sum(sizes), 3), np.float32)
+    rays, base = [], 0
+    for s_ in sizes:
+        pix = np.sort(rng.choice(s_, 2048, replace=False)).astype(np.int32)
+        grad_rgb[base + pix] = rng.normal(size=(pix.size, 3))
+        rays.append(pix)
+        base += s_
+    gf, gm, _ = _gpu(sc, grad_rgb, hp.HP_BF16)
+    ref = _oracle(sc, grad_rgb, rays, quant=oracle.QUANT_BF16)
+    errs = _errors(gf, gm, ref)
+    print("diff_4x400 BF16 gradient (max/max, relative L2) per tensor:")
+    for k, e in errs.items():
+        print(f"  {k:5s} {e[0]:.3e} {e[1]:.3e}")
+    assert all(e[0] <= BF16_GRAD_TOL for e in errs.values()), errs
+
+    views = []
+    for v, cam in enumerate(sc.cams):
+        pc = oracle.to_camera(sc.xyz, cam)
+        ex = oracle.exact(pc, cam, sc.params, rays[v])
+        off = oracle.QuantOffsets(rays[v].size, sc.params)
+        oracle.render64(pc, sc.feat, sc.mlp, cam, sc.params, ex, quant=oracle.QUANT_BF16, offsets=off)
+        w = grad_rgb[sum(sizes[:v]) + rays[v].astype(np.int64)].astype(np.float64)
+        views.append((cam, pc, ex, off, w))
+    used = np.unique(np.concatenate([vw[2]["knn_idx"][vw[2]["knn_idx"] >= 0] for vw in views]))
+    assert used.size > 1000
+
+    def loss(feat, mlp):
+        tot = 0.0
+        for cam, pc, ex, off, w in views:
+            out = oracle.render64(pc, feat, mlp, cam, sc.params, ex, quant=oracle.QUANT_FROZEN,
+                                  offsets=off)
+            tot += float((out["rgb"] * w).sum())
+        return tot
+
+    coords = [("feat", (int(i), int(c))) for i, c in zip(rng.choice(used, 48), rng.integers(0, 32, 48))]
+    for _ in range(16):
+        k = KEYS[rng.integers(0, 6)]
+        coords.append((k, tuple(int(rng.integers(0, s)) for s in sc.mlp[k].shape)))
+    print("coordinate, central difference, GPU, relative error")
+    worst = 0.0
+    for name, ij in coords:
+        base_arr = sc.feat if name == "feat" else sc.mlp[name]
+        h = 1e-5 * max(1.0, abs(float(base_arr[ij])))
+        vals = []
+        for sgn in (1, -1):
+            arr = base_arr.astype(np.float64).copy()
+            arr[ij] += sgn * h
+            arr = arr.astype(np.float32)
+            if name == "feat":
+                vals.append(loss(arr, sc.mlp))
+            else:
+                m2 = dict(sc.mlp)
+                m2[name] = arr
+                vals.append(loss(sc.feat, m2))
+        step = float(np.float32(base_arr[ij] + h)) - float(np.float32(base_arr[ij] - h))
+        fd = (vals[0] - vals[1]) / step
+        an = float(gf[ij]) if name == "feat" else float(gm[name][ij])
+        err = abs(fd - an) / max(1e-2, abs(fd))
+        worst = max(worst, err)
+        print(f"  {name}{list(ij)} {fd:+.6e} {an:+.6e} {err:.2e}")
         assert abs(fd - an) <= 2e-3 * max(1e-2, abs(fd)), (name, ij, fd, an)
     print("worst relative FD error", worst)
 

@@ -120,3 +120,27 @@ def test_autotuner_choice_changes_no_result(tmp_path):
     torch.cuda.synchronize()
     for k in ("n_sel", "primary", "n_nbr", "flags"):
         assert np.array_equal(host(a[k]), host(b[k]))
+
+
+def test_batched_16_full_size_matches_oracle():
+    """The batched workload as stated: 16 views of the 1M-point object scene,
+    sides uniform in {256..1024}, one table / search / render over all of them
+    (BF16 decoder).  256 random rays of every view against the oracle: exact
+    outputs bit for bit, rgb / depth / acc within the BF16 bounds."""
+    from paper_2404_14044_amd import hashpoint as hp
+    from paper_2404_14044_amd.batched import BatchedRenderer
+    from hp_cases import assert_render_error, render_error
+    sc = scenes.batched_16()
+    assert min(c.W for c in sc.cams) >= 256 and max(c.W for c in sc.cams) <= 1024
+    xyz, feat, mlp = _setup(sc)
+    br = BatchedRenderer(xyz, feat, mlp, sc.cams, sc.params, hp.HP_BF16)
+    br.run_eager()
+    hit = 0
+    for v in range(len(sc.cams)):
+        info = br.table.view(v)
+        pix = sample_pixels(sc.cams[v], 256, seed=90 + v)
+        ex = compare_exact(sc, br.samples, pix, view=v, ray_base=info.ray_base, check_lists=False)
+        err = render_error(sc, br.out, ex, pix, view=v, ray_base=info.ray_base)
+        assert_render_error(err, 1, sc.params)
+        hit += int((ex["n_sel"] > 0).sum())
+    assert hit > 500
