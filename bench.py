@@ -35,16 +35,69 @@ def search_algorithmic_bytes(n_buckets, n_in, n_rays, s_tot, K):
     return 8 * n_buckets + 16 * n_in + 16 * n_rays + (4 + 8 * K) * s_tot
 
 
+def build_algorithmic_bytes(n, n_in, n_buckets):
+    """Table build: read xyz (12 B per point), write one 16 B entry and a
+    4 B index per inserted point plus a 4 B slot per point, and 8 B of
+    offsets and depth summary per bucket."""
+    return 12 * n + 24 * n_in + 8 * n_buckets
+
+
 def render_algorithmic_bytes(s_tot, K, n_used, n_rays, C=32):
+    """Render: every sample's t and K (index, distance), the features of every
+    point a sample uses (read once), 20 B of outputs per ray."""
     return (4 + 8 * K) * s_tot + 4 * C * n_used + 20 * n_rays
+
+
+MLP_FLOP_PER_SAMPLE = 2 * (32 * 64 + 64 * 64 + 64 * 4)   # 12,800
+CHIP_CUS, CHIP_GHZ = 256, 2.4
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_objects_1m.md")
+COUNTER_SOURCES = ("paper_2404_14044_amd/csrc", "include")
+
+
+def sources_sha():
+    """Hash of every source file the kernels are built from: counters taken
+    on another build describe another kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for d in COUNTER_SOURCES:
+        base = os.path.join(ROOT, d)
+        for name in sorted(os.listdir(base)):
+            if name.endswith((".hip", ".hpp", ".h")):
+                h.update(name.encode())
+                with open(os.path.join(base, name), "rb") as f:
+                    h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_counters():
+    """Per-kernel counter figures from the committed profile summary, or None
+    when they were taken on other sources than the ones built here."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    text = open(COUNTERS_FILE).read()
+    i = text.find("```json")
+    if i < 0:
+        return None
+    j = text.find("```", i + 7)
+    data = json.loads(text[i + 7:j])
+    return data if data.get("sources_sha") == sources_sha() else None
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a, np.float64), q))
+
+
+def dist_stats(a):
+    return {"mean": float(np.mean(a)), "median": pct(a, 50), "p10": pct(a, 10), "p90": pct(a, 90)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target wall time of the oracle CPU baseline (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
@@ -54,7 +107,14 @@ def main():
     ap.add_argument("--legs", default="all",
                     help="comma-separated extra legs to run (batched, train, radius, samplers, "
                          "knp, fused, room, sweep) or 'all'")
+    ap.add_argument("--summarize", nargs="+", metavar="DIR",
+                    help="print the markdown summary of rocprofv3 output directories "
+                         "(kernel stats and counter collections) and exit; no GPU used")
     args = ap.parse_args()
+
+    if args.summarize:
+        print(summarize_profiles(args.summarize))
+        return
 
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -78,15 +138,16 @@ def main():
     smp = hp.alloc_samples(R, p, dev)
     outs = {prec: {"rgb": torch.empty(R * 3, device=dev), "depth": torch.empty(R, device=dev),
                    "acc": torch.empty(R, device=dev)} for prec in (hp.HP_FP32, hp.HP_BF16)}
+    # the stream every launch below goes to; the events are recorded on it
     stream = torch.cuda.current_stream()
 
     def step(prec, ev=None):
         if ev: ev[0].record(stream)
-        tab = hp.build_table(xyz, [cam], p, ws=ws)
+        tab = hp.build_table(xyz, [cam], p, ws=ws, stream=stream)
         if ev: ev[1].record(stream)
-        hp.search_sample(tab, p, out=smp)
+        hp.search_sample(tab, p, out=smp, stream=stream)
         if ev: ev[2].record(stream)
-        hp.render(smp, R, feat, mlp, p, prec, out=outs[prec])
+        hp.render(smp, R, feat, mlp, p, prec, out=outs[prec], stream=stream)
         if ev: ev[3].record(stream)
         return tab
 
@@ -100,8 +161,8 @@ def main():
             tab = step(prec, evs[k])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        st = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
-                       for e in evs])
+        st = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3]),
+                        e[0].elapsed_time(e[3])] for e in evs])
         return wall, st, tab
 
     wall16, st16, tab = timed(hp.HP_BF16)
@@ -111,6 +172,7 @@ def main():
     n_in = int(offs[-1].item())
     n_sel = smp["n_sel"].cpu().numpy()
     s_tot = int(n_sel.sum())
+    hit_rays = int((smp["n_nbr"] > 0).sum().item())
     ki = smp["knn_idx"].view(R, p.n_samples, p.K)
     mask = torch.arange(p.n_samples, device=dev)[None, :] < smp["n_sel"][:, None]
     used = torch.unique(ki[mask].reshape(-1))
@@ -118,9 +180,14 @@ def main():
 
     ms16 = wall16 * 1e3 / args.steps
     ms32 = wall32 * 1e3 / args.steps
+    build_ms = float(np.mean(st16[:, 0]))
     search_ms = float(np.mean(st16[:, 1]))
+    render_ms = float(np.mean(st16[:, 2]))
     a_bytes = search_algorithmic_bytes(tab.n_buckets, n_in, R, s_tot, p.K)
     achieved = a_bytes / (search_ms * 1e-3) / 1e9
+    b_bytes = build_algorithmic_bytes(int(xyz.shape[0]), n_in, tab.n_buckets)
+    r_bytes = render_algorithmic_bytes(s_tot, p.K, n_used, R)
+    mlp_tflops = MLP_FLOP_PER_SAMPLE * s_tot / (render_ms * 1e-3) / 1e12
 
     result = {
         "metric": METRIC,
@@ -141,17 +208,49 @@ def main():
                    "rays": R, "points": int(xyz.shape[0]), "layout": args.layout},
         "value_fp32": R / (ms32 * 1e-3) / 1e6,
         "ms_per_step_fp32": ms32,
-        "stage_ms_bf16": {"build": float(np.mean(st16[:, 0])), "search_sample": search_ms,
-                          "render": float(np.mean(st16[:, 2]))},
-        "stage_ms_fp32": {"build": float(np.mean(st32[:, 0])),
-                          "search_sample": float(np.mean(st32[:, 1])),
-                          "render": float(np.mean(st32[:, 2]))},
+        "step_ms_bf16": dist_stats(st16[:, 3]),
+        "step_ms_fp32": dist_stats(st32[:, 3]),
+        "stage_ms_bf16": {"build": dist_stats(st16[:, 0]), "search_sample": dist_stats(st16[:, 1]),
+                          "render": dist_stats(st16[:, 2])},
+        "stage_ms_fp32": {"build": dist_stats(st32[:, 0]), "search_sample": dist_stats(st32[:, 1]),
+                          "render": dist_stats(st32[:, 2])},
         "workload_stats": {"n_in": n_in, "n_buckets": int(tab.n_buckets), "samples": s_tot,
-                           "hit_rays": int((n_sel > 0).sum()), "points_used": n_used},
+                           "rays_with_neighbours": hit_rays,
+                           "rays_with_samples": int((n_sel > 0).sum()), "points_used": n_used},
         "roofline": {"kernel": "k_search_sample", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "algorithmic_bytes": a_bytes},
+        "rooflines_other": {
+            "build": {"kernels": "k_project .. k_materialize (one build)", "bound": "hbm",
+                      "algorithmic_bytes": b_bytes, "achieved": b_bytes / (build_ms * 1e-3) / 1e9,
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": b_bytes / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "render_bf16": {"kernel": "k_render_bf16", "bound": "hbm",
+                            "algorithmic_bytes": r_bytes,
+                            "achieved": r_bytes / (render_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": r_bytes / (render_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                            "decoder_tflops": mlp_tflops,
+                            "decoder_frac_of_bf16_mfma_peak": mlp_tflops / MFMA_BF16_PEAK_TFLOPS},
+        },
     }
+    counters = load_counters()
+    if counters is not None:
+        ks = counters["kernels"].get("k_search_sample_k8")
+        if ks:
+            traffic = (ks["FETCH_SIZE_kib"] * counters["fetch_scale"]
+                       + ks["WRITE_SIZE_kib"] * counters["write_scale"]) * 1024.0
+            result["roofline"]["traffic"] = traffic
+            result["roofline"]["traffic_over_algorithmic"] = traffic / a_bytes
+            slots = search_ms * 1e-3 * CHIP_GHZ * 1e9 * CHIP_CUS
+            result["roofline"]["measured_limiter"] = {
+                "resource": "VALU issue (one wave64 VALU instruction per CU per cycle)",
+                "valu_insts": ks["SQ_INSTS_VALU"], "salu_insts": ks.get("SQ_INSTS_SALU"),
+                "valu_issue_frac": ks["SQ_INSTS_VALU"] / slots,
+                "valu_insts_per_ray_with_neighbours": ks["SQ_INSTS_VALU"] / max(hit_rays, 1)}
+        kr = counters["kernels"].get("k_render_bf16")
+        if kr and "SQ_INSTS_MFMA" in kr:
+            result["rooflines_other"]["render_bf16"]["mfma_insts"] = kr["SQ_INSTS_MFMA"]
+        result["roofline"]["counters_from"] = os.path.relpath(COUNTERS_FILE, ROOT)
     # achievable bandwidth on this machine: a plain 1 GiB device-to-device copy
     copy_gbs = copy_bandwidth_gbs(dev)
     result["roofline"]["copy_gbs"] = copy_gbs
@@ -179,12 +278,73 @@ def main():
             sys.exit(2)
         for name, key, fn in legs:
             if name in wanted:
+                print(f"bench.py: leg {name}", file=sys.stderr, flush=True)
                 result[key] = fn()
 
     if args.cpu_seconds > 0:
         result.update(cpu_leg(sc, p, smp, outs, R, args.cpu_seconds))
 
     print(json.dumps(result), flush=True)
+
+
+def summarize_profiles(dirs):
+    """Markdown summary of rocprofv3 runs: kernel statistics (calls, average
+    duration) from *_kernel_stats.csv and, from *_counter_collection.csv,
+    every counter's mean value per dispatch, by kernel.  The json block at the
+    end is what the bench line reads (with the hash of the sources)."""
+    import csv
+    stats, ctr = {}, {}
+    for d in dirs:
+        for root, _, files in os.walk(d):
+            for f in files:
+                path = os.path.join(root, f)
+                if f.endswith("kernel_stats.csv"):
+                    with open(path) as fh:
+                        for row in csv.DictReader(fh):
+                            stats[row["Name"]] = {"calls": int(row["Calls"]),
+                                                  "avg_us": float(row["AverageNs"]) / 1e3,
+                                                  "total_us": float(row["TotalDurationNs"]) / 1e3}
+                elif f.endswith("counter_collection.csv"):
+                    with open(path) as fh:
+                        for row in csv.DictReader(fh):
+                            k = row["Kernel_Name"].split("(")[0].strip()
+                            ent = ctr.setdefault(k, {}).setdefault(row["Counter_Name"], {})
+                            did = (path, row["Dispatch_Id"])
+                            ent[did] = ent.get(did, 0.0) + float(row["Counter_Value"])
+    out = ["| kernel | calls | avg µs | total µs |", "|---|---|---|---|"]
+    for name, v in sorted(stats.items(), key=lambda kv: -kv[1]["total_us"]):
+        out.append(f"| `{name.split('(')[0][:60]}` | {v['calls']} | {v['avg_us']:.1f} | "
+                   f"{v['total_us']:.1f} |")
+    names = sorted({c for k in ctr.values() for c in k})
+    out += ["", "| kernel | " + " | ".join(names) + " |", "|---" * (len(names) + 1) + "|"]
+    per_kernel = {}
+    for k in sorted(ctr):
+        vals = {}
+        for c in names:
+            d = ctr[k].get(c)
+            if d:
+                vals[c] = sum(d.values()) / len(d)
+        per_kernel[k] = {(c + "_kib" if c in ("FETCH_SIZE", "WRITE_SIZE") else c): v
+                         for c, v in vals.items()}
+        out.append(f"| `{k[:60]}` | " + " | ".join(f"{vals[c]:.4g}" if c in vals else "-"
+                                                   for c in names) + " |")
+    # calibration: the largest device copy in the runs is the 1 GiB copy that
+    # measures the box's bandwidth (1 GiB read, 1 GiB written)
+    scale = {"FETCH_SIZE": None, "WRITE_SIZE": None}
+    for k in ctr:
+        if "copyBuffer" not in k:
+            continue
+        for c in scale:
+            if c in ctr[k]:
+                scale[c] = float(1 << 30) / (max(ctr[k][c].values()) * 1024.0)
+    out += ["", f"Calibration (largest device copy, 1 GiB each way): FETCH_SIZE x "
+                f"{scale['FETCH_SIZE']}, WRITE_SIZE x {scale['WRITE_SIZE']}.",
+            "", "```json", json.dumps({"sources_sha": sources_sha(),
+                                        "fetch_scale": scale["FETCH_SIZE"],
+                                        "write_scale": scale["WRITE_SIZE"],
+                                        "kernels": per_kernel}, indent=1),
+            "```"]
+    return "\n".join(out)
 
 
 def copy_bandwidth_gbs(dev, nbytes=1 << 30, reps=5):
@@ -510,34 +670,66 @@ def exact_outputs_match(smp, ex, pix, p):
     return {k: bool(v) for k, v in res.items()}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_leg(sc, p, smp, outs, R, seconds):
     """Oracle (brute-force search, candidate walk, binary64 render) on a
-    bounded random sample of the same rays; also the GPU RGB error there."""
+    bounded random sample of the same rays, with every host thread and with
+    one; also the GPU's exact outputs and RGB errors on that sample."""
     import oracle
     from paper_2404_14044_amd import hashpoint as hp
     cam = sc.cams[0]
     pc = oracle.to_camera(sc.xyz, cam)
     rng = np.random.default_rng(99)
-    pix = np.sort(rng.choice(R, 256, replace=False)).astype(np.int32)
-    t0 = time.perf_counter()
-    oracle.exact(pc, cam, p, pix)
-    dt = time.perf_counter() - t0
+    threads = oracle.num_threads()
+
+    def run(pix):
+        t0 = time.perf_counter()
+        ex = oracle.exact(pc, cam, p, pix)
+        ref = oracle.render64(pc, sc.feat, sc.mlp, cam, p, ex)
+        return ex, ref, time.perf_counter() - t0
+
+    probe = np.sort(rng.choice(R, 256, replace=False)).astype(np.int32)
+    _, _, dt = run(probe)
     n = int(min(R, max(256, 256 * seconds / max(dt, 1e-3))))
     pix = np.sort(rng.choice(R, n, replace=False)).astype(np.int32)
-    t0 = time.perf_counter()
-    ex = oracle.exact(pc, cam, p, pix)
-    ref = oracle.render64(pc, sc.feat, sc.mlp, cam, p, ex)
-    dt = time.perf_counter() - t0
+    ex, ref, dt = run(pix)
+    # one thread, on a sample sized for about a fifth of the time
+    oracle.set_num_threads(1)
+    try:
+        n1 = int(max(64, n / max(threads, 1) / 5))
+        pix1 = np.sort(rng.choice(R, n1, replace=False)).astype(np.int32)
+        _, _, dt1 = run(pix1)
+    finally:
+        oracle.set_num_threads(threads)
     errs = {}
     for prec, name in ((hp.HP_BF16, "bf16"), (hp.HP_FP32, "fp32")):
-        rgb = outs[prec]["rgb"].cpu().numpy().reshape(-1, 3)[pix].astype(np.float64)
+        o = outs[prec]
+        rgb = o["rgb"].cpu().numpy().reshape(-1, 3)[pix].astype(np.float64)
+        dep = o["depth"].cpu().numpy()[pix].astype(np.float64)
+        acc = o["acc"].cpu().numpy()[pix].astype(np.float64)
         errs[f"rgb_err_{name}"] = float(np.abs(rgb - ref["rgb"]).max())
+        errs[f"depth_err_{name}"] = float(np.abs(dep - ref["depth"]).max())
+        errs[f"acc_err_{name}"] = float(np.abs(acc - ref["acc"]).max())
+        errs[f"rgb_err_p999_{name}"] = float(np.percentile(np.abs(rgb - ref["rgb"]), 99.9))
     errs["oracle_exact_match"] = exact_outputs_match(smp, ex, pix, p)
-    return {"cpu_baseline": {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(),
-                             "kind": "oracle",
+    model = cpu_model()
+    return {"cpu_baseline": {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": threads,
+                             "kind": "oracle", "cpu_model": model,
                              "sample": f"{n} random rays of the 800x800 view (brute-force search "
                                        f"over all 1M points, candidate walk, binary64 render), "
-                                       f"{dt:.1f} s"},
+                                       f"{dt:.1f} s on {threads} threads",
+                             "one_thread": {"value": n1 / dt1 / 1e6, "unit": "Mrays/s",
+                                            "sample": f"{n1} random rays, {dt1:.1f} s"}},
             **errs}
 
 

@@ -166,6 +166,9 @@ typedef struct hp_table {
     float *bucket_z;      /* [n_buckets] depth of each bucket's first point, +inf if empty */
     uint32_t *cell_zmin;  /* [n_cells] min depth (binary32 bits) of 8x8-bucket cells      */
     int64_t n_cells;
+    uint64_t build_key;   /* hash of the cameras and of the parameters the table
+                             depends on (radius, inv_tref, t_near, radius_mode,
+                             rddot, layout); calls on the table check it       */
     void *scratch;
     hp_view_info views[HP_MAX_VIEWS];
 } hp_table;
@@ -248,7 +251,9 @@ hp_status hp_build_table(const float *xyz, int64_t n, const hp_camera *cams, int
                          void *stream);
 
 /* Search and sample every ray of every view of the table (Sec. 3.2-3.3).
- *  cams and p must be the ones the table was built with.
+ *  cams and p must be the ones the table was built with: cameras and the
+ *  fields radius, inv_tref, t_near, radius_mode, rddot and layout must be
+ *  equal (HP_E_INVALID otherwise); the other fields may differ.
  *  out: device arrays sized for R = tab->n_rays rays (see hp_samples).
  * Errors: HP_E_INVALID, HP_E_UNSUPPORTED (K > HP_MAX_K). */
 hp_status hp_search_sample(const hp_table *tab, const hp_camera *cams, int32_t n_views,
@@ -298,17 +303,21 @@ hp_status hp_knp_blend(const hp_table *tab, const hp_camera *cams, int32_t n_vie
                        int32_t *knp_cnt, int32_t *knp_idx, float *knp_dist, void *stream);
 
 /* Workspace bytes hp_render_backward needs for this table and these
- * parameters (host only): per-workgroup decoder-gradient slices plus the
- * recomputed samples of all tab->n_rays rays (as hp_samples, without the
- * optional neighbour lists). */
+ * parameters (host only): per-workgroup decoder-gradient slices plus a ring
+ * for the recomputed samples (as hp_samples, without the optional neighbour
+ * lists) of one chunk of min(tab->n_rays, 65536) rays.  The workspace does not
+ * grow with the rays beyond that; hp_render_backward accepts any workspace
+ * that holds the slices and at least one ray, and recomputes the rays in
+ * chunks of as many as it holds. */
 size_t hp_backward_workspace(const hp_table *tab, const hp_params *p, hp_status *status);
 
 /* Gradient of L with respect to the features and MLP parameters (Sec. 3.4,
  * Eq. 2 differentiated through the decoder and the inverse-distance
  * aggregation), given grad_rgb = dL/drgb (device, R x 3, R = tab->n_rays).
- * Search and sampling are recomputed from the table into the workspace
- * (samples depend on geometry only), then the gradient is computed as in
- * hp_render_backward_samples.
+ * Search and sampling are recomputed from the table (samples depend on
+ * geometry only) one chunk of rays at a time into the workspace's ring, and
+ * each chunk's gradient is accumulated as in hp_render_backward_samples; the
+ * result does not depend on the chunk size beyond the order of float atomics.
  *  cams, n_views, p: as given to hp_build_table; precision: the decoder
  *      precision of the forward render (the activations are replayed in it;
  *      the gradient itself is FP32 with FP32 weights).
@@ -316,7 +325,8 @@ size_t hp_backward_workspace(const hp_table *tab, const hp_params *p, hp_status 
  *      FP32, shapes as hp_mlp) are ADDED to: zero them first for a plain
  *      gradient.  Feature gradients are accumulated with atomics, so results
  *      are reproducible to rounding only.
- *  ws: device workspace of at least hp_backward_workspace bytes.
+ *  ws: device workspace; hp_backward_workspace bytes, or any size that holds
+ *      the gradient slices and the samples of one ray (larger: fewer chunks).
  * Errors: HP_E_INVALID, HP_E_WORKSPACE, HP_E_UNSUPPORTED (C != HP_FEAT_DIM,
  *      K > HP_MAX_K). */
 hp_status hp_render_backward(const hp_table *tab, const hp_camera *cams, int32_t n_views,

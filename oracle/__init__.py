@@ -91,6 +91,7 @@ def lib():
         _lib.or_bf16.restype = ctypes.c_double
         _lib.or_bf16.argtypes = [ctypes.c_double]
         _lib.or_num_threads.restype = i32
+        _lib.or_set_num_threads.argtypes = [i32]
     return _lib
 
 
@@ -126,6 +127,11 @@ def params_struct(p) -> Params:
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads the oracle's parallel loops use from now on."""
+    lib().or_set_num_threads(int(n))
 
 
 def exp32(x) -> np.ndarray:

@@ -900,6 +900,15 @@ void or_grad64(const float *pc, const float *feat, int32_t C,
                0, NULL, NULL, grad_rgb, g_feat, g_W1, g_b1, g_W2, g_b2, g_W3, g_b3);
 }
 
+void or_set_num_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int32_t or_num_threads(void)
 {
 #ifdef _OPENMP

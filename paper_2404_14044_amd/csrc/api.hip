@@ -154,6 +154,30 @@ hp_status plan_views(const hp_camera *cams, int32_t n_views, const hp_params &p,
 
 int knn_template(int K) { return K <= 4 ? 4 : K <= 8 ? 8 : K <= 16 ? 16 : 32; }
 
+// FNV-1a over the cameras and the parameters a table depends on (its guard
+// band, window bounds and bucket layout): a search with other values would
+// use bounds that no longer cover every neighbour.
+uint64_t table_key(const hp_camera *cams, int32_t n_views, const hp_params &p)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void *data, size_t n) {
+        const unsigned char *b = static_cast<const unsigned char *>(data);
+        for (size_t i = 0; i < n; ++i) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    };
+    mix(&n_views, sizeof(n_views));
+    mix(cams, sizeof(hp_camera) * (size_t)n_views);
+    mix(&p.radius, sizeof(p.radius));
+    mix(&p.inv_tref, sizeof(p.inv_tref));
+    mix(&p.t_near, sizeof(p.t_near));
+    mix(&p.radius_mode, sizeof(p.radius_mode));
+    mix(&p.rddot, sizeof(p.rddot));
+    mix(&p.layout, sizeof(p.layout));
+    return h;
+}
+
 }  // namespace
 
 extern "C" {
@@ -255,6 +279,7 @@ hp_status hp_build_table(const float *xyz, int64_t n, const hp_camera *cams, int
     out->bucket_z = tw.bucket_z;
     out->cell_zmin = tw.cell_zmin;
     out->n_cells = geo.n_cells;
+    out->build_key = table_key(cams, n_views, *p);
     out->scratch = tw.views;
     memcpy(out->views, info, sizeof(hp_view_info) * n_views);
     return HP_OK;
@@ -264,7 +289,8 @@ static hp_status make_ctx(const hp_table *tab, const hp_camera *cams, int32_t n_
                           const hp_params *p, hp::SearchCtx &c)
 {
     if (!tab || !cams || !p || n_views != tab->n_views || !valid_params(*p)) return HP_E_INVALID;
-    if (p->layout != tab->layout) return HP_E_INVALID;
+    if (p->layout != tab->layout || table_key(cams, n_views, *p) != tab->build_key)
+        return HP_E_INVALID;
     if (p->K > HP_MAX_K) return HP_E_UNSUPPORTED;
     if (!tab->offsets || !tab->pts || !tab->slot_of || !tab->scratch || !tab->bucket_z ||
         !tab->cell_zmin)
@@ -286,6 +312,7 @@ static hp_status make_ctx(const hp_table *tab, const hp_camera *cams, int32_t n_
     c.n_views = n_views;
     c.layout = tab->layout;
     c.n_points = tab->n_points;
+    c.ray0 = 0;
     c.n_rays = tab->n_rays;
     c.radius = p->radius;
     c.inv_tref = p->inv_tref;
@@ -420,14 +447,18 @@ hp_status hp_render(const hp_samples *smp, int64_t R, const float *feat, int32_t
 }  // extern "C"
 
 // Backward workspace: decoder-gradient slices, then (for the recomputing
-// entry point) the samples of every ray, each array 256-byte aligned.
+// entry point) a ring holding the recomputed samples of one chunk of rays,
+// each array 256-byte aligned.  The chunk is as many rays as the workspace
+// holds (at most all of them), so the workspace need not grow with the rays.
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+constexpr int64_t BWD_DEFAULT_CHUNK_RAYS = 65536;
 
 struct BwdWsLayout {
     size_t partial, n_sel, primary, n_nbr, flags, t, knn_idx, knn_dist, bytes;
 };
 
-static BwdWsLayout bwd_ws_layout(int64_t R, const hp_params &p)
+static BwdWsLayout bwd_ws_layout(int64_t chunk_rays, const hp_params &p)
 {
     BwdWsLayout L;
     size_t off = 0;
@@ -436,17 +467,32 @@ static BwdWsLayout bwd_ws_layout(int64_t R, const hp_params &p)
         off += align256(bytes);
         return at;
     };
-    const size_t RS = (size_t)R * (size_t)p.n_samples;
+    const size_t R = (size_t)chunk_rays;
+    const size_t RS = R * (size_t)p.n_samples;
     L.partial = take(hp::backward_partial_bytes());
-    L.n_sel = take((size_t)R * 4);
-    L.primary = take((size_t)R * 4);
-    L.n_nbr = take((size_t)R * 4);
-    L.flags = take((size_t)R * 4);
+    L.n_sel = take(R * 4);
+    L.primary = take(R * 4);
+    L.n_nbr = take(R * 4);
+    L.flags = take(R * 4);
     L.t = take(RS * 4);
     L.knn_idx = take(RS * (size_t)p.K * 4);
     L.knn_dist = take(RS * (size_t)p.K * 4);
     L.bytes = off;
     return L;
+}
+
+// Rays per recompute chunk that ws_bytes holds (0: not even one), at most R.
+static int64_t bwd_chunk_rays(size_t ws_bytes, int64_t R, const hp_params &p)
+{
+    if (ws_bytes < bwd_ws_layout(1, p).bytes) return 0;
+    const size_t per_ray = 16 + (size_t)p.n_samples * (4 + 8 * (size_t)p.K);
+    const size_t fixed = align256(hp::backward_partial_bytes()) + 7 * 256;
+    int64_t n = ws_bytes > fixed ? (int64_t)((ws_bytes - fixed) / per_ray) : 1;
+    const int64_t cap = R > 0 ? R : 1;
+    if (n > cap) n = cap;
+    if (n < 1) n = 1;
+    while (n > 1 && bwd_ws_layout(n, p).bytes > ws_bytes) --n;
+    return n;
 }
 
 static hp_status check_backward_args(const float *feat, int32_t C, const hp_mlp *mlp,
@@ -465,11 +511,10 @@ static hp_status check_backward_args(const float *feat, int32_t C, const hp_mlp 
     return HP_OK;
 }
 
-static hp_status run_backward(const int32_t *n_sel, const float *t, const int32_t *knn_idx,
-                              const float *knn_dist, int64_t R, const float *feat,
-                              const hp_mlp *mlp, int32_t precision, const hp_params *p,
-                              const float *grad_rgb, float *grad_feat, hp_mlp *grad_mlp,
-                              float *partial, hipStream_t stream)
+static hp::BwdArgs backward_args(const int32_t *n_sel, const float *t, const int32_t *knn_idx,
+                                  const float *knn_dist, int64_t R, const float *feat,
+                                  const hp_mlp *mlp, const hp_params *p, const float *grad_rgb,
+                                  float *grad_feat, float *partial)
 {
     hp::BwdArgs A;
     A.n_sel = n_sel;
@@ -488,9 +533,46 @@ static hp_status run_backward(const int32_t *n_sel, const float *t, const int32_
     A.grad_rgb = grad_rgb;
     A.grad_feat = grad_feat;
     A.partial = partial;
-    const hp::MlpGrad gm{grad_mlp->W1, grad_mlp->b1, grad_mlp->W2,
-                         grad_mlp->b2, grad_mlp->W3, grad_mlp->b3};
-    const hipError_t e = hp::launch_backward(A, precision, gm, stream);
+    return A;
+}
+
+static hp::MlpGrad mlp_grad(const hp_mlp *g)
+{
+    return hp::MlpGrad{g->W1, g->b1, g->W2, g->b2, g->W3, g->b3};
+}
+
+// Recompute the samples of the table's rays chunk by chunk into the ring at
+// `base` (layout L, chunk_rays rays) and accumulate each chunk's gradient.
+static hp_status backward_recompute(const hp::SearchCtx &c0, const hp_params *p, const float *feat,
+                                    const hp_mlp *mlp, int32_t precision, const float *grad_rgb,
+                                    float *grad_feat, hp_mlp *grad_mlp, char *base,
+                                    const BwdWsLayout &L, int64_t chunk_rays, hipStream_t stream)
+{
+    float *partial = reinterpret_cast<float *>(base + L.partial);
+    hipError_t e = hp::backward_zero(partial, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    hp::SampleOut o{reinterpret_cast<int32_t *>(base + L.n_sel),
+                    reinterpret_cast<int32_t *>(base + L.primary),
+                    reinterpret_cast<int32_t *>(base + L.n_nbr),
+                    reinterpret_cast<uint32_t *>(base + L.flags),
+                    reinterpret_cast<float *>(base + L.t),
+                    reinterpret_cast<int32_t *>(base + L.knn_idx),
+                    reinterpret_cast<float *>(base + L.knn_dist),
+                    nullptr,
+                    nullptr};
+    const int kt = knn_template(p->K);
+    for (int64_t r0 = 0; r0 < c0.n_rays; r0 += chunk_rays) {
+        hp::SearchCtx c = c0;
+        c.ray0 = r0;
+        c.n_rays = (c0.n_rays - r0) < chunk_rays ? c0.n_rays - r0 : chunk_rays;
+        e = hp::launch_search_sample(c, o, kt, stream);
+        if (e != hipSuccess) return hip_fail(e);
+        const hp::BwdArgs A = backward_args(o.n_sel, o.t, o.knn_idx, o.knn_dist, c.n_rays, feat, mlp,
+                                            p, grad_rgb + 3 * r0, grad_feat, partial);
+        e = hp::backward_accumulate(A, precision, stream);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    e = hp::backward_reduce(partial, mlp_grad(grad_mlp), stream);
     return e == hipSuccess ? HP_OK : hip_fail(e);
 }
 
@@ -500,7 +582,9 @@ size_t hp_backward_workspace(const hp_table *tab, const hp_params *p, hp_status 
 {
     const hp_status st = (tab && p && valid_params(*p) && tab->n_rays >= 0) ? HP_OK : HP_E_INVALID;
     if (status) *status = st;
-    return st == HP_OK ? bwd_ws_layout(tab->n_rays, *p).bytes : 0;
+    if (st != HP_OK) return 0;
+    int64_t n = tab->n_rays < BWD_DEFAULT_CHUNK_RAYS ? tab->n_rays : BWD_DEFAULT_CHUNK_RAYS;
+    return bwd_ws_layout(n > 0 ? n : 1, *p).bytes;
 }
 
 size_t hp_backward_samples_workspace(const hp_params *p, hp_status *status)
@@ -520,24 +604,11 @@ hp_status hp_render_backward(const hp_table *tab, const hp_camera *cams, int32_t
     if (st != HP_OK) return st;
     st = check_backward_args(feat, C, mlp, precision, p, grad_rgb, grad_feat, grad_mlp);
     if (st != HP_OK) return st;
-    const BwdWsLayout L = bwd_ws_layout(tab->n_rays, *p);
-    if (!ws || ws_bytes < L.bytes) return HP_E_WORKSPACE;
-    char *base = static_cast<char *>(ws);
-    // recompute the samples with the forward search kernel
-    hp::SampleOut o{reinterpret_cast<int32_t *>(base + L.n_sel),
-                    reinterpret_cast<int32_t *>(base + L.primary),
-                    reinterpret_cast<int32_t *>(base + L.n_nbr),
-                    reinterpret_cast<uint32_t *>(base + L.flags),
-                    reinterpret_cast<float *>(base + L.t),
-                    reinterpret_cast<int32_t *>(base + L.knn_idx),
-                    reinterpret_cast<float *>(base + L.knn_dist),
-                    nullptr,
-                    nullptr};
-    const hipError_t e = hp::launch_search_sample(c, o, knn_template(p->K), (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e);
-    return run_backward(o.n_sel, o.t, o.knn_idx, o.knn_dist, tab->n_rays, feat, mlp, precision, p,
-                        grad_rgb, grad_feat, grad_mlp, reinterpret_cast<float *>(base + L.partial),
-                        (hipStream_t)stream);
+    const int64_t chunk = bwd_chunk_rays(ws ? ws_bytes : 0, tab->n_rays, *p);
+    if (!ws || chunk < 1) return HP_E_WORKSPACE;
+    return backward_recompute(c, p, feat, mlp, precision, grad_rgb, grad_feat, grad_mlp,
+                              static_cast<char *>(ws), bwd_ws_layout(chunk, *p), chunk,
+                              (hipStream_t)stream);
 }
 
 hp_status hp_render_backward_samples(const hp_samples *smp, int64_t R, const float *feat,
@@ -551,8 +622,15 @@ hp_status hp_render_backward_samples(const hp_samples *smp, int64_t R, const flo
     if (R >= ((int64_t)1 << 31)) return HP_E_CAPACITY;
     if (R > 0 && (!smp->n_sel || !smp->t || !smp->knn_idx || !smp->knn_dist)) return HP_E_INVALID;
     if (!ws || ws_bytes < align256(hp::backward_partial_bytes())) return HP_E_WORKSPACE;
-    return run_backward(smp->n_sel, smp->t, smp->knn_idx, smp->knn_dist, R, feat, mlp, precision, p,
-                        grad_rgb, grad_feat, grad_mlp, static_cast<float *>(ws), (hipStream_t)stream);
+    float *partial = static_cast<float *>(ws);
+    hipError_t e = hp::backward_zero(partial, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    const hp::BwdArgs A = backward_args(smp->n_sel, smp->t, smp->knn_idx, smp->knn_dist, R, feat, mlp,
+                                        p, grad_rgb, grad_feat, partial);
+    e = hp::backward_accumulate(A, precision, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    e = hp::backward_reduce(partial, mlp_grad(grad_mlp), (hipStream_t)stream);
+    return e == hipSuccess ? HP_OK : hip_fail(e);
 }
 
 }  // extern "C"

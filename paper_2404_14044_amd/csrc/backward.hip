@@ -182,7 +182,8 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
             g1 = A.grad_rgb[3 * ray + 1];
             g2 = A.grad_rgb[3 * ray + 2];
             // a ray without incoming gradient contributes nothing
-            if (g0 != 0.0f || g1 != 0.0f || g2 != 0.0f) ns = A.n_sel[ray];
+            // (a count beyond the sample cap would index past the ray's rows)
+            if (g0 != 0.0f || g1 != 0.0f || g2 != 0.0f) ns = min(max(A.n_sel[ray], 0), A.S);
         }
         const int inc = wave_incl_scan_i32(ns);
         sh.pre[l] = inc - ns;
@@ -636,33 +637,47 @@ __global__ void __launch_bounds__(RED_P * RED_G) k_reduce_partials(const float *
 
 size_t backward_partial_bytes() { return (size_t)BWD_MAX_BLOCKS * SSTRIDE * sizeof(float); }
 
+int backward_slices()
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // one workgroup fills a CU's LDS: a persistent grid of one per CU
+    return cus < BWD_MAX_BLOCKS ? (cus > 0 ? cus : 1) : BWD_MAX_BLOCKS;
+}
+
 int backward_rays_per_wave(int S)
 {
     const int r = BWD_CHUNK / (S > 0 ? S : 1);
     return r > WAVE ? WAVE : r;
 }
 
-hipError_t launch_backward(const BwdArgs &A, int precision, const MlpGrad &gm, hipStream_t s)
+hipError_t backward_zero(float *partial, hipStream_t s)
+{
+    const int64_t nzero = (int64_t)backward_slices() * SSTRIDE;
+    k_zero_f32<<<dim3((unsigned)((nzero + 255) / 256)), 256, 0, s>>>(partial, nzero);
+    return hipGetLastError();
+}
+
+hipError_t backward_accumulate(const BwdArgs &A, int precision, hipStream_t s)
 {
     if (A.n_rays == 0) return hipSuccess;
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess)
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int64_t chunks = (A.n_rays + A.rpw - 1) / A.rpw;
     int64_t nblk = (chunks + BWD_WAVES - 1) / BWD_WAVES;
-    // one workgroup fills a CU's LDS: a persistent grid of one per CU
-    if (nblk > cus) nblk = cus;
-    if (nblk > BWD_MAX_BLOCKS) nblk = BWD_MAX_BLOCKS;
+    const int64_t nslice = backward_slices();
+    if (nblk > nslice) nblk = nslice;
     if (nblk < 1) nblk = 1;
-    const int64_t nslice = nblk;
-    const int64_t nzero = nslice * SSTRIDE;
-    k_zero_f32<<<dim3((unsigned)((nzero + 255) / 256)), 256, 0, s>>>(A.partial, nzero);
     if (precision == HP_BF16)
         k_render_backward<HP_BF16><<<dim3((unsigned)nblk), dim3(WAVE * BWD_WAVES), 0, s>>>(A);
     else
         k_render_backward<HP_FP32><<<dim3((unsigned)nblk), dim3(WAVE * BWD_WAVES), 0, s>>>(A);
+    return hipGetLastError();
+}
+
+hipError_t backward_reduce(const float *partial, const MlpGrad &gm, hipStream_t s)
+{
     k_reduce_partials<<<(NPAR + RED_P - 1) / RED_P, RED_P * RED_G, 0, s>>>(
-        A.partial, (int)nslice, gm.W1, gm.b1, gm.W2, gm.b2, gm.W3, gm.b3);
+        partial, backward_slices(), gm.W1, gm.b1, gm.W2, gm.b2, gm.W3, gm.b3);
     return hipGetLastError();
 }
 

@@ -30,8 +30,16 @@ struct BwdArgs {
     float *partial;  // per-workgroup decoder-gradient slices
 };
 
+// Decoder-gradient slices: one per workgroup of the backward grid, which is
+// at most backward_slices() workgroups for any number of rays.
 size_t backward_partial_bytes();
+int backward_slices();
 int backward_rays_per_wave(int S);
-hipError_t launch_backward(const BwdArgs &A, int precision, const MlpGrad &gm, hipStream_t s);
+// The three steps of a gradient: zero the slices, accumulate any number of
+// ray chunks into them (and into the feature gradient), then add the slices
+// in a fixed order to the caller's decoder gradients.
+hipError_t backward_zero(float *partial, hipStream_t s);
+hipError_t backward_accumulate(const BwdArgs &A, int precision, hipStream_t s);
+hipError_t backward_reduce(const float *partial, const MlpGrad &gm, hipStream_t s);
 
 }  // namespace hp

@@ -52,7 +52,8 @@ struct SearchCtx {
     const uint32_t *cell_zmin;
     const ViewK *views;
     int32_t n_views, layout;
-    int64_t n_points, n_rays;
+    int64_t n_points;
+    int64_t ray0, n_rays;   // rays ray0 .. ray0 + n_rays - 1 of the table's views
     float radius, inv_tref, t_near, t_far, gamma, inv_beta2, eps_w;
     int32_t K, S, M;
     int32_t chunk, blocks;  // rays per work chunk, persistent grid (0 = default)
@@ -414,7 +415,10 @@ __device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, RayGeom 
 {
     const int l = lane_id();
     const int64_t n_chunks = (c.n_rays + c.chunk - 1) / c.chunk;
-    const int64_t band = (BAND_RAYS + c.chunk - 1) / c.chunk;  // chunks per band
+    // chunks per band (fewer when the launch has fewer than eight full bands,
+    // so that every XCD gets a share)
+    int64_t band = (BAND_RAYS + c.chunk - 1) / c.chunk;
+    if (band * 8 > n_chunks) band = (n_chunks + 7) / 8 > 0 ? (n_chunks + 7) / 8 : 1;
     const int xcd = blockIdx.x & 7;
     const int64_t slot = blockIdx.x >> 3, n_slots = gridDim.x >> 3;
     const int64_t n_bands = (n_chunks + band - 1) / band;
@@ -428,6 +432,7 @@ __device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, RayGeom 
         if (ch >= n_chunks) return;
         r0 = ch * c.chunk;
         n = (int)min((int64_t)c.chunk, c.n_rays - r0);
+        r0 += c.ray0;
     };
     // four chunks per set-up pass (the chunks themselves stay small, for balance)
     for (int64_t li = slot; li < my_chunks; li += 4 * n_slots) {

@@ -86,7 +86,9 @@ __device__ __forceinline__ void render_body(const RenderArgs &a)
     const int nr = (a.n_rays - ray0) < RPW ? (int)(a.n_rays - ray0) : RPW;
 
     // prefix of sample counts over the chunk
-    const int ns = (l < nr) ? a.n_sel[ray0 + l] : 0;
+    // (a count beyond the sample cap would index past the ray's rows and the
+    // chunk's LDS)
+    const int ns = (l < nr) ? min(max(a.n_sel[ray0 + l], 0), a.S) : 0;
     const int inc = wave_incl_scan_i32(ns);
     if (l < RPW) sh_pre[l] = inc - ns;
     const int total = readlane_i32(inc, WAVE - 1);

@@ -10,7 +10,8 @@ __device__ __forceinline__ void search_sample_body(const SearchCtx &c, const Sam
 {
     __shared__ SearchLds sh;
     const int l = lane_id();
-    for_each_ray_banded(c, sh.rs, [&](int64_t ray, const RayGeom &g) {
+    for_each_ray_banded(c, sh.rs, [&](int64_t gray, const RayGeom &g) {
+        const int64_t ray = gray - c.ray0;  // row of the outputs
         uint64_t top;
         int count;
         search_neighbours(c, g, sh, top, count);

@@ -70,7 +70,7 @@ class HPTable(ctypes.Structure):
                 ("offsets", ctypes.c_void_p), ("pts", ctypes.c_void_p),
                 ("perm", ctypes.c_void_p), ("slot_of", ctypes.c_void_p),
                 ("bucket_z", ctypes.c_void_p), ("cell_zmin", ctypes.c_void_p),
-                ("n_cells", ctypes.c_int64),
+                ("n_cells", ctypes.c_int64), ("build_key", ctypes.c_uint64),
                 ("scratch", ctypes.c_void_p), ("views", HPViewInfo * HP_MAX_VIEWS)]
 
 
@@ -411,9 +411,10 @@ def render_backward(table: Table, feat: torch.Tensor, mlp: Dict[str, torch.Tenso
         grad_feat = torch.zeros_like(feat)
     if grad_mlp is None:
         grad_mlp = {k: torch.zeros_like(v) for k, v in mlp.items()}
-    need = backward_workspace(table, params)
-    if ws is None or ws.numel() < need:
-        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    if ws is None:
+        # (a caller's workspace is used as given: any size that holds one ray's
+        # samples works, a smaller one just means more recompute chunks)
+        ws = torch.empty(backward_workspace(table, params), dtype=torch.uint8, device=dev)
     arr, p = _cams_array(table.cams), make_params(params)
     m, gm = mlp_struct(mlp), mlp_struct(grad_mlp)
     _check(lib().hp_render_backward(ctypes.byref(table.tab), arr, len(table.cams),

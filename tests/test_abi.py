@@ -152,20 +152,26 @@ def test_backward_from_samples_rejects_bad_arguments_without_launching():
     assert L.hp_render_backward_samples(*args(smp, -1, 32, 0, need)) == hp.HP_E_INVALID
 
 
-def test_backward_workspace_holds_the_recomputed_samples():
+def test_backward_workspace_holds_one_chunk_of_recomputed_samples():
+    """The recomputing backward's workspace holds the gradient slices and the
+    samples of min(R, 65536) rays: it stops growing with the rays."""
     sc = scenes.sphere_plane(n_sphere=10, n_plane=10)
     part = hp.backward_samples_workspace(sc.params)
     st = ctypes.c_int32()
     tab = hp.HPTable()
     p = sc.params
-    for R in (0, 1, 4096):
+    S, K = p.n_samples, p.K
+    sizes = {}
+    for R in (0, 1, 4096, 65536, 640000, 10_000_000):
         tab.n_rays = R
         n = hp.lib().hp_backward_workspace(ctypes.byref(tab), ctypes.byref(hp.make_params(p)),
                                            ctypes.byref(st))
         assert st.value == hp.HP_OK
-        S, K = p.n_samples, p.K
-        assert n >= part + R * (4 * 4 + S * 4 + 2 * S * K * 4)
-        assert n <= part + R * (4 * 4 + S * 4 + 2 * S * K * 4) + 8 * 256
+        rays = max(1, min(R, 65536))
+        assert n >= part + rays * (4 * 4 + S * 4 + 2 * S * K * 4)
+        assert n <= part + rays * (4 * 4 + S * 4 + 2 * S * K * 4) + 8 * 256
+        sizes[R] = n
+    assert sizes[65536] == sizes[640000] == sizes[10_000_000]
 
 
 def test_radius_modes_validated_and_bounded_like_the_oracle():
@@ -232,3 +238,36 @@ def test_exp32_eval_rejects_bad_arguments():
     assert L.hp_exp32_eval(None, None, -1, None) == hp.HP_E_INVALID
     assert L.hp_exp32_eval(None, None, 4, None) == hp.HP_E_INVALID
     assert L.hp_exp32_eval(None, None, 0, None) == hp.HP_OK
+
+
+def _fake_table(cam, params):
+    """A table struct whose geometry matches (cam, params) but whose build key
+    is not the one hp_build_table would have written."""
+    g, d = hp.view_bounds(cam, params)
+    tab = hp.HPTable()
+    tab.n_views, tab.layout, tab.n_points = 1, int(params.layout), 100
+    tab.n_buckets = (cam.W + 2 * g) * (cam.H + 2 * g)
+    tab.n_rays = cam.W * cam.H
+    for name in ("offsets", "pts", "perm", "slot_of", "bucket_z", "cell_zmin", "scratch"):
+        setattr(tab, name, 0x1000)
+    v = tab.views[0]
+    v.W, v.H, v.g, v.Wg, v.Hg = cam.W, cam.H, g, cam.W + 2 * g, cam.H + 2 * g
+    tab.build_key = 12345
+    return tab
+
+
+def test_calls_on_a_table_check_its_build_key():
+    """A table records a hash of the cameras and of the parameters its bounds
+    depend on; a search with other values is rejected before any launch."""
+    sc = scenes.sphere_plane(n_sphere=10, n_plane=10)
+    L = hp.lib()
+    arr, pp = hp._cams_array(sc.cams), hp.make_params(sc.params)
+    tab = _fake_table(sc.cams[0], sc.params)
+    smp = hp.HPSamples()
+    for name, _ in hp.HPSamples._fields_[:7]:
+        setattr(smp, name, 0x1000)
+    assert L.hp_search_sample(ctypes.byref(tab), arr, 1, ctypes.byref(pp), ctypes.byref(smp),
+                              None) == hp.HP_E_INVALID
+    fake = ctypes.c_void_p(0x1000)
+    assert L.hp_knp_blend(ctypes.byref(tab), arr, 1, ctypes.byref(pp), 8, fake, fake, None, None,
+                          None, None) == hp.HP_E_INVALID

@@ -328,3 +328,34 @@ def test_backward_from_kept_samples_matches_recompute(prec_name):
     for k in KEYS:
         for b in (gm_b[k], m2[k].grad):
             assert float((gm_a[k] - b).abs().max() / gm_a[k].abs().max().clamp_min(1e-30)) < 1e-5, k
+
+
+@pytest.mark.parametrize("prec_name", ["fp32", "bf16"])
+def test_backward_in_small_chunks_matches_one_chunk(prec_name):
+    """A workspace that holds the samples of about 1000 rays makes the
+    recomputing backward run 37 search + gradient chunks (their boundaries
+    cut through views); the gradient equals the one-chunk result up to the
+    order of float atomics."""
+    import torch
+    from paper_2404_14044_amd import hashpoint as hp
+    sc = _multiview(n=100_000, res=96)
+    prec = hp.HP_FP32 if prec_name == "fp32" else hp.HP_BF16
+    dev = torch.device("cuda:0")
+    xyz = torch.from_numpy(sc.xyz).to(dev)
+    feat = torch.from_numpy(sc.feat).to(dev)
+    mlp = hp.to_device_mlp(sc.mlp, dev)
+    tab = hp.build_table(xyz, sc.cams, sc.params)
+    assert tab.n_rays == 4 * 96 * 96
+    g = torch.randn(tab.n_rays, 3, device=dev, generator=torch.Generator(device=dev).manual_seed(5))
+    gf_a, gm_a = hp.render_backward(tab, feat, mlp, sc.params, prec, g)
+    p = sc.params
+    per_ray = 16 + p.n_samples * (4 + 8 * p.K)
+    small = hp.backward_samples_workspace(p) + 1000 * per_ray + 8 * 256
+    assert small < hp.backward_workspace(tab, p)
+    ws = torch.empty(small, dtype=torch.uint8, device=dev)
+    gf_b, gm_b = hp.render_backward(tab, feat, mlp, p, prec, g, ws=ws)
+    torch.cuda.synchronize()
+    assert gf_a.abs().max() > 0
+    assert float((gf_a - gf_b).norm() / gf_a.norm()) < 1e-6
+    for k in KEYS:
+        assert float((gm_a[k] - gm_b[k]).abs().max() / gm_a[k].abs().max().clamp_min(1e-30)) < 1e-5, k

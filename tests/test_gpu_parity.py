@@ -291,3 +291,21 @@ def test_multiview_table_and_search():
         pix = sample_pixels(cam, 1024, seed=30 + v)
         ex = compare_exact(sc, out["samples"], pix, view=v, ray_base=info.ray_base)
         assert (ex["n_sel"] > 0).sum() > 50
+
+
+def test_search_with_other_bound_parameters_is_rejected(sphere_plane):
+    """A change of radius that keeps the guard band would search a window too
+    small for the new radius: the table's build key rejects it; parameters the
+    table does not depend on may change."""
+    import torch
+    from paper_2404_14044_amd import hashpoint as hp
+    sc = sphere_plane
+    xyz = torch.from_numpy(sc.xyz).to("cuda:0")
+    tab = hp.build_table(xyz, sc.cams, sc.params)
+    p2 = sc.params.replace(radius=sc.params.radius * 1.01)
+    assert hp.view_bounds(sc.cams[0], p2)[0] == hp.view_bounds(sc.cams[0], sc.params)[0]
+    with pytest.raises(hp.HashPointError):
+        hp.search_sample(tab, p2)
+    smp = hp.search_sample(tab, sc.params.replace(K=4, gamma=0.5, n_samples=4))
+    torch.cuda.synchronize()
+    assert int(smp["n_sel"].max().item()) <= 4
