@@ -76,6 +76,8 @@ enum {
 #define HP_MAX_MCAP 64
 #define HP_FEAT_DIM 32
 #define HP_HIDDEN 64
+/* device scratch of hp_render_backward_noalloc, per GPU (32 MiB) */
+#define HP_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
 
 /* Pinhole camera (host).  OpenCV axes: +x right, +y down, +z forward.
  * Camera-space position of world point p is R (p - C); pixel (u, v) spans
@@ -347,6 +349,26 @@ hp_status hp_render_backward_samples(const hp_samples *smp, int64_t R, const flo
                                      int32_t C, const hp_mlp *mlp, int32_t precision,
                                      const hp_params *p, const float *grad_rgb, float *grad_feat,
                                      hp_mlp *grad_mlp, void *ws, size_t ws_bytes, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * recomputing gradient of hp_render_backward, with the same arguments and
+ * results but no workspace.  Its decoder-gradient slices and recompute ring
+ * live in a device array of HP_NOALLOC_SCRATCH_BYTES that the library holds
+ * on each GPU it runs on until the process ends; the rays are recomputed in
+ * chunks of as many as the ring holds after the slices (about 24,000 rays at
+ * K = 8, S = 16), so any number of rays is accepted.  It calls no hipMalloc,
+ * hipFree or allocating library routine.  Calls on one GPU share its array:
+ * calls that overlap on one GPU (several streams or threads at once) race
+ * and must be serialised by the caller.
+ * Errors: as hp_render_backward, minus HP_E_WORKSPACE; HP_E_CAPACITY if the
+ *      slices and one ray's samples do not fit the array (not reachable
+ *      within HP_MAX_K and HP_MAX_SAMPLES); HP_E_HIP if the array's address
+ *      cannot be obtained. */
+hp_status hp_render_backward_noalloc(const hp_table *tab, const hp_camera *cams, int32_t n_views,
+                                     const float *feat, int32_t C, const hp_mlp *mlp,
+                                     int32_t precision, const hp_params *p, const float *grad_rgb,
+                                     float *grad_feat, hp_mlp *grad_mlp, void *stream);
 
 /* Evaluates on the device, element by element, the binary32 exponential
  * that decides the candidate confidences alpha = gamma exp(-d^2 / beta^2)

@@ -1,7 +1,10 @@
 // C ABI of the HashPoint library: host-side validation, workspace layout and
-// kernel launches.  No allocation, no global state.
+// kernel launches.  No allocation; the only global state is the per-device
+// address of the allocation-free backward's scratch array.
 #include <math.h>
 #include <string.h>
+
+#include <mutex>
 
 #include "hp_backward.hpp"
 #include "hp_device.hpp"
@@ -631,6 +634,70 @@ hp_status hp_render_backward_samples(const hp_samples *smp, int64_t R, const flo
     if (e != hipSuccess) return hip_fail(e);
     e = hp::backward_reduce(partial, mlp_grad(grad_mlp), (hipStream_t)stream);
     return e == hipSuccess ? HP_OK : hip_fail(e);
+}
+
+}  // extern "C"
+
+// Allocation-free backward.  Its decoder-gradient slices and recompute ring
+// live in `scratch`, a device array that the code object brings with it (each
+// GPU that loads the library holds its own copy until the process ends).  In
+// host code the array's name stands for a host-side shadow, not a device
+// address, so the kernels only ever receive the address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device and kept.  Every call on a GPU reuses that GPU's array: the slices
+// are cleared by a fill kernel at the start of each call, the ring is fully
+// rewritten by each chunk's search; calls that overlap on one GPU race.
+static __device__ __align__(256) unsigned char scratch[HP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[SCRATCH_MAX_DEVICES];
+
+// Device address of the current device's scratch array (looked up on the
+// first call on each device).
+hipError_t scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+hp_status hp_render_backward_noalloc(const hp_table *tab, const hp_camera *cams, int32_t n_views,
+                                     const float *feat, int32_t C, const hp_mlp *mlp,
+                                     int32_t precision, const hp_params *p, const float *grad_rgb,
+                                     float *grad_feat, hp_mlp *grad_mlp, void *stream)
+{
+    hp::SearchCtx c;
+    hp_status st = make_ctx(tab, cams, n_views, p, c);
+    if (st != HP_OK) return st;
+    st = check_backward_args(feat, C, mlp, precision, p, grad_rgb, grad_feat, grad_mlp);
+    if (st != HP_OK) return st;
+    // the slices and the samples of at least one ray must fit the array
+    const int64_t chunk = bwd_chunk_rays(HP_NOALLOC_SCRATCH_BYTES, tab->n_rays, *p);
+    if (chunk < 1) return HP_E_CAPACITY;
+    void *base = nullptr;
+    const hipError_t e = scratch_address(&base);
+    if (e != hipSuccess) return hip_fail(e);
+    return backward_recompute(c, p, feat, mlp, precision, grad_rgb, grad_feat, grad_mlp,
+                              static_cast<char *>(base), bwd_ws_layout(chunk, *p), chunk,
+                              (hipStream_t)stream);
 }
 
 }  // extern "C"

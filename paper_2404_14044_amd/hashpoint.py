@@ -28,6 +28,7 @@ EXPORTED = ["hp_table_workspace", "hp_view_bounds", "hp_paper_kernel_size", "hp_
             "hp_render", "hp_backward_workspace", "hp_render_backward",
             "hp_backward_samples_workspace", "hp_render_backward_samples", "hp_knp_blend",
             "hp_search_render", "hp_samples_shape", "hp_exp32_eval",
+            "hp_render_backward_noalloc",
             "hp_status_str",
             "hp_last_hip_error"]
 
@@ -124,6 +125,8 @@ def lib():
         L.hp_backward_samples_workspace.argtypes = [P, P]
         L.hp_render_backward_samples.restype = i32
         L.hp_render_backward_samples.argtypes = [P, i64, P, i32, P, i32, P, P, P, P, P, ctypes.c_size_t, P]
+        L.hp_render_backward_noalloc.restype = i32
+        L.hp_render_backward_noalloc.argtypes = [P, P, i32, P, i32, P, i32, P, P, P, P, P]
         L.hp_samples_shape.restype = i32
         L.hp_samples_shape.argtypes = [i64, P, P]
         L.hp_exp32_eval.restype = i32
@@ -424,6 +427,25 @@ def render_backward(table: Table, feat: torch.Tensor, mlp: Dict[str, torch.Tenso
                                     _dev(grad_feat, torch.float32, "grad_feat"), ctypes.byref(gm),
                                     ws.data_ptr(), ws.numel(), _stream(stream)),
            "hp_render_backward")
+    return grad_feat, grad_mlp
+
+
+def render_backward_noalloc(table: Table, feat: torch.Tensor, mlp: Dict[str, torch.Tensor], params,
+                            precision: int, grad_rgb: torch.Tensor,
+                            grad_feat: torch.Tensor, grad_mlp: Dict[str, torch.Tensor], stream=None):
+    """render_backward without a workspace: the library's per-GPU scratch array
+    holds the gradient slices and the recompute ring, and the call allocates
+    nothing (grad_feat / grad_mlp are given by the caller and added to)."""
+    params = params or table.params
+    arr, p = _cams_array(table.cams), make_params(params)
+    m, gm = mlp_struct(mlp), mlp_struct(grad_mlp)
+    _check(lib().hp_render_backward_noalloc(ctypes.byref(table.tab), arr, len(table.cams),
+                                            _dev(feat, torch.float32, "feat"), int(feat.shape[1]),
+                                            ctypes.byref(m), int(precision), ctypes.byref(p),
+                                            _dev(grad_rgb, torch.float32, "grad_rgb"),
+                                            _dev(grad_feat, torch.float32, "grad_feat"),
+                                            ctypes.byref(gm), _stream(stream)),
+           "hp_render_backward_noalloc")
     return grad_feat, grad_mlp
 
 

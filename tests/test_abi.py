@@ -271,3 +271,33 @@ def test_calls_on_a_table_check_its_build_key():
     fake = ctypes.c_void_p(0x1000)
     assert L.hp_knp_blend(ctypes.byref(tab), arr, 1, ctypes.byref(pp), 8, fake, fake, None, None,
                           None, None) == hp.HP_E_INVALID
+    mlp = hp.HPMlp()
+    for name, _ in hp.HPMlp._fields_:
+        setattr(mlp, name, 0x1000)
+    assert L.hp_render_backward_noalloc(ctypes.byref(tab), arr, 1, fake, 32, ctypes.byref(mlp), 0,
+                                        ctypes.byref(pp), fake, fake, ctypes.byref(mlp),
+                                        None) == hp.HP_E_INVALID
+
+
+def test_backward_noalloc_rejects_bad_arguments_without_launching():
+    """The allocation-free backward validates like hp_render_backward (no
+    workspace to check) before it touches a device or its scratch array."""
+    sc = scenes.sphere_plane(n_sphere=10, n_plane=10)
+    L = hp.lib()
+    arr, pp = hp._cams_array(sc.cams), hp.make_params(sc.params)
+    fake = ctypes.c_void_p(0x1000)
+    mlp = hp.HPMlp()
+    for name, _ in hp.HPMlp._fields_:
+        setattr(mlp, name, 0x1000)
+    f = L.hp_render_backward_noalloc
+    args = lambda tab, C, prec, m: (tab, arr, 1, fake, C, m, prec, ctypes.byref(pp), fake, fake,
+                                    m, None)
+    tab = _fake_table(sc.cams[0], sc.params)
+    assert f(*args(None, 32, 0, ctypes.byref(mlp))) == hp.HP_E_INVALID
+    assert f(*args(ctypes.byref(tab), 32, 0, None)) == hp.HP_E_INVALID
+    # a table whose build key does not match is rejected before the others
+    assert f(*args(ctypes.byref(tab), 16, 0, ctypes.byref(mlp))) == hp.HP_E_INVALID
+    bad = hp.make_params(sc.params)
+    bad.K = 0
+    assert f(ctypes.byref(tab), arr, 1, fake, 32, ctypes.byref(mlp), 0, ctypes.byref(bad), fake,
+             fake, ctypes.byref(mlp), None) == hp.HP_E_INVALID
