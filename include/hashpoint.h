@@ -307,7 +307,7 @@ hp_status hp_knp_blend(const hp_table *tab, const hp_camera *cams, int32_t n_vie
 /* Workspace bytes hp_render_backward needs for this table and these
  * parameters (host only): per-workgroup decoder-gradient slices plus a ring
  * for the recomputed samples (as hp_samples, without the optional neighbour
- * lists) of one chunk of min(tab->n_rays, 65536) rays.  The workspace does not
+ * lists) of one chunk of min(tab->n_rays, 262144) rays.  The workspace does not
  * grow with the rays beyond that; hp_render_backward accepts any workspace
  * that holds the slices and at least one ray, and recomputes the rays in
  * chunks of as many as it holds. */

@@ -455,7 +455,7 @@ hp_status hp_render(const hp_samples *smp, int64_t R, const float *feat, int32_t
 // holds (at most all of them), so the workspace need not grow with the rays.
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-constexpr int64_t BWD_DEFAULT_CHUNK_RAYS = 65536;
+constexpr int64_t BWD_DEFAULT_CHUNK_RAYS = 262144;
 
 struct BwdWsLayout {
     size_t partial, n_sel, primary, n_nbr, flags, t, knn_idx, knn_dist, bytes;
@@ -536,6 +536,7 @@ static hp::BwdArgs backward_args(const int32_t *n_sel, const float *t, const int
     A.grad_rgb = grad_rgb;
     A.grad_feat = grad_feat;
     A.partial = partial;
+    A.queue = nullptr;  // (set by backward_accumulate)
     return A;
 }
 

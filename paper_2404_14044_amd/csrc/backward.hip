@@ -169,9 +169,16 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
     float gW3[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     float gb1 = 0.0f, gb2 = 0.0f, gb3 = 0.0f;
 
+    // chunks of consecutive rays are taken from a work counter, one per
+    // wave at a time: a chunk's cost follows its sample count, which varies
+    // from none (background) to rpw * S, so a fixed deal would leave the
+    // launch waiting on the waves that drew the busiest chunks
     const int64_t n_chunks = (A.n_rays + A.rpw - 1) / A.rpw;
-    for (int64_t ch = (int64_t)blockIdx.x * BWD_WAVES + wave; ch < n_chunks;
-         ch += (int64_t)gridDim.x * BWD_WAVES) {
+    for (;;) {
+        int taken = 0;
+        if (l == 0) taken = atomicAdd(A.queue, 1);
+        const int64_t ch = __builtin_amdgcn_readfirstlane(taken);
+        if (ch >= n_chunks) break;
         const int64_t ray0 = ch * A.rpw;
         const int nr = (A.n_rays - ray0) < A.rpw ? (int)(A.n_rays - ray0) : A.rpw;
         float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
@@ -635,7 +642,13 @@ __global__ void __launch_bounds__(RED_P * RED_G) k_reduce_partials(const float *
     dst[j] += t;
 }
 
-size_t backward_partial_bytes() { return (size_t)BWD_MAX_BLOCKS * SSTRIDE * sizeof(float); }
+// the slices, then one 256-byte line for the work counter
+size_t backward_partial_bytes() { return (size_t)BWD_MAX_BLOCKS * SSTRIDE * sizeof(float) + 256; }
+
+static int32_t *queue_of(float *partial)
+{
+    return reinterpret_cast<int32_t *>(partial + (size_t)BWD_MAX_BLOCKS * SSTRIDE);
+}
 
 int backward_slices()
 {
@@ -659,9 +672,13 @@ hipError_t backward_zero(float *partial, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t backward_accumulate(const BwdArgs &A, int precision, hipStream_t s)
+hipError_t backward_accumulate(const BwdArgs &args, int precision, hipStream_t s)
 {
-    if (A.n_rays == 0) return hipSuccess;
+    if (args.n_rays == 0) return hipSuccess;
+    BwdArgs A = args;
+    A.queue = queue_of(A.partial);
+    // (a fill kernel, not a memset: callers may capture this in a graph)
+    k_zero_f32<<<1, 64, 0, s>>>(reinterpret_cast<float *>(A.queue), 1);
     const int64_t chunks = (A.n_rays + A.rpw - 1) / A.rpw;
     int64_t nblk = (chunks + BWD_WAVES - 1) / BWD_WAVES;
     const int64_t nslice = backward_slices();

@@ -28,10 +28,12 @@ struct BwdArgs {
     const float *grad_rgb;
     float *grad_feat;
     float *partial;  // per-workgroup decoder-gradient slices
+    int32_t *queue;  // work counter of one accumulate launch (zeroed before it)
 };
 
 // Decoder-gradient slices: one per workgroup of the backward grid, which is
-// at most backward_slices() workgroups for any number of rays.
+// at most backward_slices() workgroups for any number of rays, followed by
+// the work counter of the accumulate launches.
 size_t backward_partial_bytes();
 int backward_slices();
 int backward_rays_per_wave(int S);

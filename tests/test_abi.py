@@ -154,7 +154,7 @@ def test_backward_from_samples_rejects_bad_arguments_without_launching():
 
 def test_backward_workspace_holds_one_chunk_of_recomputed_samples():
     """The recomputing backward's workspace holds the gradient slices and the
-    samples of min(R, 65536) rays: it stops growing with the rays."""
+    samples of min(R, 262144) rays: it stops growing with the rays."""
     sc = scenes.sphere_plane(n_sphere=10, n_plane=10)
     part = hp.backward_samples_workspace(sc.params)
     st = ctypes.c_int32()
@@ -162,16 +162,16 @@ def test_backward_workspace_holds_one_chunk_of_recomputed_samples():
     p = sc.params
     S, K = p.n_samples, p.K
     sizes = {}
-    for R in (0, 1, 4096, 65536, 640000, 10_000_000):
+    for R in (0, 1, 4096, 262144, 640000, 10_000_000):
         tab.n_rays = R
         n = hp.lib().hp_backward_workspace(ctypes.byref(tab), ctypes.byref(hp.make_params(p)),
                                            ctypes.byref(st))
         assert st.value == hp.HP_OK
-        rays = max(1, min(R, 65536))
+        rays = max(1, min(R, 262144))
         assert n >= part + rays * (4 * 4 + S * 4 + 2 * S * K * 4)
         assert n <= part + rays * (4 * 4 + S * 4 + 2 * S * K * 4) + 8 * 256
         sizes[R] = n
-    assert sizes[65536] == sizes[640000] == sizes[10_000_000]
+    assert sizes[262144] == sizes[640000] == sizes[10_000_000]
 
 
 def test_radius_modes_validated_and_bounded_like_the_oracle():
