@@ -143,6 +143,14 @@ __device__ __forceinline__ void fused_body(const SearchCtx &c, const FusedArgs &
             if (a.n_sel) a.n_sel[ray] = n;
         }
         lds_sync();
+    }, [&](int64_t ray) {
+        // (one lane) a ray with no point near it: the composite of no sample
+        a.rgb[3 * ray + 0] = fma_rn(1.0f, a.bg[0], 0.0f);
+        a.rgb[3 * ray + 1] = fma_rn(1.0f, a.bg[1], 0.0f);
+        a.rgb[3 * ray + 2] = fma_rn(1.0f, a.bg[2], 0.0f);
+        if (a.depth) a.depth[ray] = 0.0f;
+        if (a.acc) a.acc[ray] = 0.0f;
+        if (a.n_sel) a.n_sel[ray] = 0;
     });
 }
 

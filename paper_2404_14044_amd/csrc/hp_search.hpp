@@ -302,11 +302,34 @@ __device__ __forceinline__ float radius_for_depth(const SearchCtx &c, float kapp
 // of the depth cells around the pixel bounds t from below, so two rounds
 // (each over the cells of the previous radius) shrink the window from the
 // view-wide bound.  If every such cell is empty, no point is near the ray.
-__device__ __forceinline__ RayGeom ray_setup(const SearchCtx &c, int64_t ray, int sub)
+__device__ __forceinline__ int ray_view(const SearchCtx &c, int64_t ray)
 {
-    RayGeom g;
     int vi = 0;
     while (vi + 1 < c.n_views && c.views[vi + 1].ray_base <= ray) ++vi;
+    return vi;
+}
+
+// Window half-width of the first depth-cell round: the view-wide bound.
+__device__ __forceinline__ int first_round_h(const ViewK &V)
+{
+    return min((int)__builtin_floorf(V.dmax + 0.5f), V.g);
+}
+
+// Minimum depth of the cells within the view-wide window of a ray (+inf:
+// no point can be near it), by a group of RS_LANES lanes.
+__device__ __forceinline__ float ray_first_zmin(const SearchCtx &c, int64_t ray, int sub)
+{
+    const int vi = ray_view(c, ray);
+    const ViewK &V = c.views[vi];
+    const int local = (int)(ray - V.ray_base);
+    return group_cells_zmin(c, V, local % V.W + V.g, local / V.W + V.g, first_round_h(V), sub);
+}
+
+// (zmin1: the first round's minimum depth, ray_first_zmin, already taken)
+__device__ __forceinline__ RayGeom ray_setup(const SearchCtx &c, int64_t ray, int sub, float zmin1)
+{
+    RayGeom g;
+    const int vi = ray_view(c, ray);
     const ViewK &V = c.views[vi];
     const int local = (int)(ray - V.ray_base);
     const int u = local % V.W, v = local / V.W;
@@ -346,9 +369,9 @@ __device__ __forceinline__ RayGeom ray_setup(const SearchCtx &c, int64_t ray, in
     g.gx = u + V.g;
     g.gy = v + V.g;
     float Dmax = V.dmax;
-    int h = min((int)__builtin_floorf(Dmax + 0.5f), V.g);
+    int h = first_round_h(V);
     for (int round = 0; round < 2; ++round) {
-        const float zmin = group_cells_zmin(c, V, g.gx, g.gy, h, sub);
+        const float zmin = round == 0 ? zmin1 : group_cells_zmin(c, V, g.gx, g.gy, h, sub);
         if (!(zmin < __builtin_inff())) {
             h = -1;  // no point anywhere near this ray
             break;
@@ -410,8 +433,13 @@ __device__ __forceinline__ RayGeom load_ray(const RayGeom &src)
 // The per-ray set-up (divisions, square roots, the depth-cell rounds) is
 // uniform work that a whole wave would repeat on every lane; groups of lanes
 // instead compute it for up to RS_CAP rays of the chunk at once into the LDS.
-template <typename Body>
-__device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, RayGeom *rs, Body body)
+// The first depth-cell round goes first: a ray whose view-wide window holds
+// no point (most rays of a view that an object does not fill) is finished
+// there by empty(ray), called on one lane per such ray, and neither gets the
+// rest of the set-up nor a pass of the wave.
+template <typename Body, typename Empty>
+__device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, RayGeom *rs, Body body,
+                                                    Empty empty)
 {
     const int l = lane_id();
     const int64_t n_chunks = (c.n_rays + c.chunk - 1) / c.chunk;
@@ -448,14 +476,21 @@ __device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, RayGeom 
         };
         for (int s0 = 0; s0 < ntot; s0 += RS_CAP) {
             const int n = min(RS_CAP, ntot - s0);
-            lds_sync();
             // lanes 4 k .. 4 k + 3 set up ray s0 + k (lanes past the batch
             // repeat its last ray)
-            const int k = l / RS_LANES;
-            const RayGeom gk = ray_setup(c, ray_at(s0 + (k < n ? k : n - 1)), l % RS_LANES);
-            if (l % RS_LANES == 0 && k < n) rs[k] = gk;
+            const int k = l / RS_LANES, sub = l % RS_LANES;
+            const int64_t rk = ray_at(s0 + (k < n ? k : n - 1));
+            const float z1 = ray_first_zmin(c, rk, sub);
+            const bool lead = sub == 0 && k < n;
+            const uint64_t near = ballot(lead && z1 < __builtin_inff());  // bit RS_LANES k
+            if (lead && !(z1 < __builtin_inff())) empty(rk);
+            if (near == 0) continue;
             lds_sync();
-            for (int i = 0; i < n; ++i) body(ray_at(s0 + i), load_ray(rs[i]));
+            const RayGeom gk = ray_setup(c, rk, sub, z1);
+            if (lead) rs[k] = gk;
+            lds_sync();
+            for (int i = 0; i < n; ++i)
+                if ((near >> (RS_LANES * i)) & 1ull) body(ray_at(s0 + i), load_ray(rs[i]));
         }
     }
 }

@@ -54,6 +54,18 @@ k_knp(SearchCtx c, KnpArgs a)
             a.dist[ray * a.K + l] = e;
         }
         lds_sync();
+    }, [&](int64_t ray) {
+        // (one lane) a ray with no point near it: background, no point
+        a.rgb[3 * ray + 0] = a.bg[0];
+        a.rgb[3 * ray + 1] = a.bg[1];
+        a.rgb[3 * ray + 2] = a.bg[2];
+        if (a.cnt) a.cnt[ray] = 0;
+        if (a.idx) {
+            for (int i = 0; i < a.K; ++i) {
+                a.idx[ray * a.K + i] = -1;
+                a.dist[ray * a.K + i] = 0.0f;
+            }
+        }
     });
 }
 

@@ -49,6 +49,19 @@ __device__ __forceinline__ void search_sample_body(const SearchCtx &c, const Sam
             o.nbr_t[ray * c.M + l] = l < m ? tj : 0.0f;
         }
         lds_sync();
+    }, [&](int64_t gray) {
+        // (one lane) a ray with no point near it: no neighbour, no sample
+        const int64_t ray = gray - c.ray0;
+        o.n_sel[ray] = 0;
+        o.n_nbr[ray] = 0;
+        o.flags[ray] = 0u;
+        o.primary[ray] = -1;
+        if (o.nbr_idx) {
+            for (int i = 0; i < c.M; ++i) {
+                o.nbr_idx[ray * c.M + i] = -1;
+                o.nbr_t[ray * c.M + i] = 0.0f;
+            }
+        }
     });
 }
 
