@@ -158,6 +158,32 @@ __device__ __forceinline__ void cswap64(uint64_t &a, uint64_t &b)
     a = lo;
 }
 
+// Keys (bits of a non-negative binary32 << 32 | index) read as binary64 are
+// non-negative finite numbers, subnormal ones included, whose numeric order is
+// the order of their bit patterns, so lane-local sorting networks order them
+// with the binary64 minimum and maximum: one instruction each, where integer
+// 64-bit keys take a compare and four selects.  (Subnormal binary64 values
+// are kept by the kernels' floating-point mode; the keys are never NaN.)
+// KEY_NONE, the largest finite binary64, marks an empty slot: a NaN would be
+// dropped by the minimum and maximum.
+constexpr uint64_t KEY_NONE = 0x7FEFFFFFFFFFFFFFull;
+
+__device__ __forceinline__ double key_f64(uint64_t k) { return __longlong_as_double((long long)k); }
+__device__ __forceinline__ uint64_t f64_key(double d) { return (uint64_t)__double_as_longlong(d); }
+
+__device__ __forceinline__ uint64_t kmin(uint64_t a, uint64_t b)
+{
+    return f64_key(__builtin_fmin(key_f64(a), key_f64(b)));
+}
+
+// (a, b) <- (min, max) of two keys
+__device__ __forceinline__ void kswap(uint64_t &a, uint64_t &b)
+{
+    const double x = key_f64(a), y = key_f64(b);
+    a = f64_key(__builtin_fmin(x, y));
+    b = f64_key(__builtin_fmax(x, y));
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }

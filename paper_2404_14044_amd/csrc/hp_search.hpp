@@ -736,12 +736,12 @@ template <int KT>
 __device__ __forceinline__ void merge_low(uint64_t (&a)[KT], const uint64_t (&b)[KT])
 {
 #pragma unroll
-    for (int k = 0; k < KT; ++k) a[k] = umin64(a[k], b[KT - 1 - k]);
+    for (int k = 0; k < KT; ++k) a[k] = kmin(a[k], b[KT - 1 - k]);
 #pragma unroll
     for (int j = KT / 2; j > 0; j >>= 1) {
 #pragma unroll
         for (int k = 0; k < KT; ++k) {
-            if ((k & j) == 0) cswap64(a[k], a[k + j]);
+            if ((k & j) == 0) kswap(a[k], a[k + j]);
         }
     }
 }
@@ -749,12 +749,12 @@ __device__ __forceinline__ void merge_low(uint64_t (&a)[KT], const uint64_t (&b)
 // Ascending sort of eight keys on the 19-comparator network for n = 8.
 __device__ __forceinline__ void sort8(uint64_t (&x)[8])
 {
-    cswap64(x[0], x[2]); cswap64(x[1], x[3]); cswap64(x[4], x[6]); cswap64(x[5], x[7]);
-    cswap64(x[0], x[4]); cswap64(x[1], x[5]); cswap64(x[2], x[6]); cswap64(x[3], x[7]);
-    cswap64(x[0], x[1]); cswap64(x[2], x[3]); cswap64(x[4], x[5]); cswap64(x[6], x[7]);
-    cswap64(x[2], x[4]); cswap64(x[3], x[5]);
-    cswap64(x[1], x[4]); cswap64(x[3], x[6]);
-    cswap64(x[1], x[2]); cswap64(x[3], x[4]); cswap64(x[5], x[6]);
+    kswap(x[0], x[2]); kswap(x[1], x[3]); kswap(x[4], x[6]); kswap(x[5], x[7]);
+    kswap(x[0], x[4]); kswap(x[1], x[5]); kswap(x[2], x[6]); kswap(x[3], x[7]);
+    kswap(x[0], x[1]); kswap(x[2], x[3]); kswap(x[4], x[5]); kswap(x[6], x[7]);
+    kswap(x[2], x[4]); kswap(x[3], x[5]);
+    kswap(x[1], x[4]); kswap(x[3], x[6]);
+    kswap(x[1], x[2]); kswap(x[3], x[4]); kswap(x[5], x[6]);
 }
 
 // Quad-split nearest neighbours of the ray point at tq among the sorted-list
@@ -767,7 +767,7 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
 {
     const int q = lane_id() & 3;
 #pragma unroll
-    for (int k = 0; k < KT; ++k) kd[k] = ~0ull;
+    for (int k = 0; k < KT; ++k) kd[k] = KEY_NONE;
     int n_it = (hi - lo - q + 3) >> 2;
     n_it = n_it > 0 ? n_it : 0;
     n_it = max(n_it, (int)xor_lane_u32<4>((uint32_t)n_it));
@@ -788,14 +788,14 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
                 const int i = lo + q + 4 * e;
-                x[e] = ~0ull;
+                x[e] = KEY_NONE;
                 if (e < n_it && i < hi) {
                     const float4 P = sh.nb_p[i];
                     const float d2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, tq);
                     if (d2 <= R2) x[e] = ((uint64_t)__float_as_uint(d2) << 32) | __float_as_uint(P.w);
                 }
             }
-            cswap64(x[0], x[1]);
+            kswap(x[0], x[1]);
             uint64_t v[8];
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
@@ -810,10 +810,10 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
                 const uint64_t t = w[2];
                 w[2] = w[3];
                 w[3] = t;
-                cswap64(w[0], w[2]);
-                cswap64(w[1], w[3]);
-                cswap64(w[0], w[1]);
-                cswap64(w[2], w[3]);
+                kswap(w[0], w[2]);
+                kswap(w[1], w[3]);
+                kswap(w[0], w[1]);
+                kswap(w[2], w[3]);
             }
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
@@ -825,9 +825,9 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
             for (int j = 4; j > 0; j >>= 1)
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
-                    if ((k & j) == 0) cswap64(v[k], v[k + j]);
+                    if ((k & j) == 0) kswap(v[k], v[k + j]);
 #pragma unroll
-            for (int k = 0; k < KT; ++k) kd[k] = k < 8 ? v[k < 8 ? k : 0] : ~0ull;
+            for (int k = 0; k < KT; ++k) kd[k] = k < 8 ? v[k < 8 ? k : 0] : KEY_NONE;
             return;
         }
     }
@@ -840,18 +840,18 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int i = lo + q + 4 * e;
-                x[e] = ~0ull;
+                x[e] = KEY_NONE;
                 if (e < n_it && i < hi) {
                     const float4 P = sh.nb_p[i];
                     const float d2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, tq);
                     if (d2 <= R2) x[e] = ((uint64_t)__float_as_uint(d2) << 32) | __float_as_uint(P.w);
                 }
             }
-            cswap64(x[0], x[1]);
-            cswap64(x[2], x[3]);
-            cswap64(x[0], x[2]);
-            cswap64(x[1], x[3]);
-            cswap64(x[1], x[2]);
+            kswap(x[0], x[1]);
+            kswap(x[2], x[3]);
+            kswap(x[0], x[2]);
+            kswap(x[1], x[3]);
+            kswap(x[1], x[2]);
             uint64_t v[16];
 #pragma unroll
             for (int p = 0; p < 4; ++p)
@@ -872,7 +872,7 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
                 for (int j = 4; j > 0; j >>= 1)
 #pragma unroll
                     for (int k = 0; k < 8; ++k)
-                        if ((k & j) == 0) cswap64(w[k], w[k + j]);
+                        if ((k & j) == 0) kswap(w[k], w[k + j]);
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -884,9 +884,9 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
             for (int j = 8; j > 0; j >>= 1)
 #pragma unroll
                 for (int k = 0; k < 16; ++k)
-                    if ((k & j) == 0) cswap64(v[k], v[k + j]);
+                    if ((k & j) == 0) kswap(v[k], v[k + j]);
 #pragma unroll
-            for (int k = 0; k < KT; ++k) kd[k] = k < 16 ? v[k < 16 ? k : 0] : ~0ull;
+            for (int k = 0; k < KT; ++k) kd[k] = k < 16 ? v[k < 16 ? k : 0] : KEY_NONE;
             return;
         }
     }
@@ -900,7 +900,7 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int i = lo + q + 4 * e;
-            x[e] = ~0ull;
+            x[e] = KEY_NONE;
             if (e < n_it && i < hi) {
                 const float4 P = sh.nb_p[i];
                 const float d2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, tq);
@@ -919,27 +919,27 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int i = lo + q + 4 * (it + e);
-            x[e] = ~0ull;
+            x[e] = KEY_NONE;
             if (i < hi) {
                 const float4 P = sh.nb_p[i];
                 const float d2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, tq);
                 if (d2 <= R2) x[e] = ((uint64_t)__float_as_uint(d2) << 32) | __float_as_uint(P.w);
             }
         }
-        cswap64(x[0], x[1]);
-        cswap64(x[2], x[3]);
-        cswap64(x[0], x[2]);
-        cswap64(x[1], x[3]);
-        cswap64(x[1], x[2]);
+        kswap(x[0], x[1]);
+        kswap(x[2], x[3]);
+        kswap(x[0], x[2]);
+        kswap(x[1], x[3]);
+        kswap(x[1], x[2]);
         static_assert(KT >= 4, "lists of at least four");
 #pragma unroll
-        for (int e = 0; e < 4; ++e) kd[KT - 4 + e] = umin64(kd[KT - 4 + e], x[3 - e]);
+        for (int e = 0; e < 4; ++e) kd[KT - 4 + e] = kmin(kd[KT - 4 + e], x[3 - e]);
         // kd is now bitonic and holds the KT smallest: half-cleaners sort it
 #pragma unroll
         for (int j = KT / 2; j > 0; j >>= 1) {
 #pragma unroll
             for (int k = 0; k < KT; ++k)
-                if ((k & j) == 0) cswap64(kd[k], kd[k + j]);
+                if ((k & j) == 0) kswap(kd[k], kd[k + j]);
         }
     }
     uint64_t other[KT];
@@ -955,7 +955,7 @@ __device__ __forceinline__ void knn_window(const RayGeom &g, const SearchLds &sh
 // candidate c0 + g; its four lanes split the candidate's t-window of the
 // sorted list (entries within R_j in t), each keeping an ascending register
 // list, merged across the quad.  On return every lane of the quad holds the
-// candidate's KT smallest keys (~0 = none).
+// candidate's KT smallest keys (KEY_NONE = none).
 template <int KT>
 __device__ __forceinline__ void knn_quad(const SearchCtx &c, const RayGeom &g, const SearchLds &sh,
                                          int j, int m, uint64_t (&kd)[KT])
@@ -1017,7 +1017,7 @@ __device__ __forceinline__ void quad_list_sqrt(const uint64_t (&kd)[KT], float (
 // processed 16 at a time, candidate c0 + g on lanes 4 g .. 4 g + 3.  After a
 // chunk's transmittance walk, emit(s, q, tj, kd, kc) is called on the four
 // lanes (q = 0..3) of every candidate that became sample s, with its K nearest
-// neighbours kd (ascending (dist^2 bits, index), ~0 = none), their number kc
+// neighbours kd (ascending (dist^2 bits, index), KEY_NONE = none), their number kc
 // and the lane's share dq of their distances (quad_list_sqrt).  Returns the sample count and sets first_idx to the primary point.
 template <int KT, typename Emit>
 __device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom &g, SearchLds &sh,
@@ -1050,7 +1050,7 @@ __device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom
         // the list's valid entries (key != ~0) form a prefix; the first K count
         int kc = 0;
 #pragma unroll
-        for (int k = 0; k < KT; ++k) kc += kd[k] != ~0ull ? 1 : 0;
+        for (int k = 0; k < KT; ++k) kc += kd[k] != KEY_NONE ? 1 : 0;
         kc = min(kc, c.K);
         float alpha = 0.0f, tj = 0.0f;
         if (j < m) {
@@ -1203,7 +1203,7 @@ __device__ __forceinline__ int uniform_samples(const SearchCtx &c, const RayGeom
         }
         uint64_t kd[KT];
         knn_window<KT>(g, sh, tk, R2, wlo, whi, kd);
-        const bool kept = active && kd[0] != ~0ull;
+        const bool kept = active && kd[0] != KEY_NONE;
         const uint64_t km = ballot(kept && (l & 3) == 0);  // bit 4 p: position b + p kept
         const int room = c.S - sel;
         const int rank = popc64(km & ((1ull << (4 * gp)) - 1ull));
@@ -1212,7 +1212,7 @@ __device__ __forceinline__ int uniform_samples(const SearchCtx &c, const RayGeom
             if (kept && rank < room) {
                 int kc = 0;
 #pragma unroll
-                for (int q = 0; q < KT; ++q) kc += (q < c.K && kd[q] != ~0ull) ? 1 : 0;
+                for (int q = 0; q < KT; ++q) kc += (q < c.K && kd[q] != KEY_NONE) ? 1 : 0;
                 float dq[KT / 4];
                 quad_list_sqrt<KT>(kd, dq);
                 emit(sel + rank, l & 3, tk, kd, dq, kc);

@@ -226,6 +226,33 @@ def test_adversarial_scene():
     assert_render_error(err, 0, sc.params)
 
 
+def test_zero_distances_on_the_optical_axis():
+    """Copies of points on the optical axis of an odd-sized view: the centre
+    pixel's ray is (0, 0, 1) exactly, so a candidate's distance to each copy
+    of itself is exactly zero and the nearest-neighbour order of those copies
+    rests on the index alone (keys whose distance part is zero); some copies
+    differ only in depth, a few in the last bit of a coordinate."""
+    rng = np.random.default_rng(3)
+    cam = scenes.pinhole(23, 23, 50.0, np.eye(3), np.zeros(3))
+    p = scenes.default_params(0.02, 1.0, 5.0, K=8, S=16)
+    pts = [np.repeat([[0.0, 0.0, 2.0]], 12, 0), np.repeat([[0.0, 0.0, 2.004]], 5, 0),
+           np.array([[0.0, 1e-30, 2.0], [1e-38, 0.0, 2.0], [0.0, 0.0, np.nextafter(np.float32(2.0), 3)]]),
+           np.concatenate([rng.uniform(-0.6, 0.6, (2000, 2)), rng.uniform(2.0, 2.02, (2000, 1))], 1)]
+    xyz = np.concatenate(pts).astype(np.float32)
+    perm = rng.permutation(xyz.shape[0])   # copies at scattered indices
+    xyz = xyz[perm]
+    feat = rng.normal(size=(xyz.shape[0], 32)).astype(np.float32)
+    sc = scenes.Scene("axis", xyz, feat, [cam], p, scenes.make_mlp(9))
+    from paper_2404_14044_amd import hashpoint as hp
+    out = gpu_forward(sc, precision=hp.HP_FP32)
+    pix = _all_pix(cam)
+    ex = compare_exact(sc, out["samples"], pix)
+    centre = 11 * 23 + 11
+    assert ex["n_sel"][centre] > 0
+    err = render_error(sc, out["render"], ex, pix)
+    assert_render_error(err, 0, sc.params)
+
+
 def test_objects_sampled_rays(objects):
     sc = objects
     from paper_2404_14044_amd import hashpoint as hp
