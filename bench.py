@@ -380,29 +380,43 @@ def _time_ms(fn, reps):
 
 def batched_leg(sc, reps=5):
     """16 views of the object scene, sides uniform in {256..1024}: one batched
-    pass (eager and replayed from a captured graph) vs 16 per-view passes."""
+    pass (eager and replayed from a captured graph) vs 16 per-view passes,
+    with the library's default layout and launch shapes and with the
+    autotuner's choice for these views (tuned here, in a fresh cache)."""
     import torch
     from paper_2404_14044_amd import hashpoint as hp
     from paper_2404_14044_amd import scenes
+    from paper_2404_14044_amd.autotune import Autotuner
     from paper_2404_14044_amd.batched import BatchedRenderer, render_views_separately
     dev = torch.device("cuda:0")
     bs = scenes.batched_16(base=sc)
     xyz = torch.from_numpy(bs.xyz).to(dev)
     feat = torch.from_numpy(bs.feat).to(dev)
     mlp = hp.to_device_mlp(bs.mlp, dev)
-    br = BatchedRenderer(xyz, feat, mlp, bs.cams, bs.params, hp.HP_BF16)
-    t_eager = _time_ms(br.run_eager, reps)
-    br.capture()
-    t_graph = _time_ms(br.replay, reps)
-    del br
-    state = render_views_separately(xyz, feat, mlp, bs.cams, bs.params, hp.HP_BF16)
-    t_sep = _time_ms(lambda: render_views_separately(xyz, feat, mlp, bs.cams, bs.params,
-                                                     hp.HP_BF16, state), reps)
     rays = sum(c.W * c.H for c in bs.cams)
-    return {"rays": rays, "views": len(bs.cams),
-            "graph_ms": t_graph, "eager_ms": t_eager, "separate_ms": t_sep,
-            "graph_mrays_s": rays / t_graph / 1e3, "eager_mrays_s": rays / t_eager / 1e3,
-            "separate_mrays_s": rays / t_sep / 1e3, "speedup_vs_separate": t_sep / t_graph}
+    out = {"rays": rays, "views": len(bs.cams)}
+    tuner = Autotuner()
+    t0 = time.time()
+    tuned = BatchedRenderer(xyz, feat, mlp, bs.cams, bs.params, hp.HP_BF16, tuner=tuner)
+    ent = tuner.entry(xyz, bs.cams, bs.params, hp.HP_BF16)
+    out["autotune"] = {"best": ent["best"], "trials": len(ent["trials"]),
+                       "tune_s": time.time() - t0,
+                       "frame_ms_default": ent["default_ms"], "frame_ms_tuned": ent["ms"]}
+    for name, br in (("default", BatchedRenderer(xyz, feat, mlp, bs.cams, bs.params, hp.HP_BF16)),
+                     ("tuned", tuned)):
+        t_eager = _time_ms(br.run_eager, reps)
+        br.capture()
+        t_graph = _time_ms(br.replay, reps)
+        state = render_views_separately(xyz, feat, mlp, bs.cams, br.params, hp.HP_BF16)
+        t_sep = _time_ms(lambda: render_views_separately(xyz, feat, mlp, bs.cams, br.params,
+                                                         hp.HP_BF16, state), reps)
+        out[name] = {"graph_ms": t_graph, "eager_ms": t_eager, "separate_ms": t_sep,
+                     "graph_mrays_s": rays / t_graph / 1e3, "eager_mrays_s": rays / t_eager / 1e3,
+                     "separate_mrays_s": rays / t_sep / 1e3,
+                     "speedup_vs_separate": t_sep / t_graph}
+        del br, state
+    out["tuned_over_default_graph"] = out["default"]["graph_ms"] / out["tuned"]["graph_ms"]
+    return out
 
 
 def radius_modes_leg(sc, reps=5):

@@ -56,7 +56,17 @@ enum {
 };
 
 enum { HP_FP32 = 0, HP_BF16 = 1 };                 /* decoder precision  */
-enum { HP_LAYOUT_ROWMAJOR = 0, HP_LAYOUT_TILED = 1 }; /* bucket order     */
+/* Bucket order of the table (hp_params.layout); no result depends on it. */
+enum {
+    HP_LAYOUT_ROWMAJOR = 0, /* row-major over the guard-banded pixel grid         */
+    HP_LAYOUT_TILED = 1,    /* 8x8-pixel tiles, row-major inside each tile        */
+    HP_LAYOUT_MORTON = 2    /* 8x8-pixel tiles, Z-order (Morton) inside each tile */
+};
+/* Window of buckets a ray visits (hp_params.window_shape); both complete. */
+enum {
+    HP_WINDOW_DISC = 0,  /* buckets within the proven pixel radius of the ray */
+    HP_WINDOW_SQUARE = 1 /* the square around that disc (fewer tests per bucket) */
+};
 /* Search radius laws (hp_params.radius_mode). */
 enum {
     HP_RADIUS_LINEAR = 0, /* rho = radius * max(1, t * inv_tref)                     */
@@ -104,7 +114,8 @@ typedef struct hp_camera {
  *  eps_idw: floor of the distance in the inverse-distance feature weights.
  *  delta_last: interval length of the last sample of a ray (Eq. 2).
  *  bg: background colour.
- *  layout: HP_LAYOUT_ROWMAJOR or HP_LAYOUT_TILED (8x8 pixel tiles).
+ *  layout: HP_LAYOUT_ROWMAJOR, HP_LAYOUT_TILED or HP_LAYOUT_MORTON (Sec. 3.2
+ *      mentions a Z-order arrangement; read here as an order of buckets).
  *  flags: reserved, must be 0.
  *  search_chunk: rays a search workgroup takes at a time, 0 = default (4),
  *      at most 64; search_blocks: persistent search grid, 0 = default.
@@ -123,7 +134,16 @@ typedef struct hp_camera {
  *      neighbour list lies within rho(t_k) of it, with its K nearest listed
  *      points; primary = the nearest point of the first sample.  gamma,
  *      inv_beta2 and eps_w are then unused.
- *  ms_steps: 1..2^24 with HP_SAMPLER_MS, 0 otherwise. */
+ *  ms_steps: 1..2^24 with HP_SAMPLER_MS, 0 otherwise.
+ *  Launch shapes, none of which changes any result (an autotuner picks them
+ *  per workload; 0 = default):
+ *  search_band: consecutive rays dealt to one XCD at a time by the search
+ *      kernels, 0 (12,800) or 64..2^24;
+ *  window_shape: HP_WINDOW_DISC or HP_WINDOW_SQUARE;
+ *  render_rays: rays a render wave composites at a time, 0 (32), 16, 32 or 64;
+ *  render_blocks: render grid; a workgroup takes every render_blocks-th
+ *      chunk of render_rays rays (persistent, loading the decoder weights
+ *      once), 0 = one workgroup per chunk. */
 typedef struct hp_params {
     float radius, inv_tref, t_near, t_far;
     int32_t K, n_samples, m_cap;
@@ -134,6 +154,7 @@ typedef struct hp_params {
     int32_t radius_mode;
     float rddot;
     int32_t sampler, ms_steps;
+    int32_t search_band, window_shape, render_rays, render_blocks;
 } hp_params;
 
 /* Per-view geometry of a table, filled by hp_build_table. */

@@ -2,7 +2,7 @@
 
 All views share one table (one build launch per phase for every view), one
 persistent search + sampling launch over the rays of every view, and one
-render launch.  Buffers are sized once for the views, so the whole frame can
+persistent render launch over chunks of those rays.  Buffers are sized once for the views, so the whole frame can
 be captured into a graph and each later frame is a single graph launch.
 `render_views_separately` is the per-view baseline: one build, one search and
 one render per view.
@@ -17,10 +17,18 @@ from . import hashpoint as hp
 
 
 class BatchedRenderer:
+    """All views in one build / search / render (capturable as one graph).
+    With `tuner` (an autotune.Autotuner) the bucket layout and launch shapes
+    are the tuner's choice for these views (tuned on first use, then cached);
+    no result depends on them."""
+
     def __init__(self, xyz: torch.Tensor, feat: torch.Tensor, mlp: Dict[str, torch.Tensor],
-                 cams: Sequence, params, precision: int = hp.HP_BF16):
+                 cams: Sequence, params, precision: int = hp.HP_BF16, tuner=None):
         self.xyz, self.feat, self.mlp = xyz, feat, mlp
-        self.cams, self.params, self.precision = list(cams), params, precision
+        self.cams, self.precision = list(cams), precision
+        if tuner is not None:
+            params = tuner.tune(xyz, feat, mlp, self.cams, params, precision)
+        self.params = params
         dev = xyz.device
         self.ws = torch.empty(hp.table_workspace(xyz.shape[0], self.cams, params),
                               dtype=torch.uint8, device=dev)

@@ -50,7 +50,14 @@ bool valid_params(const hp_params &p)
     if (!(p.delta_last > 0.0f) || !finite_f(p.delta_last)) return false;
     for (int i = 0; i < 3; ++i)
         if (!finite_f(p.bg[i])) return false;
-    if (p.layout != HP_LAYOUT_ROWMAJOR && p.layout != HP_LAYOUT_TILED) return false;
+    if (p.layout != HP_LAYOUT_ROWMAJOR && p.layout != HP_LAYOUT_TILED &&
+        p.layout != HP_LAYOUT_MORTON)
+        return false;
+    if (p.search_band != 0 && (p.search_band < 64 || p.search_band > (1 << 24))) return false;
+    if (p.window_shape != HP_WINDOW_DISC && p.window_shape != HP_WINDOW_SQUARE) return false;
+    if (p.render_rays != 0 && p.render_rays != 16 && p.render_rays != 32 && p.render_rays != 64)
+        return false;
+    if (p.render_blocks < 0) return false;
     if (p.flags != 0) return false;
     if (p.search_chunk < 0 || p.search_chunk > 64 || p.search_blocks < 0) return false;
     if (p.sampler == HP_SAMPLER_PS) {
@@ -111,7 +118,7 @@ hp_status plan_views(const hp_camera *cams, int32_t n_views, const hp_params &p,
         if (!view_bound(c, p, delta)) return HP_E_INVALID;
         const int32_t g = (int32_t)floor(0.5 + delta) + 1;
         int64_t Wg = (int64_t)c.W + 2 * g, Hg = (int64_t)c.H + 2 * g;
-        if (p.layout == HP_LAYOUT_TILED) {
+        if (p.layout != HP_LAYOUT_ROWMAJOR) {  // whole 8x8 tiles
             Wg = (Wg + 7) / 8 * 8;
             Hg = (Hg + 7) / 8 * 8;
         }
@@ -328,6 +335,8 @@ static hp_status make_ctx(const hp_table *tab, const hp_camera *cams, int32_t n_
     c.S = p->n_samples;
     c.M = p->m_cap;
     c.chunk = p->search_chunk > 0 ? p->search_chunk : 4;
+    c.band = p->search_band > 0 ? p->search_band : hp::BAND_RAYS;
+    c.window = p->window_shape;
     c.blocks = p->search_blocks;
     c.rmode = p->radius_mode;
     c.rddot = p->rddot;
@@ -443,6 +452,8 @@ hp_status hp_render(const hp_samples *smp, int64_t R, const float *feat, int32_t
     a.rgb = rgb;
     a.depth = depth;
     a.acc = acc;
+    a.rpw = p->render_rays > 0 ? p->render_rays : 32;
+    a.blocks = p->render_blocks;
     const hipError_t e = hp::launch_render(a, precision, (hipStream_t)stream);
     return e == hipSuccess ? HP_OK : hip_fail(e);
 }

@@ -55,12 +55,17 @@ __device__ __forceinline__ void to_camera(const ViewK &V, float px, float py, fl
 }
 
 // Bucket of grid cell (bx, by) of a view.  Row-major, or 8x8 tiles stored
-// row-major with row-major cells inside each tile.
+// row-major with the cells inside each tile row-major (TILED) or in Z-order
+// (MORTON: the bits of x and y interleaved, x in the even bits).
 __device__ __forceinline__ int32_t bucket_of(const ViewK &V, int layout, int bx, int by)
 {
-    if (layout == HP_LAYOUT_TILED) {
+    if (layout != HP_LAYOUT_ROWMAJOR) {
         const int ntx = V.Wg >> 3;
-        return V.bucket_base + ((((by >> 3) * ntx) + (bx >> 3)) << 6) + ((by & 7) << 3) + (bx & 7);
+        const int tile = V.bucket_base + ((((by >> 3) * ntx) + (bx >> 3)) << 6);
+        const int x = bx & 7, y = by & 7;
+        if (layout == HP_LAYOUT_TILED) return tile + (y << 3) + x;
+        return tile + ((x & 1) | ((y & 1) << 1) | ((x & 2) << 1) | ((y & 2) << 2) | ((x & 4) << 2) |
+                       ((y & 4) << 3));
     }
     return V.bucket_base + by * V.Wg + bx;
 }

@@ -35,6 +35,8 @@ struct RenderArgs {
     float eps_idw, delta_last;
     float bg[3];
     float *rgb, *depth, *acc;
+    int32_t rpw;     // rays per render chunk (16, 32 or 64)
+    int32_t blocks;  // render grid, 0 = one workgroup per chunk
 };
 
 struct TableWs;

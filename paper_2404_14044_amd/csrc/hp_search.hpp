@@ -61,6 +61,8 @@ struct SearchCtx {
     float rddot;            // Eq. 3 kernel disc radius (unit focal length)
     int32_t sampler;        // HP_SAMPLER_*
     int32_t ms_steps;       // uniform positions of the multi-surface sampler
+    int32_t band;           // consecutive rays per XCD band (BAND_RAYS by default)
+    int32_t window;         // HP_WINDOW_*: disc of buckets, or the square around it
 };
 
 // One ray's geometry and search bounds, uniform across the wave that
@@ -445,7 +447,7 @@ __device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, RayGeom 
     const int64_t n_chunks = (c.n_rays + c.chunk - 1) / c.chunk;
     // chunks per band (fewer when the launch has fewer than eight full bands,
     // so that every XCD gets a share)
-    int64_t band = (BAND_RAYS + c.chunk - 1) / c.chunk;
+    int64_t band = ((int64_t)c.band + c.chunk - 1) / c.chunk;
     if (band * 8 > n_chunks) band = (n_chunks + 7) / 8 > 0 ? (n_chunks + 7) / 8 : 1;
     const int xcd = blockIdx.x & 7;
     const int64_t slot = blockIdx.x >> 3, n_slots = gridDim.x >> 3;
@@ -509,6 +511,8 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
     const float z_lo = g.z_lo, z_hi = g.z_hi, dinf = g.dinf;
     const float frL2 = g.frL2, two_rw = g.two_rw, inv_L = g.inv_L, Dmax = g.Dmax;
     const int gx = g.gx, gy = g.gy, h = g.h;
+    // (the square window also visits the corners beyond the proven radius)
+    const bool square = c.window == HP_WINDOW_SQUARE;
 
     top = ~0ull;
     count = 0;
@@ -616,7 +620,7 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
         if (!valid) return false;
         const int bx = gx + dxi, by = gy + dyi;
         const float D = offset_D(dxi < 0 ? -dxi : dxi, dyi < 0 ? -dyi : dyi);
-        if (!(bx >= 0 && bx < Wg && by >= 0 && by < Hg && D <= Dmax)) return false;
+        if (!(bx >= 0 && bx < Wg && by >= 0 && by < Hg && (square || D <= Dmax))) return false;
         zmax = zmax_at(D);
         const int key = bucket_of(Vg, c.layout, bx, by);
         st = c.offsets[key];
@@ -685,7 +689,7 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
             const int ady = gy < by0 ? by0 - gy : (gy > by1 ? gy - by1 : 0);
             const float D = offset_D(adx, ady);
             const float cz = __uint_as_float(c.cell_zmin[cell_base + cyy * ncx + cxx]);
-            keep = D <= Dmax && cz <= zmax_at(D);
+            keep = (square || D <= Dmax) && cz <= zmax_at(D);
         }
         const uint64_t km = ballot(keep);
         if (km == 0) continue;

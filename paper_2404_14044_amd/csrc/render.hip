@@ -1,7 +1,8 @@
 // Decode and composite the samples (Sec. 3.4, Eq. 2).
 //
-// One wave per chunk of RPW consecutive rays.  The wave packs the chunk's
-// samples densely into tiles of 16, and for each tile:
+// One wave per chunk of RPW consecutive rays at a time (a persistent grid,
+// see render_body).  The wave packs the chunk's samples densely into tiles
+// of 16, and for each tile:
 //   1. aggregates the features of every sample's K neighbours with
 //      inverse-distance weights (FP32): lane l handles sample l % 16 and
 //      feature slice 8 (l / 16) .. +8, reading 32 contiguous bytes per neighbour;
@@ -73,16 +74,14 @@ __device__ __forceinline__ void idw_slice(const RenderArgs &a, int64_t row, int 
     for (int e = 0; e < 8; ++e) f[e] *= inv;
 }
 
-constexpr int RPW = 32;  // rays per wave
-
-template <int PREC>
-__device__ __forceinline__ void render_body(const RenderArgs &a)
+// One chunk of RPW consecutive rays starting at ray0: pack its samples into
+// tiles of 16, aggregate and decode them, composite each ray.  `mlp` is
+// loaded here unless `loaded` says an earlier chunk left it in registers.
+template <int PREC, int RPW, typename Mlp>
+__device__ __forceinline__ void render_chunk(const RenderArgs &a, int64_t ray0, Mlp &mlp,
+                                             bool &loaded, float4 *sh_out, int *sh_pre)
 {
-    extern __shared__ float4 sh_out[];  // [RPW * S] (rgb, sigma) per sample
-    __shared__ int sh_pre[RPW + 1];
     const int l = lane_id();
-    const int64_t ray0 = (int64_t)blockIdx.x * RPW;
-    if (ray0 >= a.n_rays) return;
     const int nr = (a.n_rays - ray0) < RPW ? (int)(a.n_rays - ray0) : RPW;
 
     // prefix of sample counts over the chunk
@@ -96,16 +95,17 @@ __device__ __forceinline__ void render_body(const RenderArgs &a)
     __syncthreads();
 
     if (total > 0) {
-        typename std::conditional<PREC == HP_BF16, MlpBf16, MlpF32>::type mlp;
-        const MlpWeights wts{a.W1, a.b1, a.W2, a.b2, a.W3, a.b3};
-        if constexpr (PREC == HP_BF16) load_mlp_bf16(wts, mlp);
-        else load_mlp_f32(wts, mlp);
+        if (PREC != HP_BF16 || !loaded) {
+            const MlpWeights wts{a.W1, a.b1, a.W2, a.b2, a.W3, a.b3};
+            if constexpr (PREC == HP_BF16) load_mlp_bf16(wts, mlp);
+            else load_mlp_f32(wts, mlp);
+            loaded = true;
+        }
         const int r16 = l & 15, q = l >> 4;
         for (int s0 = 0; s0 < total; s0 += 16) {
             const int sidx = s0 + r16;
             const bool valid = sidx < total;
             float f[8];
-            int cr = 0, cs = 0;
             if (valid) {
                 int lo = 0, hi = nr;  // chunk-local ray: last with pre <= sidx
                 while (hi - lo > 1) {
@@ -113,9 +113,7 @@ __device__ __forceinline__ void render_body(const RenderArgs &a)
                     if (sh_pre[mid] <= sidx) lo = mid;
                     else hi = mid;
                 }
-                cr = lo;
-                cs = sidx - sh_pre[lo];
-                idw_slice(a, (ray0 + cr) * a.S + cs, q, f);
+                idw_slice(a, (ray0 + lo) * a.S + (sidx - sh_pre[lo]), q, f);
             } else {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) f[e] = 0.0f;
@@ -155,24 +153,72 @@ __device__ __forceinline__ void render_body(const RenderArgs &a)
     }
 }
 
+// Render grid.  By default one workgroup (one wave) per chunk, so the
+// hardware dispatcher balances chunks with many samples against empty ones.
+// The persistent form (render_blocks = G) has workgroup b take chunks b,
+// b + G, b + 2G, ... and load the decoder weights at most once (BF16); the
+// autotuner chooses between them.  Neither changes a result: every ray is
+// composited by one lane from its own samples, and each sample's decoder
+// column is independent of the tile it is packed in.
+template <int PREC, int RPW, bool PERSIST>
+__device__ __forceinline__ void render_body(const RenderArgs &a)
+{
+    extern __shared__ float4 sh_out[];  // [RPW * S] (rgb, sigma) per sample
+    __shared__ int sh_pre[RPW + 1];
+    typename std::conditional<PREC == HP_BF16, MlpBf16, MlpF32>::type mlp;
+    bool loaded = false;
+    const int64_t n_chunks = (a.n_rays + RPW - 1) / RPW;
+    if constexpr (!PERSIST) {
+        if ((int64_t)blockIdx.x < n_chunks)
+            render_chunk<PREC, RPW>(a, (int64_t)blockIdx.x * RPW, mlp, loaded, sh_out, sh_pre);
+    } else {
+        for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+            render_chunk<PREC, RPW>(a, ch * RPW, mlp, loaded, sh_out, sh_pre);
+            __syncthreads();  // this chunk's compositing read sh_pre / sh_out
+        }
+    }
+}
+
 // BF16 fits three waves per SIMD; the FP32 decoder's operands need more registers.
+template <int RPW, bool PERSIST>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_render_bf16(RenderArgs a)
 {
-    render_body<HP_BF16>(a);
+    render_body<HP_BF16, RPW, PERSIST>(a);
 }
 
-__global__ void __launch_bounds__(WAVE) k_render_fp32(RenderArgs a) { render_body<HP_FP32>(a); }
+template <int RPW, bool PERSIST>
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_render_fp32(RenderArgs a)
+{
+    render_body<HP_FP32, RPW, PERSIST>(a);
+}
+
+template <int RPW>
+static void launch_render_rpw(const RenderArgs &a, int precision, int64_t blocks, bool persist,
+                              hipStream_t s)
+{
+    const size_t shmem = (size_t)RPW * a.S * sizeof(float4);
+    const dim3 grid((unsigned)blocks), block(WAVE);
+    if (precision == HP_BF16) {
+        if (persist) k_render_bf16<RPW, true><<<grid, block, shmem, s>>>(a);
+        else k_render_bf16<RPW, false><<<grid, block, shmem, s>>>(a);
+    } else {
+        if (persist) k_render_fp32<RPW, true><<<grid, block, shmem, s>>>(a);
+        else k_render_fp32<RPW, false><<<grid, block, shmem, s>>>(a);
+    }
+}
 
 hipError_t launch_render(const RenderArgs &a, int precision, hipStream_t s)
 {
-    const int64_t blocks = (a.n_rays + RPW - 1) / RPW;
-    if (blocks == 0) return hipSuccess;
-    const size_t shmem = (size_t)RPW * a.S * sizeof(float4);
-    if (precision == HP_BF16)
-        k_render_bf16<<<dim3((unsigned)blocks), dim3(WAVE), shmem, s>>>(a);
-    else
-        k_render_fp32<<<dim3((unsigned)blocks), dim3(WAVE), shmem, s>>>(a);
+    const int rpw = a.rpw == 16 || a.rpw == 64 ? a.rpw : 32;
+    const int64_t chunks = (a.n_rays + rpw - 1) / rpw;
+    if (chunks == 0) return hipSuccess;
+    const bool persist = a.blocks > 0 && a.blocks < chunks;
+    const int64_t blocks = persist ? a.blocks : chunks;
+    if (rpw == 16) launch_render_rpw<16>(a, precision, blocks, persist, s);
+    else if (rpw == 64) launch_render_rpw<64>(a, precision, blocks, persist, s);
+    else launch_render_rpw<32>(a, precision, blocks, persist, s);
     return hipGetLastError();
 }
 

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libhashpoint.so")
 
 HP_OK, HP_E_INVALID, HP_E_WORKSPACE, HP_E_UNSUPPORTED, HP_E_CAPACITY, HP_E_HIP = range(6)
 HP_FP32, HP_BF16 = 0, 1
-HP_LAYOUT_ROWMAJOR, HP_LAYOUT_TILED = 0, 1
+HP_LAYOUT_ROWMAJOR, HP_LAYOUT_TILED, HP_LAYOUT_MORTON = 0, 1, 2
+HP_WINDOW_DISC, HP_WINDOW_SQUARE = 0, 1
 HP_RADIUS_LINEAR, HP_RADIUS_EQ3, HP_RADIUS_EQ3_AF, HP_RADIUS_EQ3_AE = 0, 1, 2, 3
 HP_SAMPLER_PS, HP_SAMPLER_MS = 0, 1
 HP_MAX_VIEWS = 32
@@ -54,7 +55,9 @@ class HPParams(ctypes.Structure):
                 ("layout", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("search_chunk", ctypes.c_int32), ("search_blocks", ctypes.c_int32),
                 ("radius_mode", ctypes.c_int32), ("rddot", ctypes.c_float),
-                ("sampler", ctypes.c_int32), ("ms_steps", ctypes.c_int32)]
+                ("sampler", ctypes.c_int32), ("ms_steps", ctypes.c_int32),
+                ("search_band", ctypes.c_int32), ("window_shape", ctypes.c_int32),
+                ("render_rays", ctypes.c_int32), ("render_blocks", ctypes.c_int32)]
 
 
 class HPViewInfo(ctypes.Structure):
@@ -172,6 +175,10 @@ def make_params(p) -> HPParams:
     s.rddot = float(getattr(p, "rddot", 0.0))
     s.sampler = int(getattr(p, "sampler", 0))
     s.ms_steps = int(getattr(p, "ms_steps", 0))
+    s.search_band = int(getattr(p, "search_band", 0))
+    s.window_shape = int(getattr(p, "window_shape", 0))
+    s.render_rays = int(getattr(p, "render_rays", 0))
+    s.render_blocks = int(getattr(p, "render_blocks", 0))
     return s
 
 

@@ -94,6 +94,9 @@ class Params:
         its two small-angle variants (AB replaced by AF, by AE); rho = t kappa
         with kappa per pixel.  `eq3_rddot` picks rddot so that the principal
         pixel's radius at t_near is `radius`.
+    layout, search_chunk, search_blocks, search_band, window_shape,
+        render_rays, render_blocks: bucket order and launch shapes; none of
+        them changes a result (the autotuner picks them).
     sampler, ms_steps: sampler 0 is the adaptive primary-surface walk
         (Sec. 3.3); sampler 1 the uniform multi-surface baseline (Sec. 3.5):
         ms_steps uniform positions along [t_near, t_far], each kept when a
@@ -128,6 +131,10 @@ class Params:
     rddot: float = 0.0
     sampler: int = 0
     ms_steps: int = 0
+    search_band: int = 0
+    window_shape: int = 0
+    render_rays: int = 0
+    render_blocks: int = 0
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)

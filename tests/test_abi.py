@@ -35,7 +35,7 @@ def test_exports_every_declared_function():
 def test_struct_sizes_match_header():
     # pointer-sized fields and int64 alignment as the C compiler lays them out
     assert ctypes.sizeof(hp.HPCamera) == 4 * 18
-    assert ctypes.sizeof(hp.HPParams) == 4 * 23
+    assert ctypes.sizeof(hp.HPParams) == 4 * 27
     assert ctypes.sizeof(hp.HPViewInfo) == 32
     assert ctypes.sizeof(hp.HPSamples) == 8 * 9
     assert ctypes.sizeof(hp.HPMlp) == 8 * 6
@@ -69,7 +69,8 @@ def test_workspace_size_grows_with_points():
     ("K", 0), ("K", 33), ("n_samples", 0), ("n_samples", 65), ("m_cap", 0), ("m_cap", 65),
     ("gamma", 0.0), ("gamma", 1.5), ("eps_idw", 0.0), ("delta_last", 0.0), ("layout", 7),
     ("flags", 1), ("inv_tref", -1.0), ("search_chunk", -1), ("search_chunk", 65),
-    ("search_blocks", -2),
+    ("search_blocks", -2), ("layout", 3), ("search_band", 63), ("search_band", -1),
+    ("window_shape", 2), ("render_rays", 48), ("render_rays", 128), ("render_blocks", -1),
 ])
 def test_invalid_params_rejected_on_host(field, value):
     sc = scenes.sphere_plane(n_sphere=10, n_plane=10)

@@ -4,7 +4,8 @@
   what separate per-view launches give.
 * A captured graph replayed several times, with other GPU work and
   synchronisations in between, reproduces the eager result bit for bit.
-* The autotuner's choice changes no result.
+* Bucket layouts and launch shapes change no result, nor does the
+  autotuner's choice among them (cached and reloaded).
 """
 import numpy as np
 import pytest
@@ -103,23 +104,76 @@ def test_graph_replay_reproduces_eager(views):
         del junk
 
 
-def test_autotuner_choice_changes_no_result(tmp_path):
+def _frame(xyz, feat, mlp, cams, p, precision):
+    from paper_2404_14044_amd import hashpoint as hp
+    tab = hp.build_table(xyz, cams, p)
+    smp = hp.search_sample(tab, p, debug=True)
+    out = hp.render(smp, tab.n_rays, feat, mlp, p, precision)
+    return smp, out
+
+
+def _assert_same_frame(a, b, S, K):
+    sa, oa = a
+    sb, ob = b
+    for k in ("n_sel", "primary", "n_nbr", "flags", "nbr_idx"):
+        assert np.array_equal(host(sa[k]), host(sb[k])), k
+    assert np.array_equal(host(sa["nbr_t"]).view(np.int32), host(sb["nbr_t"]).view(np.int32))
+    ns = host(sa["n_sel"])
+    mask = np.arange(S)[None, :] < ns[:, None]
+    for k, w in (("t", 1), ("knn_idx", K), ("knn_dist", K)):
+        x = host(sa[k]).reshape(-1, S, w)[mask]
+        y = host(sb[k]).reshape(-1, S, w)[mask]
+        assert np.array_equal(x.view(np.int32), y.view(np.int32)), k
+    for k in ("rgb", "depth", "acc"):
+        assert np.array_equal(host(oa[k]).view(np.int32), host(ob[k]).view(np.int32)), k
+
+
+@pytest.mark.parametrize("shape", [
+    dict(layout=2),
+    dict(layout=1, window_shape=1, search_chunk=8, search_blocks=1024, search_band=640),
+    dict(window_shape=1, search_band=64, render_rays=16, render_blocks=64),
+    dict(layout=2, search_chunk=1, render_rays=64, render_blocks=8),
+])
+def test_launch_shapes_change_no_result(views, shape):
+    """Bucket layouts (row-major, tiles, Z-order tiles), window shapes, XCD
+    bands and the persistent search and render grids: every output of the
+    sixteen views, neighbour lists included, is bit-identical to the
+    defaults'."""
+    import torch
+    from paper_2404_14044_amd import hashpoint as hp
+    sc = views
+    xyz, feat, mlp = _setup(sc)
+    ref = _frame(xyz, feat, mlp, sc.cams, sc.params, hp.HP_BF16)
+    got = _frame(xyz, feat, mlp, sc.cams, sc.params.replace(**shape), hp.HP_BF16)
+    torch.cuda.synchronize()
+    _assert_same_frame(ref, got, sc.params.n_samples, sc.params.K)
+
+
+def test_autotuner_choice_changes_no_result(tmp_path, views):
+    """The tuner's choice (a reduced space here) is cached and reloaded, and
+    the frame it renders equals the default frame bit for bit."""
     import torch
     from paper_2404_14044_amd import hashpoint as hp
     from paper_2404_14044_amd.autotune import Autotuner
-    sc = scenes.objects_1m(n=100_000, res=128)
+    from paper_2404_14044_amd.batched import BatchedRenderer
+    sc = views
     xyz, feat, mlp = _setup(sc)
+    space = {"layout": (0, 2), "search_chunk": (1, 4), "window_shape": (0, 1),
+             "render_rays": (16, 32), "render_blocks": (0, 64)}
     tuner = Autotuner(str(tmp_path / "tune.json"))
-    p = tuner.tune(xyz, sc.cams, sc.params, reps=1, chunks=(1, 4, 16), blocks=(2048, 8192))
-    assert p.layout in (0, 1) and p.search_chunk in (1, 4, 16)
-    again = Autotuner(str(tmp_path / "tune.json")).tune(xyz, sc.cams, sc.params)
-    assert (again.layout, again.search_chunk, again.search_blocks) == \
-        (p.layout, p.search_chunk, p.search_blocks)
-    a = hp.search_sample(hp.build_table(xyz, sc.cams, sc.params), sc.params)
-    b = hp.search_sample(hp.build_table(xyz, sc.cams, p), p)
+    p = tuner.tune(xyz, feat, mlp, sc.cams, sc.params, hp.HP_BF16, reps=1, space=space)
+    ent = tuner.entry(xyz, sc.cams, sc.params, hp.HP_BF16)
+    assert ent["ms"] > 0 and ent["default_ms"] > 0 and len(ent["trials"]) >= 6
+    again = Autotuner(str(tmp_path / "tune.json")).tune(xyz, feat, mlp, sc.cams, sc.params,
+                                                        hp.HP_BF16)
+    assert again == p
+    br = BatchedRenderer(xyz, feat, mlp, sc.cams, sc.params, hp.HP_BF16,
+                         tuner=Autotuner(str(tmp_path / "tune.json")))
+    assert br.params == p
+    ref = _frame(xyz, feat, mlp, sc.cams, sc.params, hp.HP_BF16)
+    got = _frame(xyz, feat, mlp, sc.cams, p, hp.HP_BF16)
     torch.cuda.synchronize()
-    for k in ("n_sel", "primary", "n_nbr", "flags"):
-        assert np.array_equal(host(a[k]), host(b[k]))
+    _assert_same_frame(ref, got, sc.params.n_samples, sc.params.K)
 
 
 def test_batched_16_full_size_matches_oracle():

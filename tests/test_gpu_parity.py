@@ -207,9 +207,11 @@ def test_room_64x64_crop(room_run):
     _room_check(sc, out, pix.astype(np.int32))
 
 
-def test_sphere_plane_tiled_layout(sphere_plane):
+@pytest.mark.parametrize("layout", [1, 2])
+def test_sphere_plane_tiled_layout(sphere_plane, layout):
+    """8x8 tiles, row-major or Z-order inside: exact outputs as row-major."""
     sc = sphere_plane
-    p = sc.params.replace(layout=1)
+    p = sc.params.replace(layout=layout)
     out = gpu_forward(sc, params=p)
     compare_exact(sc, out["samples"], _all_pix(sc.cams[0]), params=p)
 
