@@ -343,7 +343,8 @@ void or_exact(const float *pc, int64_t n, const orc_camera *cam, const orc_param
         float *tv = (float *)malloc((size_t)(n ? n : 1) * sizeof(float));
         int64_t cap = 1024;
         kv_ent *nb = (kv_ent *)malloc((size_t)cap * sizeof(kv_ent));
-        kv_ent *kn = (kv_ent *)malloc((size_t)(M > 0 ? M : 1) * sizeof(kv_ent));
+        int64_t kn_cap = M > 0 ? M : 1;
+        kv_ent *kn = (kv_ent *)malloc((size_t)kn_cap * sizeof(kv_ent));
 #pragma omp for schedule(dynamic, 16)
         for (int64_t r = 0; r < n_rays; ++r) {
             const int32_t u = pix[r] % cam->W, v = pix[r] / cam->W;
@@ -386,24 +387,30 @@ void or_exact(const float *pc, int64_t n, const orc_camera *cam, const orc_param
             if (p->sampler == ORC_SAMPLER_MS) {
                 /* Multi-surface sampling (Sec. 3.5, the volume-rendering baseline */
                 /* it is compared with): uniform positions t_k = t_near + (k + 1/2) */
-                /* step along the ray; a position lies on a surface when some point */
-                /* of N(ray) is within R_k = rho(t_k) of it, and every such position */
-                /* becomes a sample (in depth order, up to n_samples) with its K     */
-                /* nearest points of N(ray) within R_k.  Reading: the primary       */
-                /* surface is the nearest point of the first sample.                 */
+                /* step along the ray, each with a radius search around it: a      */
+                /* position lies on a surface when some neighbour of the ray (any  */
+                /* of them: the m_cap cut of N(ray) does not apply) is within      */
+                /* R_k = rho(t_k) of it, and every such position becomes a sample  */
+                /* (in depth order, up to n_samples) with its K nearest such        */
+                /* neighbours.  Reading: the primary surface is the nearest point  */
+                /* of the first sample.                                             */
                 const float step = (p->t_far - p->t_near) / (float)p->ms_steps;
+                if (cnt > kn_cap) {
+                    kn_cap = cnt;
+                    kn = (kv_ent *)realloc(kn, (size_t)kn_cap * sizeof(kv_ent));
+                }
                 for (int k = 0; k < p->ms_steps && sel < S; ++k) {
                     const float tk = fmaf((float)k + 0.5f, step, p->t_near);
                     const float Rk = rho_of(p, kap, tk);
                     const float R2 = Rk * Rk;
-                    int kc = 0;
-                    for (int i = 0; i < m; ++i) {
+                    int64_t kc = 0;
+                    for (int64_t i = 0; i < cnt; ++i) {
                         float dd = dist2_at(pc + 3 * (int64_t)nb[i].idx, d, tk);
                         if (dd <= R2) { kn[kc].key = dd; kn[kc].idx = nb[i].idx; ++kc; }
                     }
                     if (kc == 0) continue;
                     qsort(kn, (size_t)kc, sizeof(kv_ent), cmp_kv);
-                    const int kj = kc < K ? kc : K;
+                    const int kj = kc < K ? (int)kc : K;
                     const int64_t row = r * S + sel;
                     smp_t[row] = tk;
                     knn_cnt[row] = kj;

@@ -3,8 +3,10 @@ baseline of Sec. 3.5 that primary-surface sampling is compared with).
 
 Checks: the closed form of one point on the axis ray (a position is kept iff
 it is within R of the point), two surfaces both sampled where the primary-
-surface walk stops at the first, the uniform grid of sample positions,
-agreement with an independent binary64 test of every position, invariants.
+surface walk stops at the first, a second surface sampled although the
+ray's first 64 neighbours (the list cut) all lie on the first, the uniform
+grid of sample positions, agreement with an independent binary64 test of
+every position against all of the ray's neighbours, invariants.
 """
 import numpy as np
 
@@ -63,38 +65,73 @@ def test_two_surfaces_both_sampled(orc):
 
 
 def test_positions_match_binary64(orc, rng):
+    """Every position against an independent binary64 computation of the
+    ray's neighbours (all of them: the list cut m_cap = 8 is far below the
+    neighbour counts here, and must not limit the positions' searches)."""
     cam = scenes.pinhole(10, 8, 50.0, np.eye(3), np.zeros(3))
     xyz = np.concatenate([rng.uniform(-1, 1, size=(3000, 2)), rng.uniform(1.2, 3.2, size=(3000, 1))],
                          axis=1).astype(np.float32)
-    p = scenes.default_params(0.06, 1.0, 3.5, K=4, S=64).replace(sampler=1, ms_steps=200, m_cap=64)
+    p = scenes.default_params(0.06, 1.0, 3.5, K=4, S=64).replace(sampler=1, ms_steps=200, m_cap=8)
     pc = orc.to_camera(xyz, cam)
     ex = orc.exact(pc, cam, p)
+    assert ex["flags"].sum() > 20          # most rays have more neighbours than the cut
     tk = _grid(p).astype(np.float64)
     x = pc.astype(np.float64)
+    r0, tn, tf = float(p.radius), float(p.t_near), float(p.t_far)
     checked = 0
     for r in range(cam.W * cam.H):
-        m = ex["n_nbr"][r]
-        nbr = ex["nbr_idx"][r, :m]
         u, v = r % cam.W, r // cam.W
         a, b = (u + 0.5 - cam.cx) / cam.fx, (v + 0.5 - cam.cy) / cam.fy
         d = np.array([a, b, 1.0]) / np.sqrt(1 + a * a + b * b)
-        if m == 0:
+        t = x @ d
+        e = np.linalg.norm(x - t[:, None] * d[None, :], axis=1)
+        sure_nb = (x[:, 2] > 0) & (t >= tn * (1 + 1e-6)) & (t <= tf * (1 - 1e-6)) & (e <= r0 * (1 - 1e-5))
+        maybe_nb = (x[:, 2] > 0) & (t >= tn * (1 - 1e-6)) & (t <= tf * (1 + 1e-6)) & (e <= r0 * (1 + 1e-5))
+        if not maybe_nb.any():
             assert ex["n_sel"][r] == 0
             continue
-        # binary64 distance from every position to every listed point
-        dist = np.linalg.norm(x[nbr][None, :, :] - tk[:, None, None] * d[None, None, :], axis=2)
-        near = dist.min(axis=1)
-        sure = near <= p.radius * (1 - 1e-5)
-        maybe = near <= p.radius * (1 + 1e-5)
+        # binary64 distance from every position to every (possible) neighbour
+        dist = np.linalg.norm(x[maybe_nb][None, :, :] - tk[:, None, None] * d[None, None, :], axis=2)
+        sure_pt = sure_nb[maybe_nb]
+        sure = ((dist <= r0 * (1 - 1e-5)) & sure_pt[None, :]).any(axis=1)
+        maybe = (dist <= r0 * (1 + 1e-5)).any(axis=1)
         kept = set(np.round((ex["t"][r, :ex["n_sel"][r]] - p.t_near) / (tk[1] - tk[0]) - 0.5)
                    .astype(int).tolist())
         want = np.flatnonzero(sure)
-        want = want[:p.n_samples] if want.size > p.n_samples else want
         if ex["n_sel"][r] < p.n_samples:
             assert set(want.tolist()) <= kept
             assert kept <= set(np.flatnonzero(maybe).tolist())
         checked += ex["n_sel"][r]
     assert checked > 200
+
+
+def test_second_surface_beyond_the_list_cut(orc, rng):
+    """A ray whose first surface alone holds 200 neighbours (m_cap = 64): the
+    list N(ray) ends inside that surface, yet the positions at the second
+    surface, 4 units further, are still samples, with their own points as
+    nearest neighbours (the paper's multi-surface baseline samples every
+    surface the ray crosses)."""
+    cam = _axis_cam()
+    ang = rng.uniform(0, 2 * np.pi, 200)
+    rad = 0.2 * np.sqrt(rng.uniform(0, 1, 200))
+    first = np.stack([rad * np.cos(ang), rad * np.sin(ang), rng.uniform(2.95, 3.05, 200)], 1)
+    second = np.stack([np.zeros(5), np.linspace(-0.1, 0.1, 5), np.full(5, 7.0)], 1)
+    pc = np.concatenate([first, second]).astype(np.float32)
+    ex = orc.exact(pc, cam, _ms(), [0])
+    assert ex["flags"][0] == 1 and ex["n_nbr"][0] == 64
+    assert set(ex["nbr_idx"][0].tolist()) <= set(range(200))   # the cut list: first surface only
+    ns = ex["n_sel"][0]
+    t = ex["t"][0, :ns]
+    far = np.abs(t - 7.0) <= 0.25
+    assert far.sum() >= 2 and np.any(np.abs(t - 3.0) <= 0.3)
+    idx = ex["knn_idx"][0, :ns][far]
+    assert np.all((idx[:, 0] >= 200) & (idx[:, 0] < 205))
+    # and exactly the positions within R of some far point, as in the closed form
+    tk = _grid(_ms())
+    d_far = np.abs(tk.astype(np.float64)[:, None] - 7.0)
+    e_far = np.abs(np.linspace(-0.1, 0.1, 5))[None, :]
+    want = np.flatnonzero((np.sqrt(d_far ** 2 + e_far ** 2) <= 0.25).any(axis=1))
+    assert np.array_equal(t[far], tk[want])
 
 
 def test_invariants(orc, rng):
