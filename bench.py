@@ -106,7 +106,7 @@ def main():
                     help="skip every extra leg (batched views, training step, ...)")
     ap.add_argument("--legs", default="all",
                     help="comma-separated extra legs to run (batched, train, radius, samplers, "
-                         "knp, fused, room, sweep) or 'all'")
+                         "samplers_room, knp, fused, room, sweep) or 'all'")
     ap.add_argument("--summarize", nargs="+", metavar="DIR",
                     help="print the markdown summary of rocprofv3 output directories "
                          "(kernel stats and counter collections) and exit; no GPU used")
@@ -266,7 +266,8 @@ def main():
         legs = [("batched", "batched_16", lambda: batched_leg(sc)),
                 ("train", "train_4x400", lambda: train_leg(sc)),
                 ("radius", "radius_modes", lambda: radius_modes_leg(sc)),
-                ("samplers", "samplers", lambda: sampler_leg(sc)),
+                ("samplers", "samplers", lambda: sampler_leg(sc, ms_steps=400)),
+                ("samplers_room", "samplers_room_5m", room_sampler_leg),
                 ("knp", "knp", lambda: knp_leg(sc)),
                 ("fused", "fused", lambda: fused_leg(sc)),
                 ("room", "room_5m", room_leg),
@@ -469,13 +470,14 @@ def radius_modes_leg(sc, reps=5):
     return out
 
 
-def sampler_leg(sc, reps=5):
+def sampler_leg(sc, ms_steps, reps=5):
     """Primary-surface walk at several gamma (Sec. 3.3 and the supplement's
     gamma sweep: smaller gamma samples further past the primary surface) and
-    the uniform multi-surface baseline (Sec. 3.5; 400 positions over
-    [t_near, t_far], one per r), all with up to 64 samples per ray except the
-    default gamma = 0.9, S = 16 workload.  Build + search/sample + render
-    (BF16) on the same view."""
+    the uniform multi-surface baseline (Sec. 3.5; ms_steps positions over
+    [t_near, t_far], about one per search radius, each with its own radius
+    search over all of the ray's neighbours), all with up to 64 samples per
+    ray except the workload's own gamma = 0.9, S = 16.  Build + search/sample
+    + render (BF16) on the same view."""
     import torch
     from paper_2404_14044_amd import hashpoint as hp
     dev = torch.device("cuda:0")
@@ -485,11 +487,12 @@ def sampler_leg(sc, reps=5):
     feat = torch.from_numpy(sc.feat).to(dev)
     mlp = hp.to_device_mlp(sc.mlp, dev)
     base = sc.params
-    runs = {"ps_gamma0.9_S16": base}
+    runs = {f"ps_gamma0.9_S{base.n_samples}": base}
     for gm in (0.9, 0.5, 0.1, 0.01):
         runs[f"ps_gamma{gm}_S64"] = base.replace(gamma=float(np.float32(gm)), n_samples=64)
-    runs["ms_400_S64"] = base.replace(sampler=hp.HP_SAMPLER_MS, ms_steps=400, n_samples=64)
-    out = {}
+    ms_name = f"ms_{ms_steps}_S64"
+    runs[ms_name] = base.replace(sampler=hp.HP_SAMPLER_MS, ms_steps=ms_steps, n_samples=64)
+    out = {"rays": R, "points": int(xyz.shape[0])}
     ws = torch.empty(hp.table_workspace(xyz.shape[0], [cam], base), dtype=torch.uint8, device=dev)
     tab = hp.build_table(xyz, [cam], base, ws=ws)
     t_build = _time_ms(lambda: hp.build_table(xyz, [cam], base, ws=ws), reps)
@@ -506,10 +509,17 @@ def sampler_leg(sc, reps=5):
                      "samples_per_hit_ray": float(ns.sum().item()) / max(hit, 1),
                      "hit_rays": hit}
         del smp, o
-    ms = out["ms_400_S64"]["total_ms"]
-    for name in out:
+    ms = out[ms_name]["total_ms"]
+    for name in runs:
         out[name]["speedup_vs_ms"] = ms / out[name]["total_ms"]
     return out
+
+
+def room_sampler_leg(reps=3):
+    """The sampler comparison on the scene-scale room (1008 x 756, 5M points,
+    rays crossing 2-8 surfaces; MS positions every 0.02 = r over [0.5, 21])."""
+    from paper_2404_14044_amd import scenes
+    return sampler_leg(scenes.room_5m(), ms_steps=1025, reps=reps)
 
 
 def knp_leg(sc, reps=5):

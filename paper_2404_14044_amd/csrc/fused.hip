@@ -50,7 +50,7 @@ __device__ __forceinline__ void fused_body(const SearchCtx &c, const FusedArgs &
             }
         };
         int n;
-        if constexpr (MS) n = uniform_samples<KT>(c, g, sh.s, top, m, prim, emit);
+        if constexpr (MS) n = uniform_samples<KT>(c, g, sh.s, top, count, prim, emit);
         else n = walk_candidates<KT>(c, g, sh.s, top, m, prim, emit);
         lds_sync();
         if (n > 0) {

@@ -499,12 +499,14 @@ __device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, RayGeom 
 
 // Search one ray.  Returns, in `top` (one key per lane, ascending), the
 // 64 smallest (t, index) keys of the ray's neighbours (missing = ~0), and
-// the total neighbour count.
+// the total neighbour count; with `lo`, only the keys >= lo count (the
+// multi-surface sampler walks a ray's neighbours 64 at a time this way).
 // BY_E2 orders the kept neighbours by (squared distance to the ray, index)
 // instead of (t, index): the K nearest points to the ray (K-NP, Eq. 1).
 template <bool BY_E2 = false>
 __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayGeom &g,
-                                                  SearchLds &sh, uint64_t &top, int &count)
+                                                  SearchLds &sh, uint64_t &top, int &count,
+                                                  uint64_t lo = 0)
 {
     const int l = lane_id();
     const ViewK &V = c.views[g.vi];
@@ -588,8 +590,9 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
                     key = ((uint64_t)__float_as_uint(BY_E2 ? e2 : t) << 32) | __float_as_uint(P.w);
                 }
             }
-            count += popc64(ballot(pass));
-            const bool keep = pass && key < tau;
+            const bool live = pass && key >= lo;
+            count += popc64(ballot(live));
+            const bool keep = live && key < tau;
             const uint64_t km = ballot(keep);
             if (keep) sh.pend[npend + rank_below(km)] = key;
             npend += popc64(km);
@@ -1128,85 +1131,104 @@ __device__ __forceinline__ int wave_min_i32(int v)
     return v;
 }
 
-// Uniform multi-surface sampling on the same neighbour list (the baseline of
-// Sec. 3.5): positions t_k = t_near + (k + 1/2) step, k < ms_steps; a position
-// is a sample when some listed point lies within R_k = rho(t_k) of it (the
-// exact test), in depth order up to S, with its K nearest listed points.
-// Only positions near a listed point can pass: |t_k - t_i| <= dist and
-// rho(t_k) <= rho(t_i) + s |t_k - t_i| (s: the slope of rho), so
-// |t_k - t_i| <= rho(t_i) / (1 - s); lane i turns that into a range of k
-// (one extra position on each side), and batches of 16 positions jump
-// from range to range.  emit() as for the candidate walk; first_idx is the
-// nearest point of the first sample.
+// Uniform multi-surface sampling (the baseline of Sec. 3.5): positions
+// t_k = t_near + (k + 1/2) step, k < ms_steps, each with a radius search: a
+// position is a sample when some neighbour of the ray (any of them, not only
+// the first m_cap) lies within R_k = rho(t_k) of it (the exact test), in
+// depth order up to S, with its K nearest such neighbours.  The neighbours
+// are walked in depth order 64 at a time: a slab is the 64 smallest keys at
+// or above a bound (search_neighbours with `lo`), kept sorted in the LDS.
+// Positions go 16 at a time, one per quad (lanes 4 g .. 4 g + 3), each
+// keeping its K nearest over the slabs that reach its window |t - t_k| <= R_k
+// (distance >= |t_i - t_k| up to rounding); a batch starts from the slab of
+// keys at or above its first window and jumps over positions that no
+// neighbour can reach.  emit() as for the candidate walk; first_idx is the
+// nearest point of the first sample.  top, count: the ray's first slab and
+// neighbour count, as search_neighbours returned them.
 template <int KT, typename Emit>
 __device__ __forceinline__ int uniform_samples(const SearchCtx &c, const RayGeom &g, SearchLds &sh,
-                                               uint64_t top, int m, int &first_idx, Emit emit)
+                                               uint64_t top, int count, int &first_idx, Emit emit)
 {
     const int l = lane_id();
-    lds_sync();
-    if (l < m) {
-        const int idxj = (int)(uint32_t)top;
-        const int slot = c.slot_of[(int64_t)g.vi * c.n_points + idxj];
-        sh.nb_p[l] = c.pts[slot];
-        sh.nb_t[l] = __uint_as_float((uint32_t)(top >> 32));
-    }
-    lds_sync();
     first_idx = -1;
-    if (m == 0) return 0;
-    constexpr int NONE = 0x7fffffff;
+    if (count == 0) return 0;
     const int nk = c.ms_steps;
     const float step = (c.t_far - c.t_near) / (float)nk;
-    const float slope = c.rmode == HP_RADIUS_LINEAR ? c.radius * c.inv_tref : g.kappa;
-    int klo = NONE, khi = -1;
-    if (l < m) {
-        klo = 0;
-        khi = nk - 1;
-        if (slope < 0.999f) {
-            const float ti = sh.nb_t[l];
-            const float B = (rho_at(c, g, ti) / (1.0f - slope)) * 1.001f + ti * 4e-6f + 1e-6f;
-            float flo = (ti - B - c.t_near) / step - 0.5f;
-            float fhi = (ti + B - c.t_near) / step - 0.5f;
-            flo = __builtin_fminf(__builtin_fmaxf(flo, -2.0f), (float)nk + 2.0f);
-            fhi = __builtin_fminf(__builtin_fmaxf(fhi, -2.0f), (float)nk + 2.0f);
-            klo = max((int)__builtin_floorf(flo) - 1, 0);
-            khi = min((int)__builtin_ceilf(fhi) + 1, nk - 1);
+    auto pos_t = [&](int k) { return fma_rn((float)k + 0.5f, step, c.t_near); };
+    // |t_i - t_k| > span implies dist^2 > R_k^2 (margins above rounding)
+    auto pos_span = [&](float tk) { return rho_at(c, g, tk) * 1.001f + tk * 4e-6f + 1e-7f; };
+    // every window ends within smax of its position (rho grows with t)
+    const float smax = pos_span(c.t_far);
+    // a position before this one cannot reach a key at t (one spare)
+    auto first_reaching = [&](float t) -> int {
+        float f = (t - smax - c.t_near) / step - 0.5f;
+        f = __builtin_fminf(__builtin_fmaxf(f, -2.0f), (float)nk + 2.0f);
+        return max((int)__builtin_floorf(f) - 1, 0);
+    };
+    uint64_t keys = top;  // the current slab, one key per lane
+    int n = count < WAVE ? count : WAVE, rest = count;
+    auto load_slab = [&]() {
+        lds_sync();
+        if (l < n) {
+            const int idxj = (int)(uint32_t)keys;
+            const int slot = c.slot_of[(int64_t)g.vi * c.n_points + idxj];
+            sh.nb_p[l] = c.pts[slot];
+            sh.nb_t[l] = __uint_as_float((uint32_t)(keys >> 32));
         }
-        if (klo > khi) {
-            klo = NONE;
-            khi = -1;
+        lds_sync();
+    };
+    // first slab entry with t >= tlo (n if none)
+    auto slab_lower = [&](float tlo) {
+        int a = 0, e = n;
+        while (a < e) {
+            const int mid = (a + e) >> 1;
+            if (sh.nb_t[mid] < tlo) a = mid + 1;
+            else e = mid;
         }
-    }
+        return a;
+    };
+    load_slab();
     int sel = 0;
-    int b = wave_min_i32(klo);
     const int gp = l >> 2;
+    int b = first_reaching(sh.nb_t[0]);
     while (b < nk && sel < c.S) {
         const int k = b + gp;
         const bool active = k < nk;
-        float tk = 0.0f, R2 = 0.0f;
-        int wlo = 0, whi = 0;
+        float tk = 0.0f, R2 = 0.0f, span = 0.0f;
         if (active) {
-            tk = fma_rn((float)k + 0.5f, step, c.t_near);
+            tk = pos_t(k);
             const float Rk = rho_at(c, g, tk);
             R2 = Rk * Rk;
-            const float span = Rk * 1.001f + tk * 4e-6f + 1e-7f;
-            const float tlo = tk - span, thi = tk + span;
-            int a = 0, e = m;
-            while (a < e) {
-                const int mid = (a + e) >> 1;
-                if (sh.nb_t[mid] < tlo) a = mid + 1;
-                else e = mid;
-            }
-            wlo = a;
-            e = m;
-            while (a < e) {
-                const int mid = (a + e) >> 1;
-                if (sh.nb_t[mid] <= thi) a = mid + 1;
-                else e = mid;
-            }
-            whi = a;
+            span = pos_span(tk);
         }
+        const float tl = pos_t(min(b + 15, nk - 1));
+        const float t_end = tl + pos_span(tl);  // where the batch's last window ends
         uint64_t kd[KT];
-        knn_window<KT>(g, sh, tk, R2, wlo, whi, kd);
+#pragma unroll
+        for (int q = 0; q < KT; ++q) kd[q] = KEY_NONE;
+        for (;;) {
+            int wlo = 0, whi = 0;
+            if (active) {
+                wlo = slab_lower(tk - span);
+                whi = wlo;
+                int e = n;  // first entry with t > tk + span
+                while (whi < e) {
+                    const int mid = (whi + e) >> 1;
+                    if (sh.nb_t[mid] <= tk + span) whi = mid + 1;
+                    else e = mid;
+                }
+            }
+            uint64_t part[KT];
+            knn_window<KT>(g, sh, tk, R2, wlo, whi, part);
+            merge_low<KT>(kd, part);
+            // the next slab, unless this one held every remaining key or
+            // ends beyond the last window of the batch
+            if (rest <= n || sh.nb_t[n - 1] > t_end) break;
+            const uint64_t last = readlane_u64(keys, n - 1);
+            search_neighbours(c, g, sh, keys, rest, last + 1ull);
+            n = rest < WAVE ? rest : WAVE;
+            load_slab();
+        }
         const bool kept = active && kd[0] != KEY_NONE;
         const uint64_t km = ballot(kept && (l & 3) == 0);  // bit 4 p: position b + p kept
         const int room = c.S - sel;
@@ -1224,9 +1246,22 @@ __device__ __forceinline__ int uniform_samples(const SearchCtx &c, const RayGeom
             const int nkept = popc64(km);
             sel += nkept < room ? nkept : room;
         }
-        // next batch: the first position >= b + 16 that some range covers
-        const int nb = b + 16;
-        b = wave_min_i32(khi >= nb ? (klo > nb ? klo : nb) : NONE);
+        // the next batch starts from the keys at or above its first window
+        b += 16;
+        if (b >= nk || sel >= c.S) break;
+        const float tb = pos_t(b);
+        const float tlo = tb - pos_span(tb);
+        if (!(sh.nb_t[0] <= tlo && rest <= n)) {
+            // (the current slab does not hold every key from tlo on)
+            const uint64_t lo_key = tlo > 0.0f ? ((uint64_t)__float_as_uint(tlo) << 32) : 0ull;
+            search_neighbours(c, g, sh, keys, rest, lo_key);
+            if (rest == 0) break;
+            n = rest < WAVE ? rest : WAVE;
+            load_slab();
+        }
+        const int j = slab_lower(tlo);
+        if (j >= n) break;  // no key at or beyond the next window
+        b = max(b, first_reaching(sh.nb_t[j]));
     }
     return sel;
 }

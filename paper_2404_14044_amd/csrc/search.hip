@@ -34,7 +34,7 @@ __device__ __forceinline__ void search_sample_body(const SearchCtx &c, const Sam
             }
         };
         int nsel;
-        if constexpr (MS) nsel = uniform_samples<KT>(c, g, sh, top, m, prim, emit);
+        if constexpr (MS) nsel = uniform_samples<KT>(c, g, sh, top, count, prim, emit);
         else nsel = walk_candidates<KT>(c, g, sh, top, m, prim, emit);
         if (l == 0) {
             o.n_sel[ray] = nsel;

@@ -96,6 +96,36 @@ def test_sphere_plane_multi_surface(sphere_plane):
     assert (ex["n_sel"] > 4).sum() > 300
 
 
+def test_multi_surface_beyond_the_list_cut():
+    """Multi-surface sampling where rays have far more neighbours than the
+    list cut: a dense slab of 20,000 points at depth 2 in front of a plane at
+    depth 3.5, and the adversarial scene (a pixel whose ray grazes 5,000
+    points, so single positions see more than 64).  Every ray's samples,
+    their nearest neighbours and distances bit for bit; rays that overflow
+    the cut still sample the surface behind it."""
+    rng = np.random.default_rng(17)
+    cam = scenes.pinhole(32, 32, 40.0, np.eye(3), np.zeros(3))
+    p = scenes.default_params(0.03, 1.0, 5.0, K=8, S=32).replace(sampler=1, ms_steps=500)
+    slab = np.concatenate([rng.uniform(-0.4, 0.4, (20000, 2)), rng.uniform(1.97, 2.03, (20000, 1))], 1)
+    back = np.concatenate([rng.uniform(-1.0, 1.0, (6000, 2)), np.full((6000, 1), 3.5)], 1)
+    xyz = np.concatenate([slab, back]).astype(np.float32)
+    feat = rng.normal(size=(xyz.shape[0], 32)).astype(np.float32)
+    sc = scenes.Scene("slab", xyz, feat, [cam], p, scenes.make_mlp(5))
+    from paper_2404_14044_amd import hashpoint as hp
+    out = gpu_forward(sc, precision=hp.HP_FP32)
+    ex = compare_exact(sc, out["samples"], _all_pix(cam))
+    over = ex["flags"] > 0
+    assert over.sum() > 100
+    behind = np.array([np.any(np.abs(ex["t"][r, :ex["n_sel"][r]] - 3.5) < 0.2) for r in range(len(over))])
+    assert (over & behind).sum() > 50
+    err = render_error(sc, out["render"], ex, _all_pix(cam))
+    assert_render_error(err, 0, p)
+    adv = adversarial_scene()
+    pa = adv.params.replace(sampler=1, ms_steps=300, n_samples=64)
+    out = gpu_forward(adv, params=pa)
+    compare_exact(adv, out["samples"], _all_pix(adv.cams[0]), params=pa)
+
+
 @pytest.mark.parametrize("K", [1, 3, 5, 12, 24, 32])
 def test_sphere_plane_list_lengths(sphere_plane, K):
     """K away from the register-list lengths 4 / 8 / 16 / 32: only the first K
