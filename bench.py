@@ -247,7 +247,7 @@ def main():
                 "valu_insts": ks["SQ_INSTS_VALU"], "salu_insts": ks.get("SQ_INSTS_SALU"),
                 "valu_issue_frac": ks["SQ_INSTS_VALU"] / slots,
                 "valu_insts_per_ray_with_neighbours": ks["SQ_INSTS_VALU"] / max(hit_rays, 1)}
-        kr = counters["kernels"].get("k_render_bf16")
+        kr = counters["kernels"].get("k_render_bf16<32,false>")
         if kr and "SQ_INSTS_MFMA" in kr:
             result["rooflines_other"]["render_bf16"]["mfma_insts"] = kr["SQ_INSTS_MFMA"]
         result["roofline"]["counters_from"] = os.path.relpath(COUNTERS_FILE, ROOT)
@@ -288,6 +288,28 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def kernel_key(name):
+    """Short name of a kernel as the profiler reports it: no return type,
+    namespace or argument list; template arguments kept, without spaces
+    (e.g. "k_render_bf16<32,false>")."""
+    name = name.strip()
+    if name.startswith("void "):
+        name = name[5:]
+    depth, cut = 0, len(name)
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = i
+            break
+    name = name[:cut]
+    head, sep, tmpl = name.partition("<")
+    head = head.split("::")[-1]
+    return (head + sep + tmpl).replace(" ", "")
+
+
 def summarize_profiles(dirs):
     """Markdown summary of rocprofv3 runs: kernel statistics (calls, average
     duration) from *_kernel_stats.csv and, from *_counter_collection.csv,
@@ -302,19 +324,19 @@ def summarize_profiles(dirs):
                 if f.endswith("kernel_stats.csv"):
                     with open(path) as fh:
                         for row in csv.DictReader(fh):
-                            stats[row["Name"]] = {"calls": int(row["Calls"]),
+                            stats[kernel_key(row["Name"])] = {"calls": int(row["Calls"]),
                                                   "avg_us": float(row["AverageNs"]) / 1e3,
                                                   "total_us": float(row["TotalDurationNs"]) / 1e3}
                 elif f.endswith("counter_collection.csv"):
                     with open(path) as fh:
                         for row in csv.DictReader(fh):
-                            k = row["Kernel_Name"].split("(")[0].strip()
+                            k = kernel_key(row["Kernel_Name"])
                             ent = ctr.setdefault(k, {}).setdefault(row["Counter_Name"], {})
                             did = (path, row["Dispatch_Id"])
                             ent[did] = ent.get(did, 0.0) + float(row["Counter_Value"])
     out = ["| kernel | calls | avg µs | total µs |", "|---|---|---|---|"]
     for name, v in sorted(stats.items(), key=lambda kv: -kv[1]["total_us"]):
-        out.append(f"| `{name.split('(')[0][:60]}` | {v['calls']} | {v['avg_us']:.1f} | "
+        out.append(f"| `{name[:60]}` | {v['calls']} | {v['avg_us']:.1f} | "
                    f"{v['total_us']:.1f} |")
     names = sorted({c for k in ctr.values() for c in k})
     out += ["", "| kernel | " + " | ".join(names) + " |", "|---" * (len(names) + 1) + "|"]
