@@ -51,7 +51,7 @@ def render_algorithmic_bytes(s_tot, K, n_used, n_rays, C=32):
 MLP_FLOP_PER_SAMPLE = 2 * (32 * 64 + 64 * 64 + 64 * 4)   # 12,800
 CHIP_CUS, CHIP_GHZ = 256, 2.4
 MFMA_BF16_PEAK_TFLOPS = 2500.0
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_objects_1m.md")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "forward_path_objects_1m.md")
 COUNTER_SOURCES = ("paper_2404_14044_amd/csrc", "include")
 
 
