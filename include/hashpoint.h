@@ -173,8 +173,9 @@ typedef struct hp_view_info {
  *  pts[4 * slot + 0..3]: camera-space x, y, z and the point index (as int32
  *      bits), ordered by bucket, then z, then point index.
  *  perm[slot]: the point index of each slot.
- *  slot_of[view * n_points + i]: slot of point i in that view (only defined
- *      for inserted points).
+ *  pcam[4 * (view * n_points + i) + 0..3]: camera-space x, y, z of point i in
+ *      that view and its index (as pts; only defined for inserted points),
+ *      in point order: the search finds a listed point's coordinates here.
  *  bucket_z, cell_zmin: depth summaries used to bound each ray's window. */
 typedef struct hp_table {
     int32_t n_views;
@@ -185,7 +186,7 @@ typedef struct hp_table {
     int32_t *offsets;
     float *pts;
     int32_t *perm;
-    int32_t *slot_of;
+    float *pcam;
     float *bucket_z;      /* [n_buckets] depth of each bucket's first point, +inf if empty */
     uint32_t *cell_zmin;  /* [n_cells] min depth (binary32 bits) of 8x8-bucket cells      */
     int64_t n_cells;

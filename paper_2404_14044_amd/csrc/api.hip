@@ -285,7 +285,7 @@ hp_status hp_build_table(const float *xyz, int64_t n, const hp_camera *cams, int
     out->offsets = tw.offsets;
     out->pts = reinterpret_cast<float *>(tw.pts);
     out->perm = tw.perm;
-    out->slot_of = tw.slot_of;
+    out->pcam = reinterpret_cast<float *>(tw.pcam);
     out->bucket_z = tw.bucket_z;
     out->cell_zmin = tw.cell_zmin;
     out->n_cells = geo.n_cells;
@@ -302,7 +302,7 @@ static hp_status make_ctx(const hp_table *tab, const hp_camera *cams, int32_t n_
     if (p->layout != tab->layout || table_key(cams, n_views, *p) != tab->build_key)
         return HP_E_INVALID;
     if (p->K > HP_MAX_K) return HP_E_UNSUPPORTED;
-    if (!tab->offsets || !tab->pts || !tab->slot_of || !tab->scratch || !tab->bucket_z ||
+    if (!tab->offsets || !tab->pts || !tab->pcam || !tab->scratch || !tab->bucket_z ||
         !tab->cell_zmin)
         return HP_E_INVALID;
     Geometry geo;
@@ -315,7 +315,7 @@ static hp_status make_ctx(const hp_table *tab, const hp_camera *cams, int32_t n_
             return HP_E_INVALID;
     c.offsets = tab->offsets;
     c.pts = reinterpret_cast<const float4 *>(tab->pts);
-    c.slot_of = tab->slot_of;
+    c.pcam = reinterpret_cast<const float4 *>(tab->pcam);
     c.bucket_z = tab->bucket_z;
     c.cell_zmin = tab->cell_zmin;
     c.views = reinterpret_cast<const hp::ViewK *>(tab->scratch);

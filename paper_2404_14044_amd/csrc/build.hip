@@ -4,15 +4,15 @@
 // point at offset + rank, and order each bucket by depth.
 //
 // Passes (each a coalesced sweep except the scatter and the bucket sorts):
-//   k_project      (view, point)  -> (bucket, z), a per-bucket count and the
-//                  point's arrival rank in its bucket (kept in slot_of until
-//                  k_materialize overwrites it)
+//   k_project      (view, point)  -> (bucket, z), the camera-space point (pcam),
+//                  a per-bucket count and the point's arrival rank in its
+//                  bucket (kept in perm until k_materialize overwrites it)
 //   k_scan_*       counts         -> exclusive offsets, three passes
 //   k_scatter      (view, point)  -> 64-bit key (z bits, point index) per slot
 //   k_sort_small   one lane per bucket of at most 16 points, register network
-//   k_sort_mid     one wave per bucket of 17..64 points, register bitonic
+//   k_sort_mid     one wave per bucket of 17..128 points, register bitonic
 //   k_sort_big     one workgroup per larger bucket, bitonic in LDS or global
-//   k_materialize  one lane per slot: camera-space point, perm, slot_of
+//   k_materialize  one lane per slot: camera-space point and index (from pcam)
 #include "hp_device.hpp"
 #include "hp_kernels.hpp"
 #include "hp_search.hpp"
@@ -33,32 +33,55 @@ __global__ void k_fill_i32(int32_t *p, int32_t val, int64_t n)
         p[i] = val;
 }
 
-// grid: (ceil(n / 256), n_views)
+// grid: (ceil(n / (256 PROJ_PER)), n_views).  Each thread takes PROJ_PER
+// points strided by the workgroup size, so that its count atomics (whose
+// returned rank the point needs) are in flight together: one at a time, the
+// wave would wait out the device-scope round trip of each.
+constexpr int PROJ_PER = 4;
+
 __global__ void __launch_bounds__(256) k_project(const float *__restrict__ xyz, int64_t n,
                                                  const ViewK *__restrict__ views, int layout,
-                                                 int2 *__restrict__ kz, int32_t *__restrict__ count,
+                                                 int2 *__restrict__ kz, float4 *__restrict__ pcam,
+                                                 int32_t *__restrict__ count,
                                                  int32_t *__restrict__ rank)
 {
     const int vi = blockIdx.y;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     const ViewK &V = views[vi];
-    float x, y, z;
-    to_camera(V, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], x, y, z);
-    int32_t key = -1, r = 0;
-    if (z > 0.0f && __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z)) {
-        const float uf = fma_rn(V.fx, x / z, V.cx);
-        const float vf = fma_rn(V.fy, y / z, V.cy);
-        const float lo = (float)(-V.g);
-        if (uf >= lo && uf < (float)(V.W + V.g) && vf >= lo && vf < (float)(V.H + V.g)) {
-            const int bx = (int)__builtin_floorf(uf) + V.g;
-            const int by = (int)__builtin_floorf(vf) + V.g;
-            key = bucket_of(V, layout, bx, by);
-            r = atomicAdd(&count[key], 1);  // arrival rank inside the bucket
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x * PROJ_PER + threadIdx.x;
+    int32_t key[PROJ_PER];
+    float zz[PROJ_PER];
+#pragma unroll
+    for (int j = 0; j < PROJ_PER; ++j) {
+        const int64_t i = i0 + (int64_t)j * blockDim.x;
+        key[j] = -1;
+        zz[j] = 0.0f;
+        if (i >= n) continue;
+        float x, y, z;
+        to_camera(V, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], x, y, z);
+        pcam[(int64_t)vi * n + i] = make_float4(x, y, z, __int_as_float((int)i));
+        zz[j] = z;
+        if (z > 0.0f && __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z)) {
+            const float uf = fma_rn(V.fx, x / z, V.cx);
+            const float vf = fma_rn(V.fy, y / z, V.cy);
+            const float lo = (float)(-V.g);
+            if (uf >= lo && uf < (float)(V.W + V.g) && vf >= lo && vf < (float)(V.H + V.g)) {
+                const int bx = (int)__builtin_floorf(uf) + V.g;
+                const int by = (int)__builtin_floorf(vf) + V.g;
+                key[j] = bucket_of(V, layout, bx, by);
+            }
         }
     }
-    kz[(int64_t)vi * n + i] = make_int2(key, __float_as_int(z));
-    rank[(int64_t)vi * n + i] = r;
+    int32_t r[PROJ_PER];
+#pragma unroll
+    for (int j = 0; j < PROJ_PER; ++j)
+        r[j] = key[j] >= 0 ? atomicAdd(&count[key[j]], 1) : 0;  // arrival rank inside the bucket
+#pragma unroll
+    for (int j = 0; j < PROJ_PER; ++j) {
+        const int64_t i = i0 + (int64_t)j * blockDim.x;
+        if (i >= n) continue;
+        kz[(int64_t)vi * n + i] = make_int2(key[j], __float_as_int(zz[j]));
+        rank[(int64_t)vi * n + i] = r[j];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -225,6 +248,214 @@ __global__ void __launch_bounds__(256) k_sort_small(const int32_t *__restrict__ 
     bucket_z[b] = cnt > 0 ? __uint_as_float((uint32_t)(first >> 32)) : __builtin_inff();
 }
 
+// ---------------------------------------------------------------------------
+// Two-level build (tables of up to SB_MAX superbuckets).  Per-point atomics
+// on the bucket counters cost the build most of its time: device-scope
+// atomics whose returned value the point needs (its rank in the bucket)
+// stall at the memory side, one per point.  Here buckets are grouped into
+// superbuckets of SB consecutive keys; a workgroup counts its points per
+// superbucket in LDS and makes one global atomic per superbucket it touches,
+// which places its points' records contiguously by superbucket; then one
+// workgroup per superbucket counts, scans, places and sorts the buckets of
+// its SB keys with LDS atomics only.
+// ---------------------------------------------------------------------------
+constexpr int SB = 1 << SB_SHIFT;  // buckets per superbucket
+constexpr int SB_PER = 8;          // points per thread of the projection passes
+constexpr int SB_T = 256;
+
+// superbuckets spanned by view V's buckets
+__device__ __forceinline__ void view_superbuckets(const ViewK &V, int &lo, int &cnt)
+{
+    lo = V.bucket_base >> SB_SHIFT;
+    cnt = ((V.bucket_base + V.Wg * V.Hg - 1) >> SB_SHIFT) - lo + 1;
+}
+
+// grid: (ceil(n / (SB_T SB_PER)), n_views).  Projection, bucket key and
+// depth of each point; per-superbucket totals.
+__global__ void __launch_bounds__(SB_T) k_project_sb(const float *__restrict__ xyz, int64_t n,
+                                                     const ViewK *__restrict__ views, int layout,
+                                                     int2 *__restrict__ kz,
+                                                     float4 *__restrict__ pcam,
+                                                     int32_t *__restrict__ sb_count)
+{
+    __shared__ int hist[SB_MAX];
+    const int vi = blockIdx.y;
+    const ViewK &V = views[vi];
+    int sb_lo, nsb;
+    view_superbuckets(V, sb_lo, nsb);
+    for (int j = threadIdx.x; j < nsb; j += SB_T) hist[j] = 0;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * SB_T * SB_PER + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < SB_PER; ++j) {
+        const int64_t i = i0 + (int64_t)j * SB_T;
+        if (i >= n) break;
+        float x, y, z;
+        to_camera(V, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], x, y, z);
+        pcam[(int64_t)vi * n + i] = make_float4(x, y, z, __int_as_float((int)i));
+        int32_t key = -1;
+        if (z > 0.0f && __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z)) {
+            const float uf = fma_rn(V.fx, x / z, V.cx);
+            const float vf = fma_rn(V.fy, y / z, V.cy);
+            const float lo = (float)(-V.g);
+            if (uf >= lo && uf < (float)(V.W + V.g) && vf >= lo && vf < (float)(V.H + V.g)) {
+                const int bx = (int)__builtin_floorf(uf) + V.g;
+                const int by = (int)__builtin_floorf(vf) + V.g;
+                key = bucket_of(V, layout, bx, by);
+                atomicAdd(&hist[(key >> SB_SHIFT) - sb_lo], 1);
+            }
+        }
+        kz[(int64_t)vi * n + i] = make_int2(key, __float_as_int(z));
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < nsb; j += SB_T)
+        if (hist[j]) atomicAdd(&sb_count[sb_lo + j], hist[j]);
+}
+
+// one workgroup: exclusive scan of the superbucket totals -> sb_off[0 .. nsb],
+// and the table's last offset (points inserted)
+__global__ void __launch_bounds__(1024) k_sb_scan(const int32_t *__restrict__ sb_count, int nsb,
+                                                  int32_t *__restrict__ sb_off,
+                                                  int32_t *__restrict__ offsets_end)
+{
+    __shared__ int sh[1024 / WAVE];
+    const int l = lane_id(), w = threadIdx.x / WAVE;
+    int carry = 0;
+    for (int b0 = 0; b0 < nsb; b0 += 1024) {
+        const int i = b0 + threadIdx.x;
+        const int v = i < nsb ? sb_count[i] : 0;
+        const int inc = wave_incl_scan_i32(v);
+        if (l == WAVE - 1) sh[w] = inc;
+        __syncthreads();
+        int base = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < 1024 / WAVE; ++k) {
+            base += k < w ? sh[k] : 0;
+            tot += sh[k];
+        }
+        if (i < nsb) sb_off[i] = carry + base + inc - v;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sb_off[nsb] = carry;
+        *offsets_end = carry;
+    }
+}
+
+// grid as k_project_sb.  Each point's record (key, z bits, index) goes to its
+// superbucket's range: rank among the workgroup's points of the superbucket
+// (LDS atomic) plus the workgroup's share of the range (one global atomic per
+// superbucket touched).  The order inside a superbucket does not matter: its
+// buckets are sorted by (z, index) next.
+__global__ void __launch_bounds__(SB_T) k_scatter_sb(const int2 *__restrict__ kz, int64_t n,
+                                                     const ViewK *__restrict__ views,
+                                                     const int32_t *__restrict__ sb_off,
+                                                     int32_t *__restrict__ sb_cursor,
+                                                     int4 *__restrict__ rec)
+{
+    __shared__ int hist[SB_MAX];
+    const int vi = blockIdx.y;
+    const ViewK &V = views[vi];
+    int sb_lo, nsb;
+    view_superbuckets(V, sb_lo, nsb);
+    for (int j = threadIdx.x; j < nsb; j += SB_T) hist[j] = 0;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * SB_T * SB_PER + threadIdx.x;
+    int2 e[SB_PER];
+    int r[SB_PER];
+#pragma unroll
+    for (int j = 0; j < SB_PER; ++j) {
+        const int64_t i = i0 + (int64_t)j * SB_T;
+        e[j] = i < n ? kz[(int64_t)vi * n + i] : make_int2(-1, 0);
+        r[j] = e[j].x >= 0 ? atomicAdd(&hist[(e[j].x >> SB_SHIFT) - sb_lo], 1) : 0;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < nsb; j += SB_T) {
+        const int c = hist[j];
+        hist[j] = c ? sb_off[sb_lo + j] + atomicAdd(&sb_cursor[sb_lo + j], c) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SB_PER; ++j) {
+        if (e[j].x < 0) continue;
+        const int64_t i = i0 + (int64_t)j * SB_T;
+        rec[hist[(e[j].x >> SB_SHIFT) - sb_lo] + r[j]] = make_int4(e[j].x, e[j].y, (int)i, 0);
+    }
+}
+
+// One workgroup per superbucket: bucket counts (LDS atomics), their scan
+// (the table's offsets for these SB keys), placement of every record, then
+// each bucket of at most SMALL_MAX points sorted by (z, index) in registers
+// (larger ones are listed for k_sort_mid / k_sort_big) and its depth noted.
+constexpr int FIN_T = 1024;  // threads of a superbucket's workgroup
+
+__global__ void __launch_bounds__(FIN_T) k_finalize_sb(const int4 *__restrict__ rec,
+                                                      const int32_t *__restrict__ sb_off,
+                                                      int64_t n_buckets,
+                                                      int32_t *__restrict__ offsets,
+                                                      uint64_t *__restrict__ skey,
+                                                      int32_t *__restrict__ big_list,
+                                                      int32_t *__restrict__ big_n,
+                                                      float *__restrict__ bucket_z)
+{
+    __shared__ int cnt[SB];
+    __shared__ int cur[SB];
+    __shared__ int sh[FIN_T / WAVE];
+    const int sb = blockIdx.x;
+    const int64_t key0 = (int64_t)sb << SB_SHIFT;
+    const int nkeys = (int)min((int64_t)SB, n_buckets - key0);
+    const int r0 = sb_off[sb], r1 = sb_off[sb + 1];
+    for (int k = threadIdx.x; k < SB; k += FIN_T) cnt[k] = 0;
+    __syncthreads();
+    for (int i = r0 + threadIdx.x; i < r1; i += FIN_T) atomicAdd(&cnt[rec[i].x - (int)key0], 1);
+    __syncthreads();
+    // exclusive scan over the SB counts, SB / FIN_T consecutive ones per thread
+    constexpr int PER = SB / FIN_T;
+    const int k0 = threadIdx.x * PER;
+    int c[PER], s = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        c[q] = cnt[k0 + q];
+        s += c[q];
+    }
+    const int l = lane_id(), w = threadIdx.x / WAVE;
+    const int inc = wave_incl_scan_i32(s);
+    if (l == WAVE - 1) sh[w] = inc;
+    __syncthreads();
+    int run = r0 + inc - s;
+#pragma unroll
+    for (int k = 0; k < FIN_T / WAVE; ++k) run += k < w ? sh[k] : 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        cur[k0 + q] = run;
+        if (k0 + q < nkeys) offsets[key0 + k0 + q] = run;
+        run += c[q];
+    }
+    __syncthreads();
+    for (int i = r0 + threadIdx.x; i < r1; i += FIN_T) {
+        const int4 e = rec[i];
+        const int slot = atomicAdd(&cur[e.x - (int)key0], 1);
+        skey[slot] = ((uint64_t)(uint32_t)e.y << 32) | (uint32_t)e.z;
+    }
+    __syncthreads();  // (the placed keys are read back below by other threads)
+    for (int k = threadIdx.x; k < nkeys; k += FIN_T) {
+        const int b = (int)key0 + k;
+        const int n_b = cnt[k];
+        const int start = cur[k] - n_b;
+        uint64_t first = ~0ull;
+        if (n_b == 1) first = skey[start];
+        else if (n_b > 1 && n_b <= 4) first = sort_bucket_regs<4>(skey, start, n_b);
+        else if (n_b > 4 && n_b <= 8) first = sort_bucket_regs<8>(skey, start, n_b);
+        else if (n_b > 8 && n_b <= SMALL_MAX) first = sort_bucket_regs<16>(skey, start, n_b);
+        else if (n_b > SMALL_MAX) {
+            big_list[atomicAdd(big_n, 1)] = b;
+            continue;  // k_sort_mid / k_sort_big write bucket_z
+        }
+        bucket_z[b] = n_b > 0 ? __uint_as_float((uint32_t)(first >> 32)) : __builtin_inff();
+    }
+}
+
 constexpr int BIG_T = 256;
 constexpr int BIG_LDS = 4096;
 
@@ -263,8 +494,8 @@ __device__ void block_flip_bitonic(int cnt, Load ld, Store st)
     }
 }
 
-// Buckets of 17..64 points: one wave each, a register bitonic sort across
-// the wave (one key per lane), no LDS and no workgroup barrier.
+// Buckets of 17..128 points: one wave each, a register bitonic sort across
+// the wave (one or two keys per lane), no LDS and no workgroup barrier.
 __global__ void __launch_bounds__(256) k_sort_mid(const int32_t *__restrict__ offsets,
                                                   uint64_t *__restrict__ skey,
                                                   const int32_t *__restrict__ big_list,
@@ -278,15 +509,27 @@ __global__ void __launch_bounds__(256) k_sort_mid(const int32_t *__restrict__ of
         const int b = big_list[it];
         const int start = offsets[b];
         const int cnt = offsets[b + 1] - start;
-        if (cnt > WAVE) continue;  // left to k_sort_big
+        if (cnt > 2 * WAVE) continue;  // left to k_sort_big
         uint64_t x = l < cnt ? skey[start + l] : ~0ull;
-        x = wave_sort_fast(x);
+        if (cnt <= WAVE) {
+            x = wave_sort_fast(x);
+        } else {
+            // 128 keys: an ascending and a descending run, the lane-wise
+            // half-cleaner, then both halves sorted
+            uint64_t y = WAVE + l < cnt ? skey[start + WAVE + l] : ~0ull;
+            x = wave_sort_fast(x);
+            y = wave_sort_desc(y);
+            const uint64_t lo = umin64(x, y), hi = umax64(x, y);
+            x = wave_merge_low_fast(lo, ~0ull);
+            y = wave_merge_low_fast(hi, ~0ull);
+            if (WAVE + l < cnt) skey[start + WAVE + l] = y;
+        }
         if (l < cnt) skey[start + l] = x;
         if (l == 0) bucket_z[b] = __uint_as_float((uint32_t)(x >> 32));
     }
 }
 
-// Buckets of more than 64 points: one workgroup each, bitonic in LDS (in
+// Buckets of more than 128 points: one workgroup each, bitonic in LDS (in
 // global memory beyond BIG_LDS entries).
 __global__ void __launch_bounds__(BIG_T) k_sort_big(const int32_t *__restrict__ offsets,
                                                     uint64_t *__restrict__ skey,
@@ -300,7 +543,7 @@ __global__ void __launch_bounds__(BIG_T) k_sort_big(const int32_t *__restrict__ 
         const int b = big_list[it];
         const int start = offsets[b];
         const int cnt = offsets[b + 1] - start;
-        if (cnt <= WAVE) continue;  // sorted by k_sort_mid (uniform across the workgroup)
+        if (cnt <= 2 * WAVE) continue;  // sorted by k_sort_mid (uniform across the workgroup)
         uint64_t *g = skey + start;
         if (cnt <= BIG_LDS) {
             for (int i = threadIdx.x; i < cnt; i += blockDim.x) sh[i] = g[i];
@@ -345,29 +588,26 @@ __global__ void k_view_slots(const int32_t *__restrict__ offsets, ViewK *views, 
 
 __global__ void __launch_bounds__(256) k_materialize(const uint64_t *__restrict__ skey,
                                                      const int32_t *__restrict__ n_in_ptr,
-                                                     const float *__restrict__ xyz, int64_t n,
+                                                     const float4 *__restrict__ pcam, int64_t n,
                                                      const ViewK *__restrict__ views, int n_views,
                                                      float4 *__restrict__ pts,
-                                                     int32_t *__restrict__ perm,
-                                                     int32_t *__restrict__ slot_of)
+                                                     int32_t *__restrict__ perm)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= *n_in_ptr) return;
     int vi = 0;
     while (vi + 1 < n_views && views[vi + 1].slot_base <= s) ++vi;
-    const uint64_t key = skey[s];
-    const int32_t idx = (int32_t)(uint32_t)key;
-    float x, y, z;
-    to_camera(views[vi], xyz[3 * (int64_t)idx], xyz[3 * (int64_t)idx + 1], xyz[3 * (int64_t)idx + 2],
-              x, y, z);
-    pts[s] = make_float4(x, y, z, __int_as_float(idx));
+    const int32_t idx = (int32_t)(uint32_t)skey[s];
+    pts[s] = pcam[(int64_t)vi * n + idx];
     perm[s] = idx;
-    slot_of[(int64_t)vi * n + idx] = (int32_t)s;
 }
 
 }  // namespace hp
 
 namespace hp {
+
+static void finish_build(const float *xyz, int64_t n, const ViewSet &vs, const TableWs &tw,
+                         hipStream_t s);
 
 hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t n_buckets,
                         int64_t n_cells, const TableWs &tw, hipStream_t s)
@@ -375,17 +615,53 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
     const int V = vs.n;
     const int64_t nv = n * V;
     k_init_views<<<1, HP_MAX_VIEWS, 0, s>>>(vs, tw.views);
+    const int64_t nsb = (n_buckets + SB - 1) / SB;
+    if (nsb <= SB_MAX) {
+        // two-level build: superbucket totals, records by superbucket, then
+        // each superbucket's buckets in LDS
+        k_fill_i32<<<64, 256, 0, s>>>(tw.sb_count, 0, tw.sb_words);  // totals, cursors, big_n
+        if (nv > 0) {
+            const dim3 grid((unsigned)((n + SB_T * SB_PER - 1) / (SB_T * SB_PER)), V);
+            k_project_sb<<<grid, SB_T, 0, s>>>(xyz, n, tw.views, vs.layout, tw.kz, tw.pcam,
+                                               tw.sb_count);
+            k_sb_scan<<<1, 1024, 0, s>>>(tw.sb_count, (int)nsb, tw.sb_off, tw.offsets + n_buckets);
+            k_scatter_sb<<<grid, SB_T, 0, s>>>(tw.kz, n, tw.views, tw.sb_off, tw.sb_cursor,
+                                               reinterpret_cast<int4 *>(tw.pts));
+        } else {
+            k_sb_scan<<<1, 1024, 0, s>>>(tw.sb_count, (int)nsb, tw.sb_off, tw.offsets + n_buckets);
+        }
+        k_finalize_sb<<<(unsigned)nsb, FIN_T, 0, s>>>(reinterpret_cast<const int4 *>(tw.pts), tw.sb_off,
+                                                     n_buckets, tw.offsets, tw.skey, tw.big_list,
+                                                     tw.big_n, tw.bucket_z);
+        k_sort_mid<<<1024, 256, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
+        k_sort_big<<<256, BIG_T, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
+        finish_build(xyz, n, vs, tw, s);
+        return hipGetLastError();
+    }
+    // one level (tables beyond SB_MAX superbuckets): a counter per bucket
     k_fill_i32<<<1024, 256, 0, s>>>(tw.count, 0, n_buckets);
     k_fill_i32<<<1, 64, 0, s>>>(tw.big_n, 0, 1);
-    if (n > 0) k_project<<<dim3((unsigned)((n + 255) / 256), V), 256, 0, s>>>(xyz, n, tw.views, vs.layout, tw.kz, tw.count, tw.slot_of);
+    if (n > 0)
+        k_project<<<dim3((unsigned)((n + 256 * PROJ_PER - 1) / (256 * PROJ_PER)), V), 256, 0, s>>>(
+            xyz, n, tw.views, vs.layout, tw.kz, tw.pcam, tw.count, tw.perm);
     const int64_t nblk = (n_buckets + SCAN_TILE - 1) / SCAN_TILE;
     k_scan_reduce<<<(unsigned)nblk, SCAN_T, 0, s>>>(tw.count, n_buckets, tw.block_sums);
     k_scan_blocks<<<1, SCAN_T, 0, s>>>(tw.block_sums, nblk);
     k_scan_apply<<<(unsigned)nblk, SCAN_T, 0, s>>>(tw.count, n_buckets, tw.block_sums, tw.offsets);
-    if (nv > 0) k_scatter<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tw.kz, tw.slot_of, nv, n, tw.offsets, tw.skey);
+    if (nv > 0) k_scatter<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tw.kz, tw.perm, nv, n, tw.offsets, tw.skey);
     k_sort_small<<<(unsigned)((n_buckets + 255) / 256), 256, 0, s>>>(tw.offsets, n_buckets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
     k_sort_mid<<<1024, 256, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
     k_sort_big<<<256, BIG_T, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
+    finish_build(xyz, n, vs, tw, s);
+    return hipGetLastError();
+}
+
+// depth cells, the views' first slots and the camera-space points per slot
+static void finish_build(const float *xyz, int64_t n, const ViewSet &vs, const TableWs &tw,
+                         hipStream_t s)
+{
+    const int V = vs.n;
+    const int64_t nv = n * V;
     int max_cells = 0;
     for (int i = 0; i < V; ++i) {
         const ViewK &vk = vs.v[i];
@@ -394,8 +670,7 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
     k_cell_zmin<<<dim3((unsigned)((max_cells + 3) / 4), V), 256, 0, s>>>(tw.bucket_z, tw.views, vs.layout, tw.cell_zmin);
     k_view_slots<<<1, HP_MAX_VIEWS, 0, s>>>(tw.offsets, tw.views, V);
     if (nv > 0)
-        k_materialize<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tw.skey, tw.offsets + n_buckets, xyz, n, tw.views, V, tw.pts, tw.perm, tw.slot_of);
-    return hipGetLastError();
+        k_materialize<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tw.skey, tw.offsets + tw.n_buckets, tw.pcam, n, tw.views, V, tw.pts, tw.perm);
 }
 
 }  // namespace hp

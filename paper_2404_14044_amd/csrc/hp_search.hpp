@@ -47,7 +47,7 @@ namespace hp {
 struct SearchCtx {
     const int32_t *offsets;
     const float4 *pts;
-    const int32_t *slot_of;
+    const float4 *pcam;    // camera-space points in point order, per view
     const float *bucket_z;
     const uint32_t *cell_zmin;
     const ViewK *views;
@@ -1034,8 +1034,7 @@ __device__ __forceinline__ int walk_candidates(const SearchCtx &c, const RayGeom
     lds_sync();
     if (l < m) {
         const int idxj = (int)(uint32_t)top;
-        const int slot = c.slot_of[(int64_t)g.vi * c.n_points + idxj];
-        sh.nb_p[l] = c.pts[slot];
+        sh.nb_p[l] = c.pcam[(int64_t)g.vi * c.n_points + idxj];
         sh.nb_t[l] = __uint_as_float((uint32_t)(top >> 32));
     }
     lds_sync();
@@ -1171,8 +1170,7 @@ __device__ __forceinline__ int uniform_samples(const SearchCtx &c, const RayGeom
         lds_sync();
         if (l < n) {
             const int idxj = (int)(uint32_t)keys;
-            const int slot = c.slot_of[(int64_t)g.vi * c.n_points + idxj];
-            sh.nb_p[l] = c.pts[slot];
+            sh.nb_p[l] = c.pcam[(int64_t)g.vi * c.n_points + idxj];
             sh.nb_t[l] = __uint_as_float((uint32_t)(keys >> 32));
         }
         lds_sync();

@@ -9,6 +9,11 @@
 
 namespace hp {
 
+// Superbuckets of the two-level build: SB = 2^SB_SHIFT consecutive bucket
+// keys; tables of up to SB_MAX of them (2^24 buckets) take that path.
+constexpr int SB_SHIFT = 11;
+constexpr int SB_MAX = 8192;
+
 struct TableWs {
     ViewK *views;          // [HP_MAX_VIEWS]  per-view constants
     int32_t *count;        // [n_buckets]     per-bucket counters
@@ -18,9 +23,14 @@ struct TableWs {
     uint64_t *skey;        // [n_views * n]   (z bits, index) per slot
     float4 *pts;           // [n_views * n]   camera-space point per slot
     int32_t *perm;         // [n_views * n]   point index per slot
-    int32_t *slot_of;      // [n_views * n]   slot per point and view
+    float4 *pcam;          // [n_views * n]   camera-space point (x, y, z, index bits) per point and view
     int32_t *big_list;     // [n_buckets]     buckets too large for one lane
-    int32_t *big_n;        // [1]
+    int32_t *sb_count;     // [n_sb]          points per superbucket, then
+    int32_t *sb_cursor;    // [n_sb]          records placed per superbucket, then
+    int32_t *big_n;        // [1]             entries of big_list (one region, zeroed at once)
+    int64_t sb_words;      //                 2 n_sb + 1
+    int32_t *sb_off;       // [n_sb + 1]      first record of each superbucket
+    int64_t n_buckets;
     float *bucket_z;       // [n_buckets]     depth of the first point (+inf if empty)
     uint32_t *cell_zmin;   // [n_cells]       min depth bits per cell (+inf if empty)
     size_t bytes;
@@ -47,9 +57,15 @@ inline TableWs table_ws_layout(void *base, int64_t n, int n_views, int64_t n_buc
     w.skey = (uint64_t *)take(sizeof(uint64_t) * nvs);
     w.pts = (float4 *)take(sizeof(float4) * nvs);
     w.perm = (int32_t *)take(sizeof(int32_t) * nvs);
-    w.slot_of = (int32_t *)take(sizeof(int32_t) * nvs);
+    w.pcam = (float4 *)take(sizeof(float4) * nvs);
     w.big_list = (int32_t *)take(sizeof(int32_t) * n_buckets);
-    w.big_n = (int32_t *)take(sizeof(int32_t) * 64);
+    const int64_t n_sb = (n_buckets + (1 << SB_SHIFT) - 1) >> SB_SHIFT;
+    w.sb_count = (int32_t *)take(sizeof(int32_t) * (2 * n_sb + 64));
+    w.sb_cursor = base ? w.sb_count + n_sb : nullptr;
+    w.big_n = base ? w.sb_count + 2 * n_sb : nullptr;
+    w.sb_words = 2 * n_sb + 1;
+    w.sb_off = (int32_t *)take(sizeof(int32_t) * (n_sb + 1));
+    w.n_buckets = n_buckets;
     w.bucket_z = (float *)take(sizeof(float) * n_buckets);
     w.cell_zmin = (uint32_t *)take(sizeof(uint32_t) * (n_cells > 0 ? n_cells : 1));
     w.bytes = off;

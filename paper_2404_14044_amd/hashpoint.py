@@ -72,7 +72,7 @@ class HPTable(ctypes.Structure):
                 ("n_points", ctypes.c_int64), ("n_buckets", ctypes.c_int64),
                 ("n_rays", ctypes.c_int64),
                 ("offsets", ctypes.c_void_p), ("pts", ctypes.c_void_p),
-                ("perm", ctypes.c_void_p), ("slot_of", ctypes.c_void_p),
+                ("perm", ctypes.c_void_p), ("pcam", ctypes.c_void_p),
                 ("bucket_z", ctypes.c_void_p), ("cell_zmin", ctypes.c_void_p),
                 ("n_cells", ctypes.c_int64), ("build_key", ctypes.c_uint64),
                 ("scratch", ctypes.c_void_p), ("views", HPViewInfo * HP_MAX_VIEWS)]

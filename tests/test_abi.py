@@ -249,7 +249,7 @@ def _fake_table(cam, params):
     tab.n_views, tab.layout, tab.n_points = 1, int(params.layout), 100
     tab.n_buckets = (cam.W + 2 * g) * (cam.H + 2 * g)
     tab.n_rays = cam.W * cam.H
-    for name in ("offsets", "pts", "perm", "slot_of", "bucket_z", "cell_zmin", "scratch"):
+    for name in ("offsets", "pts", "perm", "pcam", "bucket_z", "cell_zmin", "scratch"):
         setattr(tab, name, 0x1000)
     v = tab.views[0]
     v.W, v.H, v.g, v.Wg, v.Hg = cam.W, cam.H, g, cam.W + 2 * g, cam.H + 2 * g
