@@ -226,6 +226,18 @@ __device__ __forceinline__ uint64_t sort_bucket_regs(uint64_t *__restrict__ skey
 
 constexpr int SMALL_MAX = 16;
 
+// Buckets of more than SMALL_MAX points are listed for the wave and
+// workgroup sorts: those of up to 128 points from the front of big_list
+// (count big_n[0], k_sort_mid), larger ones from its back (count big_n[1],
+// k_sort_big), so that neither kernel walks the other's entries.
+__device__ __forceinline__ void list_big_bucket(int32_t *__restrict__ big_list,
+                                                int32_t *__restrict__ big_n, int64_t cap, int b,
+                                                int cnt)
+{
+    if (cnt <= 2 * WAVE) big_list[atomicAdd(&big_n[0], 1)] = b;
+    else big_list[cap - 1 - atomicAdd(&big_n[1], 1)] = b;
+}
+
 __global__ void __launch_bounds__(256) k_sort_small(const int32_t *__restrict__ offsets, int64_t nb,
                                                     uint64_t *__restrict__ skey,
                                                     int32_t *__restrict__ big_list,
@@ -242,10 +254,51 @@ __global__ void __launch_bounds__(256) k_sort_small(const int32_t *__restrict__ 
     else if (cnt > 4 && cnt <= 8) first = sort_bucket_regs<8>(skey, start, cnt);
     else if (cnt > 8 && cnt <= SMALL_MAX) first = sort_bucket_regs<16>(skey, start, cnt);
     else if (cnt > SMALL_MAX) {
-        big_list[atomicAdd(big_n, 1)] = (int32_t)b;
+        list_big_bucket(big_list, big_n, nb, (int32_t)b, cnt);
         return;  // k_sort_mid / k_sort_big write bucket_z
     }
     bucket_z[b] = cnt > 0 ? __uint_as_float((uint32_t)(first >> 32)) : __builtin_inff();
+}
+
+// Where sorted slots also become table points: pts[slot] = the camera-space
+// point of its index (pcam of the bucket's view) and perm[slot] = the index.
+// pts == nullptr: the slots are materialised afterwards (k_materialize).
+struct SlotOut {
+    const float4 *pcam;
+    int64_t n;
+    const ViewK *views;
+    int n_views;
+    float4 *pts;
+    int32_t *perm;
+};
+
+__device__ __forceinline__ const float4 *bucket_pcam(const SlotOut &o, int b)
+{
+    int vi = 0;
+    while (vi + 1 < o.n_views && o.views[vi + 1].bucket_base <= b) ++vi;
+    return o.pcam + (int64_t)vi * o.n;
+}
+
+__device__ __forceinline__ void put_slot(const SlotOut &o, const float4 *pc, int slot, uint64_t key)
+{
+    const int32_t idx = (int32_t)(uint32_t)key;
+    o.pts[slot] = pc[idx];
+    o.perm[slot] = idx;
+}
+
+template <int N>
+__device__ __forceinline__ uint64_t sort_bucket_to_slots(const uint64_t *__restrict__ skey, int start,
+                                                         int cnt, const SlotOut &so,
+                                                         const float4 *pc)
+{
+    uint64_t k[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) k[i] = (i < cnt) ? skey[start + i] : ~0ull;
+    sort_net<N>(k);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (i < cnt) put_slot(so, pc, start + i, k[i]);
+    return k[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -380,7 +433,7 @@ __global__ void __launch_bounds__(SB_T) k_scatter_sb(const int2 *__restrict__ kz
     for (int j = 0; j < SB_PER; ++j) {
         if (e[j].x < 0) continue;
         const int64_t i = i0 + (int64_t)j * SB_T;
-        rec[hist[(e[j].x >> SB_SHIFT) - sb_lo] + r[j]] = make_int4(e[j].x, e[j].y, (int)i, 0);
+        rec[hist[(e[j].x >> SB_SHIFT) - sb_lo] + r[j]] = make_int4(e[j].x, e[j].y, (int)i, vi);
     }
 }
 
@@ -388,7 +441,7 @@ __global__ void __launch_bounds__(SB_T) k_scatter_sb(const int2 *__restrict__ kz
 // (the table's offsets for these SB keys), placement of every record, then
 // each bucket of at most SMALL_MAX points sorted by (z, index) in registers
 // (larger ones are listed for k_sort_mid / k_sort_big) and its depth noted.
-constexpr int FIN_T = 1024;  // threads of a superbucket's workgroup
+constexpr int FIN_T = 512;  // threads of a superbucket's workgroup
 
 __global__ void __launch_bounds__(FIN_T) k_finalize_sb(const int4 *__restrict__ rec,
                                                       const int32_t *__restrict__ sb_off,
@@ -397,7 +450,7 @@ __global__ void __launch_bounds__(FIN_T) k_finalize_sb(const int4 *__restrict__ 
                                                       uint64_t *__restrict__ skey,
                                                       int32_t *__restrict__ big_list,
                                                       int32_t *__restrict__ big_n,
-                                                      float *__restrict__ bucket_z)
+                                                      float *__restrict__ bucket_z, SlotOut so)
 {
     __shared__ int cnt[SB];
     __shared__ int cur[SB];
@@ -443,14 +496,24 @@ __global__ void __launch_bounds__(FIN_T) k_finalize_sb(const int4 *__restrict__ 
         const int b = (int)key0 + k;
         const int n_b = cnt[k];
         const int start = cur[k] - n_b;
+        if (n_b > SMALL_MAX) {
+            list_big_bucket(big_list, big_n, n_buckets, b, n_b);
+            continue;  // k_sort_mid / k_sort_big sort it, place it and write bucket_z
+        }
         uint64_t first = ~0ull;
-        if (n_b == 1) first = skey[start];
-        else if (n_b > 1 && n_b <= 4) first = sort_bucket_regs<4>(skey, start, n_b);
-        else if (n_b > 4 && n_b <= 8) first = sort_bucket_regs<8>(skey, start, n_b);
-        else if (n_b > 8 && n_b <= SMALL_MAX) first = sort_bucket_regs<16>(skey, start, n_b);
-        else if (n_b > SMALL_MAX) {
-            big_list[atomicAdd(big_n, 1)] = b;
-            continue;  // k_sort_mid / k_sort_big write bucket_z
+        if (n_b > 0) {
+            // sorted slots become table points right away
+            const float4 *pc = bucket_pcam(so, b);
+            if (n_b == 1) {
+                first = skey[start];
+                put_slot(so, pc, start, first);
+            } else if (n_b <= 4) {
+                first = sort_bucket_to_slots<4>(skey, start, n_b, so, pc);
+            } else if (n_b <= 8) {
+                first = sort_bucket_to_slots<8>(skey, start, n_b, so, pc);
+            } else {
+                first = sort_bucket_to_slots<16>(skey, start, n_b, so, pc);
+            }
         }
         bucket_z[b] = n_b > 0 ? __uint_as_float((uint32_t)(first >> 32)) : __builtin_inff();
     }
@@ -500,16 +563,15 @@ __global__ void __launch_bounds__(256) k_sort_mid(const int32_t *__restrict__ of
                                                   uint64_t *__restrict__ skey,
                                                   const int32_t *__restrict__ big_list,
                                                   const int32_t *__restrict__ big_n,
-                                                  float *__restrict__ bucket_z)
+                                                  float *__restrict__ bucket_z, SlotOut so)
 {
-    const int nbig = *big_n;
+    const int nbig = big_n[0];
     const int l = lane_id();
     const int waves = blockDim.x / WAVE;
     for (int it = blockIdx.x * waves + (threadIdx.x >> 6); it < nbig; it += gridDim.x * waves) {
         const int b = big_list[it];
         const int start = offsets[b];
         const int cnt = offsets[b + 1] - start;
-        if (cnt > 2 * WAVE) continue;  // left to k_sort_big
         uint64_t x = l < cnt ? skey[start + l] : ~0ull;
         if (cnt <= WAVE) {
             x = wave_sort_fast(x);
@@ -522,9 +584,15 @@ __global__ void __launch_bounds__(256) k_sort_mid(const int32_t *__restrict__ of
             const uint64_t lo = umin64(x, y), hi = umax64(x, y);
             x = wave_merge_low_fast(lo, ~0ull);
             y = wave_merge_low_fast(hi, ~0ull);
-            if (WAVE + l < cnt) skey[start + WAVE + l] = y;
+            if (WAVE + l < cnt) {
+                if (so.pts) put_slot(so, bucket_pcam(so, b), start + WAVE + l, y);
+                else skey[start + WAVE + l] = y;
+            }
         }
-        if (l < cnt) skey[start + l] = x;
+        if (l < cnt) {
+            if (so.pts) put_slot(so, bucket_pcam(so, b), start + l, x);
+            else skey[start + l] = x;
+        }
         if (l == 0) bucket_z[b] = __uint_as_float((uint32_t)(x >> 32));
     }
 }
@@ -535,15 +603,15 @@ __global__ void __launch_bounds__(BIG_T) k_sort_big(const int32_t *__restrict__ 
                                                     uint64_t *__restrict__ skey,
                                                     const int32_t *__restrict__ big_list,
                                                     const int32_t *__restrict__ big_n,
-                                                    float *__restrict__ bucket_z)
+                                                    float *__restrict__ bucket_z, int64_t cap,
+                                                    SlotOut so)
 {
     __shared__ uint64_t sh[BIG_LDS];
-    const int nbig = *big_n;
+    const int nbig = big_n[1];
     for (int it = blockIdx.x; it < nbig; it += gridDim.x) {
-        const int b = big_list[it];
+        const int b = big_list[cap - 1 - it];
         const int start = offsets[b];
         const int cnt = offsets[b + 1] - start;
-        if (cnt <= 2 * WAVE) continue;  // sorted by k_sort_mid (uniform across the workgroup)
         uint64_t *g = skey + start;
         if (cnt <= BIG_LDS) {
             for (int i = threadIdx.x; i < cnt; i += blockDim.x) sh[i] = g[i];
@@ -555,7 +623,12 @@ __global__ void __launch_bounds__(BIG_T) k_sort_big(const int32_t *__restrict__ 
                                [&](int i, uint64_t v) { g[i] = v; });
         }
         __syncthreads();
+        if (so.pts) {
+            const float4 *pc = bucket_pcam(so, b);
+            for (int i = threadIdx.x; i < cnt; i += blockDim.x) put_slot(so, pc, start + i, g[i]);
+        }
         if (threadIdx.x == 0) bucket_z[b] = __uint_as_float((uint32_t)(g[0] >> 32));
+        __syncthreads();
     }
 }
 
@@ -607,7 +680,7 @@ __global__ void __launch_bounds__(256) k_materialize(const uint64_t *__restrict_
 namespace hp {
 
 static void finish_build(const float *xyz, int64_t n, const ViewSet &vs, const TableWs &tw,
-                         hipStream_t s);
+                         bool materialize, hipStream_t s);
 
 hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t n_buckets,
                         int64_t n_cells, const TableWs &tw, hipStream_t s)
@@ -619,7 +692,7 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
     if (nsb <= SB_MAX) {
         // two-level build: superbucket totals, records by superbucket, then
         // each superbucket's buckets in LDS
-        k_fill_i32<<<64, 256, 0, s>>>(tw.sb_count, 0, tw.sb_words);  // totals, cursors, big_n
+        k_fill_i32<<<64, 256, 0, s>>>(tw.sb_count, 0, tw.sb_words);  // totals, cursors, big_n[2]
         if (nv > 0) {
             const dim3 grid((unsigned)((n + SB_T * SB_PER - 1) / (SB_T * SB_PER)), V);
             k_project_sb<<<grid, SB_T, 0, s>>>(xyz, n, tw.views, vs.layout, tw.kz, tw.pcam,
@@ -630,17 +703,21 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
         } else {
             k_sb_scan<<<1, 1024, 0, s>>>(tw.sb_count, (int)nsb, tw.sb_off, tw.offsets + n_buckets);
         }
+        // (the records sit in pts: a superbucket's workgroup overwrites only
+        // its own range, after reading all of it)
+        const SlotOut so{tw.pcam, n, tw.views, V, tw.pts, tw.perm};
         k_finalize_sb<<<(unsigned)nsb, FIN_T, 0, s>>>(reinterpret_cast<const int4 *>(tw.pts), tw.sb_off,
                                                      n_buckets, tw.offsets, tw.skey, tw.big_list,
-                                                     tw.big_n, tw.bucket_z);
-        k_sort_mid<<<1024, 256, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
-        k_sort_big<<<256, BIG_T, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
-        finish_build(xyz, n, vs, tw, s);
+                                                     tw.big_n, tw.bucket_z, so);
+        k_sort_mid<<<1024, 256, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z, so);
+        k_sort_big<<<256, BIG_T, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z,
+                                         n_buckets, so);
+        finish_build(nullptr, n, vs, tw, false, s);
         return hipGetLastError();
     }
     // one level (tables beyond SB_MAX superbuckets): a counter per bucket
     k_fill_i32<<<1024, 256, 0, s>>>(tw.count, 0, n_buckets);
-    k_fill_i32<<<1, 64, 0, s>>>(tw.big_n, 0, 1);
+    k_fill_i32<<<1, 64, 0, s>>>(tw.big_n, 0, 2);
     if (n > 0)
         k_project<<<dim3((unsigned)((n + 256 * PROJ_PER - 1) / (256 * PROJ_PER)), V), 256, 0, s>>>(
             xyz, n, tw.views, vs.layout, tw.kz, tw.pcam, tw.count, tw.perm);
@@ -650,15 +727,18 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
     k_scan_apply<<<(unsigned)nblk, SCAN_T, 0, s>>>(tw.count, n_buckets, tw.block_sums, tw.offsets);
     if (nv > 0) k_scatter<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tw.kz, tw.perm, nv, n, tw.offsets, tw.skey);
     k_sort_small<<<(unsigned)((n_buckets + 255) / 256), 256, 0, s>>>(tw.offsets, n_buckets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
-    k_sort_mid<<<1024, 256, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
-    k_sort_big<<<256, BIG_T, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
-    finish_build(xyz, n, vs, tw, s);
+    const SlotOut none{nullptr, 0, nullptr, 0, nullptr, nullptr};
+    k_sort_mid<<<1024, 256, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z, none);
+    k_sort_big<<<256, BIG_T, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z,
+                                     n_buckets, none);
+    finish_build(xyz, n, vs, tw, true, s);
     return hipGetLastError();
 }
 
-// depth cells, the views' first slots and the camera-space points per slot
+// depth cells; with `materialize`, the views' first slots and the table
+// points per slot (the two-level build places them while sorting)
 static void finish_build(const float *xyz, int64_t n, const ViewSet &vs, const TableWs &tw,
-                         hipStream_t s)
+                         bool materialize, hipStream_t s)
 {
     const int V = vs.n;
     const int64_t nv = n * V;
@@ -668,6 +748,7 @@ static void finish_build(const float *xyz, int64_t n, const ViewSet &vs, const T
         max_cells = max(max_cells, vk.ncx * ((vk.Hg + CELL - 1) / CELL));
     }
     k_cell_zmin<<<dim3((unsigned)((max_cells + 3) / 4), V), 256, 0, s>>>(tw.bucket_z, tw.views, vs.layout, tw.cell_zmin);
+    if (!materialize) return;
     k_view_slots<<<1, HP_MAX_VIEWS, 0, s>>>(tw.offsets, tw.views, V);
     if (nv > 0)
         k_materialize<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tw.skey, tw.offsets + tw.n_buckets, tw.pcam, n, tw.views, V, tw.pts, tw.perm);

@@ -10,8 +10,8 @@
 namespace hp {
 
 // Superbuckets of the two-level build: SB = 2^SB_SHIFT consecutive bucket
-// keys; tables of up to SB_MAX of them (2^24 buckets) take that path.
-constexpr int SB_SHIFT = 11;
+// keys; tables of up to SB_MAX of them (2^23 buckets) take that path.
+constexpr int SB_SHIFT = 10;
 constexpr int SB_MAX = 8192;
 
 struct TableWs {
@@ -27,8 +27,8 @@ struct TableWs {
     int32_t *big_list;     // [n_buckets]     buckets too large for one lane
     int32_t *sb_count;     // [n_sb]          points per superbucket, then
     int32_t *sb_cursor;    // [n_sb]          records placed per superbucket, then
-    int32_t *big_n;        // [1]             entries of big_list (one region, zeroed at once)
-    int64_t sb_words;      //                 2 n_sb + 1
+    int32_t *big_n;        // [2]             entries of big_list (one region, zeroed at once)
+    int64_t sb_words;      //                 2 n_sb + 2
     int32_t *sb_off;       // [n_sb + 1]      first record of each superbucket
     int64_t n_buckets;
     float *bucket_z;       // [n_buckets]     depth of the first point (+inf if empty)
@@ -63,7 +63,7 @@ inline TableWs table_ws_layout(void *base, int64_t n, int n_views, int64_t n_buc
     w.sb_count = (int32_t *)take(sizeof(int32_t) * (2 * n_sb + 64));
     w.sb_cursor = base ? w.sb_count + n_sb : nullptr;
     w.big_n = base ? w.sb_count + 2 * n_sb : nullptr;
-    w.sb_words = 2 * n_sb + 1;
+    w.sb_words = 2 * n_sb + 2;
     w.sb_off = (int32_t *)take(sizeof(int32_t) * (n_sb + 1));
     w.n_buckets = n_buckets;
     w.bucket_z = (float *)take(sizeof(float) * n_buckets);
