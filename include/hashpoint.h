@@ -405,6 +405,14 @@ hp_status hp_render_backward_noalloc(const hp_table *tab, const hp_camera *cams,
  * Errors: HP_E_INVALID (n < 0, null pointer with n > 0). */
 hp_status hp_exp32_eval(const float *x, float *y, int64_t n, void *stream);
 
+/* Evaluates on the device the rounding of binary32 values to bfloat16 that
+ * the BF16 decoder applies to its operands (features, activations, weights;
+ * round to nearest, ties to even, subnormals kept): y[i] = x[i] rounded, as
+ * binary32 (n values, device; y may not overlap x).  For tests of
+ * bit-reproducibility against the definition.  Asynchronous on `stream`.
+ * Errors: HP_E_INVALID (n < 0, null pointer with n > 0). */
+hp_status hp_bf16_eval(const float *x, float *y, int64_t n, void *stream);
+
 /* Status text, and the last HIP error code seen by this thread. */
 const char *hp_status_str(hp_status s);
 int32_t hp_last_hip_error(void);

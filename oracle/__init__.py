@@ -68,6 +68,7 @@ def lib():
         _lib.or_exp32.restype = ctypes.c_float
         _lib.or_exp32.argtypes = [ctypes.c_float]
         _lib.or_exp32_array.argtypes = [P, P, i64]
+        _lib.or_bf16_array.argtypes = [P, P, i64]
         _lib.or_guard.restype = i32
         _lib.or_guard.argtypes = [P, P]
         _lib.or_to_camera.argtypes = [P, i64, P, P]
@@ -138,6 +139,14 @@ def exp32(x) -> np.ndarray:
     x = np.ascontiguousarray(x, np.float32)
     y = np.empty_like(x)
     lib().or_exp32_array(_ptr(x), _ptr(y), x.size)
+    return y
+
+
+def bf16_f32(x) -> np.ndarray:
+    """Binary32 values rounded to bfloat16 (or_bf16), as binary32."""
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.empty_like(x)
+    lib().or_bf16_array(_ptr(x), _ptr(y), x.size)
     return y
 
 

@@ -593,6 +593,14 @@ double or_bf16(double x)
     return ldexp(nearbyint(ldexp(x, 8 - e)), e - 8);
 }
 
+/* or_bf16 over an array of binary32 values, each result rounded to binary32 */
+/* (a value that rounds past the largest bfloat16 gives infinity).           */
+void or_bf16_array(const float *x, float *y, int64_t n)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) y[i] = (float)or_bf16((double)x[i]);
+}
+
 typedef struct {
     int32_t mode;         /* 0, 1 or 2 (above)                                 */
     double *w_off;        /* [n_w1 + n_w2 + n_w3] weight offsets: written by   */

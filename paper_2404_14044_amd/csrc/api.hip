@@ -419,6 +419,13 @@ hp_status hp_exp32_eval(const float *x, float *y, int64_t n, void *stream)
     return e == hipSuccess ? HP_OK : hip_fail(e);
 }
 
+hp_status hp_bf16_eval(const float *x, float *y, int64_t n, void *stream)
+{
+    if (n < 0 || (n > 0 && (!x || !y))) return HP_E_INVALID;
+    const hipError_t e = hp::launch_bf16_round(x, y, n, (hipStream_t)stream);
+    return e == hipSuccess ? HP_OK : hip_fail(e);
+}
+
 hp_status hp_render(const hp_samples *smp, int64_t R, const float *feat, int32_t C,
                     const hp_mlp *mlp, int32_t precision, const hp_params *p, float *rgb,
                     float *depth, float *acc, void *stream)

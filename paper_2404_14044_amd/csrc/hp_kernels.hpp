@@ -74,6 +74,7 @@ struct FusedArgs {
 
 int fused_max_samples();
 hipError_t launch_exp_neg(const float *x, float *y, int64_t n, hipStream_t s);
+hipError_t launch_bf16_round(const float *x, float *y, int64_t n, hipStream_t s);
 hipError_t launch_fused(const SearchCtx &c, const FusedArgs &a, int kt, int precision, hipStream_t s);
 
 }  // namespace hp

@@ -17,14 +17,25 @@ struct MlpWeights {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
-__device__ __forceinline__ uint32_t bf16_bits_rne(float x)
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+
+// Rounding to bfloat16 (round to nearest, ties to even): gfx950 converts two
+// binary32 values per instruction (v_cvt_pk_bf16_f32), subnormals kept in
+// the kernels' floating-point mode; checked bit for bit against the
+// definition by the exact-rounding test of hp_bf16_eval.
+__device__ __forceinline__ uint32_t bf16_pair_bits(float lo, float hi)
 {
-    const uint32_t u = __float_as_uint(x);
-    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+    bf16x2 v;
+    v[0] = (__bf16)lo;
+    v[1] = (__bf16)hi;
+    return __builtin_bit_cast(uint32_t, v);
 }
 
-// x rounded to bfloat16 (round to nearest, ties to even), as a float
-__device__ __forceinline__ float bf16_round(float x) { return __uint_as_float(bf16_bits_rne(x) << 16); }
+// x rounded to bfloat16, as a float
+__device__ __forceinline__ float bf16_round(float x)
+{
+    return __uint_as_float(bf16_pair_bits(x, 0.0f) << 16);
+}
 
 __device__ __forceinline__ bf16x8 pack_bf16x8(const float *v)
 {
@@ -33,7 +44,7 @@ __device__ __forceinline__ bf16x8 pack_bf16x8(const float *v)
         bf16x8 b;
     } r;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) r.u[i] = bf16_bits_rne(v[2 * i]) | (bf16_bits_rne(v[2 * i + 1]) << 16);
+    for (int i = 0; i < 4; ++i) r.u[i] = bf16_pair_bits(v[2 * i], v[2 * i + 1]);
     return r.b;
 }
 

@@ -29,7 +29,7 @@ EXPORTED = ["hp_table_workspace", "hp_view_bounds", "hp_paper_kernel_size", "hp_
             "hp_render", "hp_backward_workspace", "hp_render_backward",
             "hp_backward_samples_workspace", "hp_render_backward_samples", "hp_knp_blend",
             "hp_search_render", "hp_samples_shape", "hp_exp32_eval",
-            "hp_render_backward_noalloc",
+            "hp_render_backward_noalloc", "hp_bf16_eval",
             "hp_status_str",
             "hp_last_hip_error"]
 
@@ -134,6 +134,8 @@ def lib():
         L.hp_samples_shape.argtypes = [i64, P, P]
         L.hp_exp32_eval.restype = i32
         L.hp_exp32_eval.argtypes = [P, P, i64, P]
+        L.hp_bf16_eval.restype = i32
+        L.hp_bf16_eval.argtypes = [P, P, i64, P]
         L.hp_status_str.restype = ctypes.c_char_p
         L.hp_status_str.argtypes = [i32]
         L.hp_last_hip_error.restype = i32
@@ -306,6 +308,15 @@ def exp32_eval(x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None)
         out = torch.empty_like(x)
     _check(lib().hp_exp32_eval(_dev(x, torch.float32, "x"), _dev(out, torch.float32, "out"),
                                int(x.numel()), _stream(stream)), "hp_exp32_eval")
+    return out
+
+
+def bf16_eval(x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """The device's rounding of binary32 values to bfloat16 (as binary32), element-wise."""
+    if out is None:
+        out = torch.empty_like(x)
+    _check(lib().hp_bf16_eval(_dev(x, torch.float32, "x"), _dev(out, torch.float32, "out"),
+                               int(x.numel()), _stream(stream)), "hp_bf16_eval")
     return out
 
 
