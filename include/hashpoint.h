@@ -118,7 +118,8 @@ typedef struct hp_camera {
  *      mentions a Z-order arrangement; read here as an order of buckets).
  *  flags: reserved, must be 0.
  *  search_chunk: rays a search workgroup takes at a time, 0 = default (4),
- *      at most 64; search_blocks: persistent search grid, 0 = default.
+ *      at most 64; search_blocks: search grid (workgroups each taking
+ *      chunks of rays in turn), 0 = default (65,536).
  *      Neither changes any result; an autotuner picks them per workload.
  *  radius_mode: HP_RADIUS_*.  In the Eq. 3 modes rho(t) = kappa t with, for
  *      the pixel centre E = (a, b, 1) on the image plane at unit focal

@@ -6,7 +6,7 @@ trade work distribution against locality:
   layout          buckets row-major, in 8x8 tiles, or in 8x8 tiles in Z-order
                   (the Morton arrangement the paper mentions, Sec. 3.2);
   search_chunk    consecutive rays a search workgroup takes at a time;
-  search_blocks   size of the persistent search grid;
+  search_blocks   size of the search grid (workgroups dealt chunks of rays);
   search_band     consecutive rays dealt to one XCD (its own L2) at a time;
   window_shape    disc of buckets within the proven radius, or its square
                   (more buckets, fewer instructions per bucket);
@@ -33,14 +33,14 @@ from . import hashpoint as hp
 SPACE = {
     "layout": (hp.HP_LAYOUT_ROWMAJOR, hp.HP_LAYOUT_TILED, hp.HP_LAYOUT_MORTON),
     "search_chunk": (1, 2, 4, 8, 16),
-    "search_blocks": (2048, 4096, 8192, 16384),
+    "search_blocks": (8192, 16384, 32768, 65536, 131072),
     "search_band": (3200, 12800, 51200),
     "window_shape": (hp.HP_WINDOW_DISC, hp.HP_WINDOW_SQUARE),
     "render_rays": (16, 32, 64),
     "render_blocks": (0, 3072, 6144, 12288),
 }
 # the values the library takes for 0 (its defaults), the descent's start
-DEFAULTS = {"layout": hp.HP_LAYOUT_ROWMAJOR, "search_chunk": 4, "search_blocks": 8192,
+DEFAULTS = {"layout": hp.HP_LAYOUT_ROWMAJOR, "search_chunk": 4, "search_blocks": 65536,
             "search_band": 12800, "window_shape": hp.HP_WINDOW_DISC, "render_rays": 32,
             "render_blocks": 0}
 

@@ -182,7 +182,7 @@ static void launch_fused_k(const SearchCtx &c, const FusedArgs &a, int precision
 
 hipError_t launch_fused(const SearchCtx &c, const FusedArgs &a, int kt, int precision, hipStream_t s)
 {
-    const int64_t blocks = banded_grid(c, c.blocks > 0 ? c.blocks : 8192);
+    const int64_t blocks = banded_grid(c, c.blocks > 0 ? c.blocks : DEFAULT_SEARCH_BLOCKS);
     if (blocks == 0) return hipSuccess;
     const dim3 grid((unsigned)blocks);
     if (kt == 4) launch_fused_k<4>(c, a, precision, grid, s);

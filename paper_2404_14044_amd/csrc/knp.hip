@@ -71,7 +71,7 @@ k_knp(SearchCtx c, KnpArgs a)
 
 hipError_t launch_knp(const SearchCtx &c, const KnpArgs &a, hipStream_t s)
 {
-    const int64_t blocks = banded_grid(c, c.blocks > 0 ? c.blocks : 8192);
+    const int64_t blocks = banded_grid(c, c.blocks > 0 ? c.blocks : DEFAULT_SEARCH_BLOCKS);
     if (blocks == 0) return hipSuccess;
     k_knp<<<dim3((unsigned)blocks), dim3(WAVE), 0, s>>>(c, a);
     return hipGetLastError();

@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(WAVE) k_search_ms_k32(SearchCtx c, SampleOut o
 
 hipError_t launch_search_sample(const SearchCtx &c, const SampleOut &o, int kt, hipStream_t s)
 {
-    const int64_t blocks = banded_grid(c, c.blocks > 0 ? c.blocks : 8192);
+    const int64_t blocks = banded_grid(c, c.blocks > 0 ? c.blocks : DEFAULT_SEARCH_BLOCKS);
     if (blocks == 0) return hipSuccess;
     const dim3 grid((unsigned)blocks), block(WAVE);
     if (c.sampler == HP_SAMPLER_MS) {
