@@ -65,11 +65,12 @@ __device__ __forceinline__ void search_sample_body(const SearchCtx &c, const Sam
     });
 }
 
-// The phases are latency bound, so occupancy matters more than registers:
-// ask for 8 waves per SIMD where the nearest-neighbour lists are short.
-__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)))
+// 6 waves per SIMD where the nearest-neighbour lists are short (85 VGPRs,
+// fewer spills than at 8; with the default grid of many more workgroups
+// than fit at once, 6 measured 3% faster than 8, and 7, 5 or 4 slower).
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_search_sample_k4(SearchCtx c, SampleOut o) { search_sample_body<4, false>(c, o); }
-__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)))
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_search_sample_k8(SearchCtx c, SampleOut o) { search_sample_body<8, false>(c, o); }
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_search_sample_k16(SearchCtx c, SampleOut o) { search_sample_body<16, false>(c, o); }
@@ -79,9 +80,9 @@ __global__ void __launch_bounds__(WAVE) k_search_sample_k32(SearchCtx c, SampleO
 }
 
 // The same search with the uniform multi-surface sampler.
-__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)))
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_search_ms_k4(SearchCtx c, SampleOut o) { search_sample_body<4, true>(c, o); }
-__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(8, 8)))
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_search_ms_k8(SearchCtx c, SampleOut o) { search_sample_body<8, true>(c, o); }
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_search_ms_k16(SearchCtx c, SampleOut o) { search_sample_body<16, true>(c, o); }
