@@ -68,17 +68,14 @@ __device__ __forceinline__ float idw_slice_bwd(const BwdArgs &A, int64_t row, in
     float wsum = 0.0f;
     const int32_t *ki = A.knn_idx + row * A.K;
     const float *kd = A.knn_dist + row * A.K;
+    const bool vec = nbr_vec_ok(A.knn_idx, A.knn_dist, A.K);
     for (int k0 = 0; k0 < A.K; k0 += 4) {
         int idx[4];
-        float w[4];
+        float d[4], w[4];
         float4 x0[4], x1[4];
+        load_nbr4(ki, kd, k0, A.K, vec, idx, d);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const bool in = k0 + j < A.K;
-            idx[j] = in ? ki[k0 + j] : -1;
-            const float d = in ? kd[k0 + j] : 1.0f;
-            w[j] = 1.0f / (d > A.eps_idw ? d : A.eps_idw);
-        }
+        for (int j = 0; j < 4; ++j) w[j] = 1.0f / (d[j] > A.eps_idw ? d[j] : A.eps_idw);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (idx[j] >= 0) {

@@ -133,6 +133,32 @@ __device__ __forceinline__ float exp_neg(float x)
     return q * __uint_as_float((uint32_t)(ki + 127) << 23);
 }
 
+// Neighbours k0 .. k0 + 3 of a list of K: indices (-1 past the end) and
+// distances (1 past the end).  With `vec` (K a multiple of 4, both arrays
+// 16-byte aligned) each array takes one 16-byte load instead of four.
+__device__ __forceinline__ bool nbr_vec_ok(const int32_t *ki, const float *kd, int K)
+{
+    return (K & 3) == 0 && ((((uintptr_t)ki) | ((uintptr_t)kd)) & 15) == 0;
+}
+
+__device__ __forceinline__ void load_nbr4(const int32_t *ki, const float *kd, int k0, int K, bool vec,
+                                          int *idx, float *d)
+{
+    if (vec) {
+        const int4 iv = *reinterpret_cast<const int4 *>(ki + k0);
+        const float4 dv = *reinterpret_cast<const float4 *>(kd + k0);
+        idx[0] = iv.x, idx[1] = iv.y, idx[2] = iv.z, idx[3] = iv.w;
+        d[0] = dv.x, d[1] = dv.y, d[2] = dv.z, d[3] = dv.w;
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const bool in = k0 + j < K;
+        idx[j] = in ? ki[k0 + j] : -1;
+        d[j] = in ? kd[k0 + j] : 1.0f;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // wave-level helpers
 // ---------------------------------------------------------------------------

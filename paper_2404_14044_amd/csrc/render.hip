@@ -33,17 +33,14 @@ __device__ __forceinline__ void idw_slice(const RenderArgs &a, int64_t row, int 
     float wsum = 0.0f;
     const int32_t *ki = a.knn_idx + row * a.K;
     const float *kd = a.knn_dist + row * a.K;
+    const bool vec = nbr_vec_ok(a.knn_idx, a.knn_dist, a.K);
     for (int k0 = 0; k0 < a.K; k0 += 4) {
         int idx[4];
-        float w[4];
+        float d[4], w[4];
         float4 x0[4], x1[4];
+        load_nbr4(ki, kd, k0, a.K, vec, idx, d);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const bool in = k0 + j < a.K;
-            idx[j] = in ? ki[k0 + j] : -1;
-            const float d = in ? kd[k0 + j] : 1.0f;
-            w[j] = 1.0f / (d > a.eps_idw ? d : a.eps_idw);
-        }
+        for (int j = 0; j < 4; ++j) w[j] = 1.0f / (d[j] > a.eps_idw ? d[j] : a.eps_idw);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (idx[j] >= 0) {
