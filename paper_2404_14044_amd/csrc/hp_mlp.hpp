@@ -56,6 +56,13 @@ __device__ __forceinline__ int hid_index(int kb, int l, int e)
     return 32 * kb + 16 * (e >> 2) + 4 * (l >> 4) + (e & 3);
 }
 
+// max(x, 0) of a matrix-core result as the integer maximum of its bits (a
+// negative number or -0 has the sign bit set and becomes +0): one
+// instruction, where the floating-point maximum takes two (the compiler first
+// quiets a possible signalling NaN, which these results never are).  Equal to
+// fmaxf(x, 0) for every x that is not a NaN.
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 __device__ __forceinline__ float softplus_f(float x)
 {
     return __builtin_fmaxf(x, 0.0f) + log1pf(expf(-__builtin_fabsf(x)));
@@ -116,7 +123,7 @@ __device__ __forceinline__ f32x4 decode_bf16(const MlpBf16 &m, const float *f, f
         f32x4 acc = {m.b1[ob][0], m.b1[ob][1], m.b1[ob][2], m.b1[ob][3]};
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.w1[ob], x, acc, 0, 0, 0);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = __builtin_fmaxf(acc[e], 0.0f);
+        for (int e = 0; e < 4; ++e) acc[e] = relu(acc[e]);
         h1[ob] = acc;
         if (keep1) keep1[ob] = acc;
     }
@@ -135,7 +142,7 @@ __device__ __forceinline__ f32x4 decode_bf16(const MlpBf16 &m, const float *f, f
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.w2[ob][0], x2[0], acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.w2[ob][1], x2[1], acc, 0, 0, 0);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = __builtin_fmaxf(acc[e], 0.0f);
+        for (int e = 0; e < 4; ++e) acc[e] = relu(acc[e]);
         h2[ob] = acc;
         if (keep2) keep2[ob] = acc;
     }
@@ -197,7 +204,7 @@ __device__ __forceinline__ f32x4 decode_f32(const MlpF32 &m, const float *f, f32
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(m.w1[ob][ks], f[ks], acc, 0, 0, 0);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = __builtin_fmaxf(acc[e], 0.0f);
+        for (int e = 0; e < 4; ++e) acc[e] = relu(acc[e]);
         h1[ob] = acc;
         if (keep1) keep1[ob] = acc;
     }
@@ -209,7 +216,7 @@ __device__ __forceinline__ f32x4 decode_f32(const MlpF32 &m, const float *f, f32
         for (int st = 0; st < 16; ++st)
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(m.w2[ob][st], h1[st >> 2][st & 3], acc, 0, 0, 0);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = __builtin_fmaxf(acc[e], 0.0f);
+        for (int e = 0; e < 4; ++e) acc[e] = relu(acc[e]);
         h2[ob] = acc;
         if (keep2) keep2[ob] = acc;
     }

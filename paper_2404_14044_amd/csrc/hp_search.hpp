@@ -588,7 +588,11 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
             if (p < totp) {
                 const int bpre = (own < WAVE) ? pa : pb;
                 const int slot = sh.bl_start[own] + (p - bpre);
-                const float4 P = c.pts[slot];
+                float4 P = c.pts[slot];
+                // one 16-byte load: otherwise the compiler loads (z, w) first
+                // and (x, y) only for points that pass the depth test, two
+                // dependent loads in place of one
+                asm volatile("" : "+v"(P.x), "+v"(P.y), "+v"(P.z), "+v"(P.w));
                 if (P.z <= sh.bl_zmax[own] && P.z >= z_lo) {
                     const float t = ray_param(P.x, P.y, P.z, g.dx, g.dy, g.dz);
                     const float e2 = dist2_at(P.x, P.y, P.z, g.dx, g.dy, g.dz, t);

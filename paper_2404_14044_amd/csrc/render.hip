@@ -24,9 +24,11 @@ namespace hp {
 
 // Aggregated feature slice (8 floats) of sample `row` for lane slice q.
 // Neighbours are taken four at a time so that their index, distance and
-// feature loads are in flight together; the sums run in neighbour order (the
-// lists are padded with -1 only at their end).
-__device__ __forceinline__ void idw_slice(const RenderArgs &a, int64_t row, int q, float *f)
+// feature loads are in flight together; the sample's four lanes divide for
+// one of the four weights each and share them through the LDS (`sh_w`, the
+// sample's slot); the sums run in neighbour order (the lists are padded with
+// -1 only at their end).
+__device__ __forceinline__ void idw_slice(const RenderArgs &a, int64_t row, int q, float4 &sh_w, float *f)
 {
 #pragma unroll
     for (int e = 0; e < 8; ++e) f[e] = 0.0f;
@@ -39,8 +41,15 @@ __device__ __forceinline__ void idw_slice(const RenderArgs &a, int64_t row, int 
         float d[4], w[4];
         float4 x0[4], x1[4];
         load_nbr4(ki, kd, k0, a.K, vec, idx, d);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) w[j] = 1.0f / (d[j] > a.eps_idw ? d[j] : a.eps_idw);
+        {
+            // the sample's four lanes share the four weights, one division each
+            const float dq = q == 0 ? d[0] : q == 1 ? d[1] : q == 2 ? d[2] : d[3];
+            wave_lds_sync();  // the previous four weights are read
+            reinterpret_cast<float *>(&sh_w)[q] = 1.0f / (dq > a.eps_idw ? dq : a.eps_idw);
+            wave_lds_sync();
+            const float4 wv = sh_w;
+            w[0] = wv.x, w[1] = wv.y, w[2] = wv.z, w[3] = wv.w;
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (idx[j] >= 0) {
@@ -76,7 +85,8 @@ __device__ __forceinline__ void idw_slice(const RenderArgs &a, int64_t row, int 
 // loaded here unless `loaded` says an earlier chunk left it in registers.
 template <int PREC, int RPW, typename Mlp>
 __device__ __forceinline__ void render_chunk(const RenderArgs &a, int64_t ray0, Mlp &mlp,
-                                             bool &loaded, float4 *sh_out, int *sh_pre)
+                                             bool &loaded, float4 *sh_out, int *sh_pre,
+                                             float4 *sh_w)
 {
     const int l = lane_id();
     const int nr = (a.n_rays - ray0) < RPW ? (int)(a.n_rays - ray0) : RPW;
@@ -110,7 +120,7 @@ __device__ __forceinline__ void render_chunk(const RenderArgs &a, int64_t ray0, 
                     if (sh_pre[mid] <= sidx) lo = mid;
                     else hi = mid;
                 }
-                idw_slice(a, (ray0 + lo) * a.S + (sidx - sh_pre[lo]), q, f);
+                idw_slice(a, (ray0 + lo) * a.S + (sidx - sh_pre[lo]), q, sh_w[r16], f);
             } else {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) f[e] = 0.0f;
@@ -118,9 +128,16 @@ __device__ __forceinline__ void render_chunk(const RenderArgs &a, int64_t ray0, 
             f32x4 o;
             if constexpr (PREC == HP_BF16) o = decode_bf16(mlp, f);
             else o = decode_f32(mlp, f);
-            if (q == 0 && valid)
-                sh_out[sidx] = make_float4(sigmoid_f(o[0]), sigmoid_f(o[1]), sigmoid_f(o[2]),
-                                           softplus_f(o[3]));
+            // the four outputs of a sample sit in its q = 0 lane; each lane of
+            // the sample takes one of them through the LDS, so the
+            // activations run on all lanes instead of a quarter of them
+            if (q == 0 && valid) sh_out[sidx] = make_float4(o[0], o[1], o[2], o[3]);
+            wave_lds_sync();
+            if (valid) {
+                float *out = reinterpret_cast<float *>(&sh_out[sidx]) + q;
+                const float x = *out;
+                *out = q < 3 ? sigmoid_f(x) : softplus_f(x);
+            }
         }
     }
     __syncthreads();
@@ -162,15 +179,16 @@ __device__ __forceinline__ void render_body(const RenderArgs &a)
 {
     extern __shared__ float4 sh_out[];  // [RPW * S] (rgb, sigma) per sample
     __shared__ int sh_pre[RPW + 1];
+    __shared__ float4 sh_w[16];  // inverse-distance weights of a tile's samples
     typename std::conditional<PREC == HP_BF16, MlpBf16, MlpF32>::type mlp;
     bool loaded = false;
     const int64_t n_chunks = (a.n_rays + RPW - 1) / RPW;
     if constexpr (!PERSIST) {
         if ((int64_t)blockIdx.x < n_chunks)
-            render_chunk<PREC, RPW>(a, (int64_t)blockIdx.x * RPW, mlp, loaded, sh_out, sh_pre);
+            render_chunk<PREC, RPW>(a, (int64_t)blockIdx.x * RPW, mlp, loaded, sh_out, sh_pre, sh_w);
     } else {
         for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
-            render_chunk<PREC, RPW>(a, ch * RPW, mlp, loaded, sh_out, sh_pre);
+            render_chunk<PREC, RPW>(a, ch * RPW, mlp, loaded, sh_out, sh_pre, sh_w);
             __syncthreads();  // this chunk's compositing read sh_pre / sh_out
         }
     }
