@@ -103,14 +103,23 @@ __device__ __forceinline__ void load_mlp_bf16(const MlpWeights &a, MlpBf16 &m)
             m.b2[ob][e] = a.b2[16 * ob + 4 * q + e];
         }
     }
+    // rows 4 .. 15 of the output block are zero padding; their lanes load a
+    // real row and drop it, so that no load waits behind a branch
+    const int r3 = r < 4 ? r : 3;
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) tmp[e] = (r < 4) ? a.W3[r * HP_HIDDEN + hid_index(kb, l, e)] : 0.0f;
+        for (int e = 0; e < 8; ++e) {
+            const float w = a.W3[r3 * HP_HIDDEN + hid_index(kb, l, e)];
+            tmp[e] = r < 4 ? w : 0.0f;
+        }
         m.w3[kb] = pack_bf16x8(tmp);
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) m.b3[e] = (4 * q + e < 4) ? a.b3[4 * q + e] : 0.0f;
+    for (int e = 0; e < 4; ++e) {
+        const float b = a.b3[(4 * q + e) & 3];
+        m.b3[e] = q == 0 ? b : 0.0f;
+    }
 }
 
 __device__ __forceinline__ f32x4 decode_bf16(const MlpBf16 &m, const float *f, f32x4 *keep1 = nullptr,
@@ -187,11 +196,17 @@ __device__ __forceinline__ void load_mlp_f32(const MlpWeights &a, MlpF32 &m)
             m.b2[ob][e] = a.b2[16 * ob + 4 * q + e];
         }
     }
+    const int r3 = r < 4 ? r : 3;  // padding rows: see load_mlp_bf16
 #pragma unroll
-    for (int st = 0; st < 16; ++st)
-        m.w3[st] = (r < 4) ? a.W3[r * HP_HIDDEN + 16 * (st >> 2) + 4 * q + (st & 3)] : 0.0f;
+    for (int st = 0; st < 16; ++st) {
+        const float w = a.W3[r3 * HP_HIDDEN + 16 * (st >> 2) + 4 * q + (st & 3)];
+        m.w3[st] = r < 4 ? w : 0.0f;
+    }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) m.b3[e] = (4 * q + e < 4) ? a.b3[4 * q + e] : 0.0f;
+    for (int e = 0; e < 4; ++e) {
+        const float b = a.b3[(4 * q + e) & 3];
+        m.b3[e] = q == 0 ? b : 0.0f;
+    }
 }
 
 __device__ __forceinline__ f32x4 decode_f32(const MlpF32 &m, const float *f, f32x4 *keep1 = nullptr,

@@ -145,10 +145,14 @@ __device__ __forceinline__ void render_chunk(const RenderArgs &a, int64_t ray0, 
         const int64_t ray = ray0 + l;
         const int base = sh_pre[l];
         float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f, dep = 0.0f, ws = 0.0f;
+        const float *tr = a.t + ray * a.S;
+        float t = ns > 0 ? tr[0] : 0.0f;
         for (int s = 0; s < ns; ++s) {
             const float4 v = sh_out[base + s];
-            const float t = a.t[ray * a.S + s];
-            const float delta = (s + 1 < ns) ? a.t[ray * a.S + s + 1] - t : a.delta_last;
+            // the next depth is loaded whether or not it exists (the last
+            // sample reloads its own), so no load waits behind a branch
+            const float tn = tr[s + 1 < ns ? s + 1 : s];
+            const float delta = (s + 1 < ns) ? tn - t : a.delta_last;
             const float e = expf(-v.w * delta);
             const float w = T * (1.0f - e);
             cr = fma_rn(w, v.x, cr);
@@ -157,6 +161,7 @@ __device__ __forceinline__ void render_chunk(const RenderArgs &a, int64_t ray0, 
             dep = fma_rn(w, t, dep);
             ws += w;
             T *= e;
+            t = tn;
         }
         const float rest = 1.0f - ws;
         a.rgb[3 * ray + 0] = fma_rn(rest, a.bg[0], cr);
