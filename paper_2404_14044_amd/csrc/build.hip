@@ -302,7 +302,7 @@ __device__ __forceinline__ uint64_t sort_bucket_to_slots(const uint64_t *__restr
 }
 
 // ---------------------------------------------------------------------------
-// Two-level build (tables of up to SB_MAX superbuckets).  Per-point atomics
+// Two-level build (views of up to SB_MAX superbuckets each).  Per-point atomics
 // on the bucket counters cost the build most of its time: device-scope
 // atomics whose returned value the point needs (its rank in the bucket)
 // stall at the memory side, one per point.  Here buckets are grouped into
@@ -689,7 +689,17 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
     const int64_t nv = n * V;
     k_init_views<<<1, HP_MAX_VIEWS, 0, s>>>(vs, tw.views);
     const int64_t nsb = (n_buckets + SB - 1) / SB;
-    if (nsb <= SB_MAX) {
+    // the projection passes count a view's points per superbucket in LDS, so
+    // each view may span at most SB_MAX superbuckets (the table as a whole
+    // may span more)
+    int64_t view_sb_max = 0;
+    for (int i = 0; i < V; ++i) {
+        const ViewK &vk = vs.v[i];
+        const int64_t lo = vk.bucket_base >> SB_SHIFT;
+        const int64_t hi = ((int64_t)vk.bucket_base + (int64_t)vk.Wg * vk.Hg - 1) >> SB_SHIFT;
+        view_sb_max = max(view_sb_max, hi - lo + 1);
+    }
+    if (view_sb_max <= SB_MAX && nsb <= INT32_MAX / SB) {
         // two-level build: superbucket totals, records by superbucket, then
         // each superbucket's buckets in LDS
         k_fill_i32<<<64, 256, 0, s>>>(tw.sb_count, 0, tw.sb_words);  // totals, cursors, big_n[2]
@@ -715,7 +725,7 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
         finish_build(nullptr, n, vs, tw, false, s);
         return hipGetLastError();
     }
-    // one level (tables beyond SB_MAX superbuckets): a counter per bucket
+    // one level (a view beyond SB_MAX superbuckets): a counter per bucket
     k_fill_i32<<<1024, 256, 0, s>>>(tw.count, 0, n_buckets);
     k_fill_i32<<<1, 64, 0, s>>>(tw.big_n, 0, 2);
     if (n > 0)

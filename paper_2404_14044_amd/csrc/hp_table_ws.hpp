@@ -10,7 +10,8 @@
 namespace hp {
 
 // Superbuckets of the two-level build: SB = 2^SB_SHIFT consecutive bucket
-// keys; tables of up to SB_MAX of them (2^23 buckets) take that path.
+// keys; tables whose views each span at most SB_MAX of them (2^23 buckets)
+// take that path.
 constexpr int SB_SHIFT = 10;
 constexpr int SB_MAX = 8192;
 

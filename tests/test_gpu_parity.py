@@ -304,6 +304,28 @@ def test_table_beyond_the_superbucket_limit():
     assert (ex["n_sel"] > 0).sum() > 100
 
 
+def test_views_beyond_the_superbucket_limit_together():
+    """Ten 1000 x 1000 views span more than 2^13 superbuckets together but
+    fewer each: the two-level build takes them (its per-view LDS counts are
+    what bounds it), and every view's table and rays match the oracle."""
+    base = scenes.objects_1m(n=120_000, res=64)
+    rng = np.random.default_rng(41)
+    cams = scenes.sphere_poses(rng, 10, 4.0, [1000] * 10)
+    sc = scenes.Scene("ten_views", base.xyz, base.feat, cams,
+                      base.params.replace(n_samples=4), base.mlp)
+    out = gpu_forward(sc, debug=False)
+    tab = out["table"]
+    assert tab.n_buckets > (1 << 23)
+    for v, cam in enumerate(sc.cams):
+        compare_table_rowmajor(sc, tab, view=v)
+    for v in (0, 9):
+        info = tab.view(v)
+        pix = sample_pixels(sc.cams[v], 512, seed=50 + v)
+        ex = compare_exact(sc, out["samples"], pix, view=v, ray_base=info.ray_base,
+                           check_lists=False)
+        assert (ex["n_sel"] > 0).sum() > 20
+
+
 def test_objects_sampled_rays(objects):
     sc = objects
     from paper_2404_14044_amd import hashpoint as hp
