@@ -10,8 +10,8 @@
 //   k_scan_*       counts         -> exclusive offsets, three passes
 //   k_scatter      (view, point)  -> 64-bit key (z bits, point index) per slot
 //   k_sort_small   one lane per bucket of at most 16 points, register network
-//   k_sort_mid     one wave per bucket of 17..128 points, register bitonic
-//   k_sort_big     one workgroup per larger bucket, bitonic in LDS or global
+//   k_sort_listed  one wave per bucket of 17..128 points, register bitonic;
+//                  one workgroup per larger bucket, bitonic in LDS or global
 //   k_materialize  one lane per slot: camera-space point and index (from pcam)
 #include "hp_device.hpp"
 #include "hp_kernels.hpp"
@@ -20,17 +20,21 @@
 
 namespace hp {
 
-__global__ void k_init_views(ViewSet vs, ViewK *out)
-{
-    const int i = threadIdx.x;
-    if (i < vs.n) out[i] = vs.v[i];
-}
-
 __global__ void k_fill_i32(int32_t *p, int32_t val, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = val;
+}
+
+// The build's first launch: the views' constants to device memory (first
+// workgroup) and n counters cleared (all of them).
+__global__ void k_build_begin(ViewSet vs, ViewK *out, int32_t *p, int64_t n)
+{
+    if (blockIdx.x == 0 && threadIdx.x < vs.n) out[threadIdx.x] = vs.v[threadIdx.x];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
 }
 
 // grid: (ceil(n / (256 PROJ_PER)), n_views).  Each thread takes PROJ_PER
@@ -228,8 +232,8 @@ constexpr int SMALL_MAX = 16;
 
 // Buckets of more than SMALL_MAX points are listed for the wave and
 // workgroup sorts: those of up to 128 points from the front of big_list
-// (count big_n[0], k_sort_mid), larger ones from its back (count big_n[1],
-// k_sort_big), so that neither kernel walks the other's entries.
+// (count big_n[0], sort_mid), larger ones from its back (count big_n[1],
+// sort_big), so that neither role walks the other's entries.
 __device__ __forceinline__ void list_big_bucket(int32_t *__restrict__ big_list,
                                                 int32_t *__restrict__ big_n, int64_t cap, int b,
                                                 int cnt)
@@ -255,7 +259,7 @@ __global__ void __launch_bounds__(256) k_sort_small(const int32_t *__restrict__ 
     else if (cnt > 8 && cnt <= SMALL_MAX) first = sort_bucket_regs<16>(skey, start, cnt);
     else if (cnt > SMALL_MAX) {
         list_big_bucket(big_list, big_n, nb, (int32_t)b, cnt);
-        return;  // k_sort_mid / k_sort_big write bucket_z
+        return;  // k_sort_listed writes bucket_z
     }
     bucket_z[b] = cnt > 0 ? __uint_as_float((uint32_t)(first >> 32)) : __builtin_inff();
 }
@@ -440,7 +444,7 @@ __global__ void __launch_bounds__(SB_T) k_scatter_sb(const int2 *__restrict__ kz
 // One workgroup per superbucket: bucket counts (LDS atomics), their scan
 // (the table's offsets for these SB keys), placement of every record, then
 // each bucket of at most SMALL_MAX points sorted by (z, index) in registers
-// (larger ones are listed for k_sort_mid / k_sort_big) and its depth noted.
+// (larger ones are listed for k_sort_listed) and its depth noted.
 constexpr int FIN_T = 512;  // threads of a superbucket's workgroup
 
 __global__ void __launch_bounds__(FIN_T) k_finalize_sb(const int4 *__restrict__ rec,
@@ -498,7 +502,7 @@ __global__ void __launch_bounds__(FIN_T) k_finalize_sb(const int4 *__restrict__ 
         const int start = cur[k] - n_b;
         if (n_b > SMALL_MAX) {
             list_big_bucket(big_list, big_n, n_buckets, b, n_b);
-            continue;  // k_sort_mid / k_sort_big sort it, place it and write bucket_z
+            continue;  // k_sort_listed sorts it, places it and writes bucket_z
         }
         uint64_t first = ~0ull;
         if (n_b > 0) {
@@ -559,16 +563,18 @@ __device__ void block_flip_bitonic(int cnt, Load ld, Store st)
 
 // Buckets of 17..128 points: one wave each, a register bitonic sort across
 // the wave (one or two keys per lane), no LDS and no workgroup barrier.
-__global__ void __launch_bounds__(256) k_sort_mid(const int32_t *__restrict__ offsets,
-                                                  uint64_t *__restrict__ skey,
-                                                  const int32_t *__restrict__ big_list,
-                                                  const int32_t *__restrict__ big_n,
-                                                  float *__restrict__ bucket_z, SlotOut so)
+// (workgroup `blk` of `nblk` taking this role)
+__device__ __forceinline__ void sort_mid(const int32_t *__restrict__ offsets,
+                                         uint64_t *__restrict__ skey,
+                                         const int32_t *__restrict__ big_list,
+                                         const int32_t *__restrict__ big_n,
+                                         float *__restrict__ bucket_z, const SlotOut &so, int blk,
+                                         int nblk)
 {
     const int nbig = big_n[0];
     const int l = lane_id();
     const int waves = blockDim.x / WAVE;
-    for (int it = blockIdx.x * waves + (threadIdx.x >> 6); it < nbig; it += gridDim.x * waves) {
+    for (int it = blk * waves + (threadIdx.x >> 6); it < nbig; it += nblk * waves) {
         const int b = big_list[it];
         const int start = offsets[b];
         const int cnt = offsets[b + 1] - start;
@@ -599,16 +605,15 @@ __global__ void __launch_bounds__(256) k_sort_mid(const int32_t *__restrict__ of
 
 // Buckets of more than 128 points: one workgroup each, bitonic in LDS (in
 // global memory beyond BIG_LDS entries).
-__global__ void __launch_bounds__(BIG_T) k_sort_big(const int32_t *__restrict__ offsets,
-                                                    uint64_t *__restrict__ skey,
-                                                    const int32_t *__restrict__ big_list,
-                                                    const int32_t *__restrict__ big_n,
-                                                    float *__restrict__ bucket_z, int64_t cap,
-                                                    SlotOut so)
+__device__ __forceinline__ void sort_big(const int32_t *__restrict__ offsets,
+                                         uint64_t *__restrict__ skey,
+                                         const int32_t *__restrict__ big_list,
+                                         const int32_t *__restrict__ big_n,
+                                         float *__restrict__ bucket_z, int64_t cap, const SlotOut &so,
+                                         uint64_t *sh, int blk, int nblk)
 {
-    __shared__ uint64_t sh[BIG_LDS];
     const int nbig = big_n[1];
-    for (int it = blockIdx.x; it < nbig; it += gridDim.x) {
+    for (int it = blk; it < nbig; it += nblk) {
         const int b = big_list[cap - 1 - it];
         const int start = offsets[b];
         const int cnt = offsets[b + 1] - start;
@@ -630,6 +635,27 @@ __global__ void __launch_bounds__(BIG_T) k_sort_big(const int32_t *__restrict__ 
         if (threadIdx.x == 0) bucket_z[b] = __uint_as_float((uint32_t)(g[0] >> 32));
         __syncthreads();
     }
+}
+
+// The listed buckets in one launch: the first MID_BLOCKS workgroups sort those
+// of 17..128 points (a wave each), the other BIG_BLOCKS the larger ones.
+constexpr int MID_BLOCKS = 1024;
+constexpr int BIG_BLOCKS = 256;
+static_assert(BIG_T == 256, "both roles run 256-thread workgroups");
+
+__global__ void __launch_bounds__(256) k_sort_listed(const int32_t *__restrict__ offsets,
+                                                     uint64_t *__restrict__ skey,
+                                                     const int32_t *__restrict__ big_list,
+                                                     const int32_t *__restrict__ big_n,
+                                                     float *__restrict__ bucket_z, int64_t cap,
+                                                     SlotOut so)
+{
+    __shared__ uint64_t sh[BIG_LDS];
+    if (blockIdx.x < MID_BLOCKS)
+        sort_mid(offsets, skey, big_list, big_n, bucket_z, so, blockIdx.x, MID_BLOCKS);
+    else
+        sort_big(offsets, skey, big_list, big_n, bucket_z, cap, so, sh, blockIdx.x - MID_BLOCKS,
+                 BIG_BLOCKS);
 }
 
 // Minimum depth of each CELL x CELL block of buckets, from the buckets'
@@ -687,7 +713,6 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
 {
     const int V = vs.n;
     const int64_t nv = n * V;
-    k_init_views<<<1, HP_MAX_VIEWS, 0, s>>>(vs, tw.views);
     const int64_t nsb = (n_buckets + SB - 1) / SB;
     // the projection passes count a view's points per superbucket in LDS, so
     // each view may span at most SB_MAX superbuckets (the table as a whole
@@ -702,7 +727,7 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
     if (view_sb_max <= SB_MAX && nsb <= INT32_MAX / SB) {
         // two-level build: superbucket totals, records by superbucket, then
         // each superbucket's buckets in LDS
-        k_fill_i32<<<64, 256, 0, s>>>(tw.sb_count, 0, tw.sb_words);  // totals, cursors, big_n[2]
+        k_build_begin<<<64, 256, 0, s>>>(vs, tw.views, tw.sb_count, tw.sb_words);  // totals, cursors, big_n[2]
         if (nv > 0) {
             const dim3 grid((unsigned)((n + SB_T * SB_PER - 1) / (SB_T * SB_PER)), V);
             k_project_sb<<<grid, SB_T, 0, s>>>(xyz, n, tw.views, vs.layout, tw.kz, tw.pcam,
@@ -719,14 +744,13 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
         k_finalize_sb<<<(unsigned)nsb, FIN_T, 0, s>>>(reinterpret_cast<const int4 *>(tw.pts), tw.sb_off,
                                                      n_buckets, tw.offsets, tw.skey, tw.big_list,
                                                      tw.big_n, tw.bucket_z, so);
-        k_sort_mid<<<1024, 256, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z, so);
-        k_sort_big<<<256, BIG_T, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z,
-                                         n_buckets, so);
+        k_sort_listed<<<MID_BLOCKS + BIG_BLOCKS, 256, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n,
+                                                            tw.bucket_z, n_buckets, so);
         finish_build(nullptr, n, vs, tw, false, s);
         return hipGetLastError();
     }
     // one level (a view beyond SB_MAX superbuckets): a counter per bucket
-    k_fill_i32<<<1024, 256, 0, s>>>(tw.count, 0, n_buckets);
+    k_build_begin<<<1024, 256, 0, s>>>(vs, tw.views, tw.count, n_buckets);
     k_fill_i32<<<1, 64, 0, s>>>(tw.big_n, 0, 2);
     if (n > 0)
         k_project<<<dim3((unsigned)((n + 256 * PROJ_PER - 1) / (256 * PROJ_PER)), V), 256, 0, s>>>(
@@ -738,9 +762,8 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
     if (nv > 0) k_scatter<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(tw.kz, tw.perm, nv, n, tw.offsets, tw.skey);
     k_sort_small<<<(unsigned)((n_buckets + 255) / 256), 256, 0, s>>>(tw.offsets, n_buckets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z);
     const SlotOut none{nullptr, 0, nullptr, 0, nullptr, nullptr};
-    k_sort_mid<<<1024, 256, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z, none);
-    k_sort_big<<<256, BIG_T, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n, tw.bucket_z,
-                                     n_buckets, none);
+    k_sort_listed<<<MID_BLOCKS + BIG_BLOCKS, 256, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n,
+                                                        tw.bucket_z, n_buckets, none);
     finish_build(xyz, n, vs, tw, true, s);
     return hipGetLastError();
 }
