@@ -141,7 +141,7 @@ typedef struct hp_camera {
  *  search_band: consecutive rays dealt to one XCD at a time by the search
  *      kernels, 0 (12,800) or 64..2^24;
  *  window_shape: HP_WINDOW_DISC or HP_WINDOW_SQUARE;
- *  render_rays: rays a render wave composites at a time, 0 (32), 16, 32 or 64;
+ *  render_rays: rays a render wave composites at a time, 0 (16), 16, 32 or 64;
  *  render_blocks: render grid; a workgroup takes every render_blocks-th
  *      chunk of render_rays rays (persistent, loading the decoder weights
  *      once), 0 = one workgroup per chunk. */

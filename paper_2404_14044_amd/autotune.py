@@ -41,7 +41,7 @@ SPACE = {
 }
 # the values the library takes for 0 (its defaults), the descent's start
 DEFAULTS = {"layout": hp.HP_LAYOUT_ROWMAJOR, "search_chunk": 4, "search_blocks": 65536,
-            "search_band": 12800, "window_shape": hp.HP_WINDOW_DISC, "render_rays": 32,
+            "search_band": 12800, "window_shape": hp.HP_WINDOW_DISC, "render_rays": 16,
             "render_blocks": 0}
 
 

@@ -459,7 +459,7 @@ hp_status hp_render(const hp_samples *smp, int64_t R, const float *feat, int32_t
     a.rgb = rgb;
     a.depth = depth;
     a.acc = acc;
-    a.rpw = p->render_rays > 0 ? p->render_rays : 32;
+    a.rpw = p->render_rays > 0 ? p->render_rays : 16;
     a.blocks = p->render_blocks;
     const hipError_t e = hp::launch_render(a, precision, (hipStream_t)stream);
     return e == hipSuccess ? HP_OK : hip_fail(e);

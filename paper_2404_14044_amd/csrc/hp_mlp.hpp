@@ -79,42 +79,67 @@ struct MlpBf16 {
     bf16x8 w2[4][2];   // [out block][k block]
     bf16x8 w3[2];      // [k block]
     float b1[4][4], b2[4][4], b3[4];
+
+    __device__ __forceinline__ bf16x8 W1(int ob) const { return w1[ob]; }
+    __device__ __forceinline__ bf16x8 W2(int ob, int kb) const { return w2[ob][kb]; }
+    __device__ __forceinline__ bf16x8 W3(int kb) const { return w3[kb]; }
+    __device__ __forceinline__ f32x4 B1(int ob) const { return {b1[ob][0], b1[ob][1], b1[ob][2], b1[ob][3]}; }
+    __device__ __forceinline__ f32x4 B2(int ob) const { return {b2[ob][0], b2[ob][1], b2[ob][2], b2[ob][3]}; }
+    __device__ __forceinline__ f32x4 B3() const { return {b3[0], b3[1], b3[2], b3[3]}; }
 };
+
+// The lane's A-operand fragments (8 bf16 of one weight row), one function
+// per piece so that the register and the shared copies of the weights hold
+// the same bits.
+__device__ __forceinline__ bf16x8 w1_fragment(const MlpWeights &a, int ob, int l)
+{
+    const int r = l & 15, q = l >> 4;
+    float tmp[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) tmp[e] = a.W1[(16 * ob + r) * HP_FEAT_DIM + 8 * q + e];
+    return pack_bf16x8(tmp);
+}
+
+__device__ __forceinline__ bf16x8 w2_fragment(const MlpWeights &a, int ob, int kb, int l)
+{
+    const int r = l & 15;
+    float tmp[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) tmp[e] = a.W2[(16 * ob + r) * HP_HIDDEN + hid_index(kb, l, e)];
+    return pack_bf16x8(tmp);
+}
+
+// rows 4 .. 15 of the output block are zero padding; their lanes load a
+// real row and drop it, so that no load waits behind a branch
+__device__ __forceinline__ bf16x8 w3_fragment(const MlpWeights &a, int kb, int l)
+{
+    const int r = l & 15, r3 = r < 4 ? r : 3;
+    float tmp[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float w = a.W3[r3 * HP_HIDDEN + hid_index(kb, l, e)];
+        tmp[e] = r < 4 ? w : 0.0f;
+    }
+    return pack_bf16x8(tmp);
+}
 
 __device__ __forceinline__ void load_mlp_bf16(const MlpWeights &a, MlpBf16 &m)
 {
     const int l = lane_id();
-    const int r = l & 15, q = l >> 4;
-    float tmp[8];
+    const int q = l >> 4;
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
+        m.w1[ob] = w1_fragment(a, ob, l);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) tmp[e] = a.W1[(16 * ob + r) * HP_FEAT_DIM + 8 * q + e];
-        m.w1[ob] = pack_bf16x8(tmp);
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) tmp[e] = a.W2[(16 * ob + r) * HP_HIDDEN + hid_index(kb, l, e)];
-            m.w2[ob][kb] = pack_bf16x8(tmp);
-        }
+        for (int kb = 0; kb < 2; ++kb) m.w2[ob][kb] = w2_fragment(a, ob, kb, l);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             m.b1[ob][e] = a.b1[16 * ob + 4 * q + e];
             m.b2[ob][e] = a.b2[16 * ob + 4 * q + e];
         }
     }
-    // rows 4 .. 15 of the output block are zero padding; their lanes load a
-    // real row and drop it, so that no load waits behind a branch
-    const int r3 = r < 4 ? r : 3;
 #pragma unroll
-    for (int kb = 0; kb < 2; ++kb) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float w = a.W3[r3 * HP_HIDDEN + hid_index(kb, l, e)];
-            tmp[e] = r < 4 ? w : 0.0f;
-        }
-        m.w3[kb] = pack_bf16x8(tmp);
-    }
+    for (int kb = 0; kb < 2; ++kb) m.w3[kb] = w3_fragment(a, kb, l);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const float b = a.b3[(4 * q + e) & 3];
@@ -122,15 +147,63 @@ __device__ __forceinline__ void load_mlp_bf16(const MlpWeights &a, MlpBf16 &m)
     }
 }
 
-__device__ __forceinline__ f32x4 decode_bf16(const MlpBf16 &m, const float *f, f32x4 *keep1 = nullptr,
+// The same weights in the LDS, shared by the waves of a workgroup: each lane
+// reads its own fragments (16-byte reads) when a tile needs them, so they
+// hold no registers between tiles.
+struct MlpBf16Shared {
+    bf16x8 w1[4][WAVE];
+    bf16x8 w2[4][2][WAVE];
+    bf16x8 w3[2][WAVE];
+    float4 b1[16], b2[16], b3[4];  // [4 ob + q]: biases 16 ob + 4 q .. + 3; b3: [q]
+
+    __device__ __forceinline__ bf16x8 W1(int ob) const { return w1[ob][lane_id()]; }
+    __device__ __forceinline__ bf16x8 W2(int ob, int kb) const { return w2[ob][kb][lane_id()]; }
+    __device__ __forceinline__ bf16x8 W3(int kb) const { return w3[kb][lane_id()]; }
+    __device__ __forceinline__ f32x4 B1(int ob) const
+    {
+        const float4 v = b1[4 * ob + (lane_id() >> 4)];
+        return {v.x, v.y, v.z, v.w};
+    }
+    __device__ __forceinline__ f32x4 B2(int ob) const
+    {
+        const float4 v = b2[4 * ob + (lane_id() >> 4)];
+        return {v.x, v.y, v.z, v.w};
+    }
+    __device__ __forceinline__ f32x4 B3() const
+    {
+        const float4 v = b3[lane_id() >> 4];
+        return {v.x, v.y, v.z, v.w};
+    }
+};
+
+// Fill the shared weights: wave `w` of `nw` packs every nw-th fragment (all
+// waves of the workgroup call this; a barrier must follow before use).
+__device__ __forceinline__ void store_mlp_bf16_shared(const MlpWeights &a, MlpBf16Shared &m, int w,
+                                                      int nw)
+{
+    const int l = lane_id();
+    for (int p = w; p < 14; p += nw) {
+        if (p < 4) m.w1[p][l] = w1_fragment(a, p, l);
+        else if (p < 12) m.w2[(p - 4) >> 1][(p - 4) & 1][l] = w2_fragment(a, (p - 4) >> 1, (p - 4) & 1, l);
+        else m.w3[p - 12][l] = w3_fragment(a, p - 12, l);
+    }
+    if (w == 0) {
+        reinterpret_cast<float *>(m.b1)[l] = a.b1[l];
+        reinterpret_cast<float *>(m.b2)[l] = a.b2[l];
+        if (l < 16) reinterpret_cast<float *>(m.b3)[l] = l < 4 ? a.b3[l] : 0.0f;
+    }
+}
+
+template <typename M>
+__device__ __forceinline__ f32x4 decode_bf16(const M &m, const float *f, f32x4 *keep1 = nullptr,
                                              f32x4 *keep2 = nullptr)
 {
     const bf16x8 x = pack_bf16x8(f);
     f32x4 h1[4];
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
-        f32x4 acc = {m.b1[ob][0], m.b1[ob][1], m.b1[ob][2], m.b1[ob][3]};
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.w1[ob], x, acc, 0, 0, 0);
+        f32x4 acc = m.B1(ob);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.W1(ob), x, acc, 0, 0, 0);
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[e] = relu(acc[e]);
         h1[ob] = acc;
@@ -147,9 +220,9 @@ __device__ __forceinline__ f32x4 decode_bf16(const MlpBf16 &m, const float *f, f
     f32x4 h2[4];
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
-        f32x4 acc = {m.b2[ob][0], m.b2[ob][1], m.b2[ob][2], m.b2[ob][3]};
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.w2[ob][0], x2[0], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.w2[ob][1], x2[1], acc, 0, 0, 0);
+        f32x4 acc = m.B2(ob);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.W2(ob, 0), x2[0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.W2(ob, 1), x2[1], acc, 0, 0, 0);
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[e] = relu(acc[e]);
         h2[ob] = acc;
@@ -163,9 +236,9 @@ __device__ __forceinline__ f32x4 decode_bf16(const MlpBf16 &m, const float *f, f
         for (int e = 0; e < 8; ++e) t8[e] = h2[2 * kb + (e >> 2)][e & 3];
         x3[kb] = pack_bf16x8(t8);
     }
-    f32x4 o = {m.b3[0], m.b3[1], m.b3[2], m.b3[3]};
-    o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.w3[0], x3[0], o, 0, 0, 0);
-    o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.w3[1], x3[1], o, 0, 0, 0);
+    f32x4 o = m.B3();
+    o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.W3(0), x3[0], o, 0, 0, 0);
+    o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(m.W3(1), x3[1], o, 0, 0, 0);
     return o;
 }
 

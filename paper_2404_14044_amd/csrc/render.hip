@@ -1,8 +1,11 @@
 // Decode and composite the samples (Sec. 3.4, Eq. 2).
 //
-// One wave per chunk of RPW consecutive rays at a time (a persistent grid,
-// see render_body).  The wave packs the chunk's samples densely into tiles
-// of 16, and for each tile:
+// One wave per chunk of RPW consecutive rays (16 by default).  BF16: eight
+// waves per workgroup, one chunk each, with the decoder weights packed once
+// per workgroup into the LDS (k_render_bf16_shared); FP32, the persistent
+// grid and chunks too large for that: one wave per workgroup with the
+// weights in its registers (render_body).  The wave packs the chunk's
+// samples densely into tiles of 16, and for each tile:
 //   1. aggregates the features of every sample's K neighbours with
 //      inverse-distance weights (FP32): lane l handles sample l % 16 and
 //      feature slice 8 (l / 16) .. +8, reading 32 contiguous bytes per neighbour;
@@ -80,67 +83,72 @@ __device__ __forceinline__ void idw_slice(const RenderArgs &a, int64_t row, int 
     for (int e = 0; e < 8; ++e) f[e] *= inv;
 }
 
-// One chunk of RPW consecutive rays starting at ray0: pack its samples into
-// tiles of 16, aggregate and decode them, composite each ray.  `mlp` is
-// loaded here unless `loaded` says an earlier chunk left it in registers.
-template <int PREC, int RPW, typename Mlp>
-__device__ __forceinline__ void render_chunk(const RenderArgs &a, int64_t ray0, Mlp &mlp,
-                                             bool &loaded, float4 *sh_out, int *sh_pre,
-                                             float4 *sh_w)
+// Sample-count prefix of the chunk of RPW consecutive rays at ray0: sh_pre[r]
+// = first sample of chunk ray r, sh_pre[RPW] = the chunk's samples.  Returns
+// the lane's own ray's count (lane r < the chunk's rays) and the total.
+struct ChunkCounts {
+    int nr, ns, total;
+};
+
+template <int RPW>
+__device__ __forceinline__ ChunkCounts chunk_prefix(const RenderArgs &a, int64_t ray0, int *sh_pre)
 {
     const int l = lane_id();
-    const int nr = (a.n_rays - ray0) < RPW ? (int)(a.n_rays - ray0) : RPW;
-
-    // prefix of sample counts over the chunk
+    ChunkCounts c;
+    c.nr = (a.n_rays - ray0) < RPW ? (int)(a.n_rays - ray0) : RPW;
     // (a count beyond the sample cap would index past the ray's rows and the
     // chunk's LDS)
-    const int ns = (l < nr) ? min(max(a.n_sel[ray0 + l], 0), a.S) : 0;
-    const int inc = wave_incl_scan_i32(ns);
-    if (l < RPW) sh_pre[l] = inc - ns;
-    const int total = readlane_i32(inc, WAVE - 1);
-    if (l == 0) sh_pre[RPW] = total;
-    __syncthreads();
+    c.ns = (l < c.nr) ? min(max(a.n_sel[ray0 + l], 0), a.S) : 0;
+    const int inc = wave_incl_scan_i32(c.ns);
+    if (l < RPW) sh_pre[l] = inc - c.ns;
+    c.total = readlane_i32(inc, WAVE - 1);
+    if (l == 0) sh_pre[RPW] = c.total;
+    wave_lds_sync();
+    return c;
+}
 
-    if (total > 0) {
-        if (PREC != HP_BF16 || !loaded) {
-            const MlpWeights wts{a.W1, a.b1, a.W2, a.b2, a.W3, a.b3};
-            if constexpr (PREC == HP_BF16) load_mlp_bf16(wts, mlp);
-            else load_mlp_f32(wts, mlp);
-            loaded = true;
+// The chunk's samples in tiles of 16: aggregate, decode (`decode`: the
+// decoder on one tile's aggregated slices), activations; then each ray
+// composited by its lane.  Only this wave touches sh_out, sh_pre and sh_w.
+template <int RPW, typename Decode>
+__device__ __forceinline__ void chunk_body(const RenderArgs &a, int64_t ray0, const ChunkCounts &c,
+                                           Decode decode, float4 *sh_out, const int *sh_pre,
+                                           float4 *sh_w)
+{
+    const int l = lane_id();
+    const int nr = c.nr, ns = c.ns, total = c.total;
+    const int r16 = l & 15, q = l >> 4;
+    const auto activate = [&](const f32x4 &o, int sidx, bool valid) {
+        // the four outputs of a sample sit in its q = 0 lane; each lane of
+        // the sample takes one of them through the LDS, so the activations
+        // run on all lanes instead of a quarter of them
+        if (q == 0 && valid) sh_out[sidx] = make_float4(o[0], o[1], o[2], o[3]);
+        wave_lds_sync();
+        if (valid) {
+            float *out = reinterpret_cast<float *>(&sh_out[sidx]) + q;
+            const float x = *out;
+            *out = q < 3 ? sigmoid_f(x) : softplus_f(x);
         }
-        const int r16 = l & 15, q = l >> 4;
-        for (int s0 = 0; s0 < total; s0 += 16) {
-            const int sidx = s0 + r16;
-            const bool valid = sidx < total;
-            float f[8];
-            if (valid) {
-                int lo = 0, hi = nr;  // chunk-local ray: last with pre <= sidx
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (sh_pre[mid] <= sidx) lo = mid;
-                    else hi = mid;
-                }
-                idw_slice(a, (ray0 + lo) * a.S + (sidx - sh_pre[lo]), q, sh_w[r16], f);
-            } else {
+    };
+    for (int s0 = 0; s0 < total; s0 += 16) {
+        const int sidx = s0 + r16;
+        const bool valid = sidx < total;
+        float f[8];
+        if (valid) {
+            int lo = 0, hi = nr;  // chunk-local ray: last with pre <= sidx
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (sh_pre[mid] <= sidx) lo = mid;
+                else hi = mid;
+            }
+            idw_slice(a, (ray0 + lo) * a.S + (sidx - sh_pre[lo]), q, sh_w[r16], f);
+        } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) f[e] = 0.0f;
-            }
-            f32x4 o;
-            if constexpr (PREC == HP_BF16) o = decode_bf16(mlp, f);
-            else o = decode_f32(mlp, f);
-            // the four outputs of a sample sit in its q = 0 lane; each lane of
-            // the sample takes one of them through the LDS, so the
-            // activations run on all lanes instead of a quarter of them
-            if (q == 0 && valid) sh_out[sidx] = make_float4(o[0], o[1], o[2], o[3]);
-            wave_lds_sync();
-            if (valid) {
-                float *out = reinterpret_cast<float *>(&sh_out[sidx]) + q;
-                const float x = *out;
-                *out = q < 3 ? sigmoid_f(x) : softplus_f(x);
-            }
+            for (int e = 0; e < 8; ++e) f[e] = 0.0f;
         }
+        activate(decode(f), sidx, valid);
     }
-    __syncthreads();
+    wave_lds_sync();
     if (l < nr) {
         const int64_t ray = ray0 + l;
         const int base = sh_pre[l];
@@ -172,6 +180,26 @@ __device__ __forceinline__ void render_chunk(const RenderArgs &a, int64_t ray0, 
     }
 }
 
+// One chunk with the decoder weights in the wave's registers: loaded here
+// unless `loaded` says an earlier chunk left them there (BF16).
+template <int PREC, int RPW, typename Mlp>
+__device__ __forceinline__ void render_chunk(const RenderArgs &a, int64_t ray0, Mlp &mlp,
+                                             bool &loaded, float4 *sh_out, int *sh_pre,
+                                             float4 *sh_w)
+{
+    const ChunkCounts c = chunk_prefix<RPW>(a, ray0, sh_pre);
+    if (c.total > 0 && (PREC != HP_BF16 || !loaded)) {
+        const MlpWeights wts{a.W1, a.b1, a.W2, a.b2, a.W3, a.b3};
+        if constexpr (PREC == HP_BF16) load_mlp_bf16(wts, mlp);
+        else load_mlp_f32(wts, mlp);
+        loaded = true;
+    }
+    chunk_body<RPW>(a, ray0, c, [&](const float *f) -> f32x4 {
+        if constexpr (PREC == HP_BF16) return decode_bf16(mlp, f);
+        else return decode_f32(mlp, f);
+    }, sh_out, sh_pre, sh_w);
+}
+
 // Render grid.  By default one workgroup (one wave) per chunk, so the
 // hardware dispatcher balances chunks with many samples against empty ones.
 // The persistent form (render_blocks = G) has workgroup b take chunks b,
@@ -194,7 +222,7 @@ __device__ __forceinline__ void render_body(const RenderArgs &a)
     } else {
         for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
             render_chunk<PREC, RPW>(a, ch * RPW, mlp, loaded, sh_out, sh_pre, sh_w);
-            __syncthreads();  // this chunk's compositing read sh_pre / sh_out
+            wave_lds_sync();  // this chunk's compositing read sh_pre / sh_out
         }
     }
 }
@@ -214,6 +242,44 @@ k_render_fp32(RenderArgs a)
     render_body<HP_FP32, RPW, PERSIST>(a);
 }
 
+// BF16 with the decoder weights in the LDS: a workgroup of WAVES waves takes
+// WAVES consecutive chunks, one per wave, and packs the weights once for all
+// of them (only if one of its chunks has samples).  Without the weights in
+// registers a wave needs about half as many, so more waves share a SIMD and
+// hide the latency of the feature gathers.
+constexpr int SHARED_WAVES = 8;
+// its chunks' sample outputs must fit beside the weights: three workgroups
+// per CU (24 waves) at 16 rays x 16 samples per chunk
+constexpr size_t SHARED_DYN_MAX = 32768;
+
+template <int RPW>
+__global__ void __launch_bounds__(WAVE *SHARED_WAVES) k_render_bf16_shared(RenderArgs a)
+{
+    extern __shared__ float4 sh_dyn[];  // [SHARED_WAVES][RPW * S] (rgb, sigma) per sample
+    __shared__ MlpBf16Shared mw;
+    __shared__ int sh_pre[SHARED_WAVES][RPW + 1];
+    __shared__ float4 sh_w[SHARED_WAVES][16];
+    __shared__ int busy;
+    const int w = threadIdx.x / WAVE;
+    const int64_t n_chunks = (a.n_rays + RPW - 1) / RPW;
+    const int64_t chunk = (int64_t)blockIdx.x * SHARED_WAVES + w;
+    const bool live = chunk < n_chunks;
+    if (threadIdx.x == 0) busy = 0;
+    __syncthreads();
+    ChunkCounts c{0, 0, 0};
+    if (live) c = chunk_prefix<RPW>(a, chunk * RPW, sh_pre[w]);
+    if (lane_id() == 0 && c.total > 0) busy = 1;
+    __syncthreads();
+    if (busy) {
+        const MlpWeights wts{a.W1, a.b1, a.W2, a.b2, a.W3, a.b3};
+        store_mlp_bf16_shared(wts, mw, w, SHARED_WAVES);
+    }
+    __syncthreads();
+    if (!live) return;
+    chunk_body<RPW>(a, chunk * RPW, c, [&](const float *f) -> f32x4 { return decode_bf16(mw, f); },
+                    sh_dyn + (size_t)w * RPW * a.S, sh_pre[w], sh_w[w]);
+}
+
 template <int RPW>
 static void launch_render_rpw(const RenderArgs &a, int precision, int64_t blocks, bool persist,
                               hipStream_t s)
@@ -221,8 +287,15 @@ static void launch_render_rpw(const RenderArgs &a, int precision, int64_t blocks
     const size_t shmem = (size_t)RPW * a.S * sizeof(float4);
     const dim3 grid((unsigned)blocks), block(WAVE);
     if (precision == HP_BF16) {
-        if (persist) k_render_bf16<RPW, true><<<grid, block, shmem, s>>>(a);
-        else k_render_bf16<RPW, false><<<grid, block, shmem, s>>>(a);
+        if (persist) {
+            k_render_bf16<RPW, true><<<grid, block, shmem, s>>>(a);
+        } else if (shmem * SHARED_WAVES <= SHARED_DYN_MAX) {
+            const int64_t chunks = (a.n_rays + RPW - 1) / RPW;
+            const unsigned g = (unsigned)((chunks + SHARED_WAVES - 1) / SHARED_WAVES);
+            k_render_bf16_shared<RPW><<<g, WAVE * SHARED_WAVES, shmem * SHARED_WAVES, s>>>(a);
+        } else {
+            k_render_bf16<RPW, false><<<grid, block, shmem, s>>>(a);
+        }
     } else {
         if (persist) k_render_fp32<RPW, true><<<grid, block, shmem, s>>>(a);
         else k_render_fp32<RPW, false><<<grid, block, shmem, s>>>(a);
@@ -231,7 +304,7 @@ static void launch_render_rpw(const RenderArgs &a, int precision, int64_t blocks
 
 hipError_t launch_render(const RenderArgs &a, int precision, hipStream_t s)
 {
-    const int rpw = a.rpw == 16 || a.rpw == 64 ? a.rpw : 32;
+    const int rpw = a.rpw == 32 || a.rpw == 64 ? a.rpw : 16;
     const int64_t chunks = (a.n_rays + rpw - 1) / rpw;
     if (chunks == 0) return hipSuccess;
     const bool persist = a.blocks > 0 && a.blocks < chunks;
