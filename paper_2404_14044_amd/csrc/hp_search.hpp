@@ -313,8 +313,14 @@ __device__ __forceinline__ float radius_for_depth(const SearchCtx &c, float kapp
 // view-wide bound.  If every such cell is empty, no point is near the ray.
 __device__ __forceinline__ int ray_view(const SearchCtx &c, int64_t ray)
 {
+    // the views' first rays are uniform loads, independent of each other (a
+    // walk along the list would wait for each in turn)
     int vi = 0;
-    while (vi + 1 < c.n_views && c.views[vi + 1].ray_base <= ray) ++vi;
+#pragma unroll
+    for (int i = 1; i < HP_MAX_VIEWS; ++i) {
+        if (i >= c.n_views) break;
+        vi += c.views[i].ray_base <= ray ? 1 : 0;
+    }
     return vi;
 }
 
@@ -639,7 +645,9 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
         const int key = bucket_of(Vg, c.layout, bx, by);
         st = c.offsets[key];
         cnt = c.offsets[key + 1] - st;
-        return cnt > 0 && c.bucket_z[key] <= zmax;
+        // the first depth is loaded with the offsets, not after them
+        const float z0 = c.bucket_z[key];
+        return cnt > 0 && z0 <= zmax;
     };
     auto append = [&](bool ok, int st, int cnt, float zmax) {
         const uint64_t m = ballot(ok);
