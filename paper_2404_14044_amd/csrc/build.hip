@@ -299,9 +299,25 @@ __device__ __forceinline__ uint64_t sort_bucket_to_slots(const uint64_t *__restr
 #pragma unroll
     for (int i = 0; i < N; ++i) k[i] = (i < cnt) ? skey[start + i] : ~0ull;
     sort_net<N>(k);
+    // all points gathered before any is stored: the stores may alias the
+    // gathered rows as far as the compiler knows, so put one by one each
+    // load would wait for the previous store
+    // (slots past the bucket's end gather its first point, unused; a plain
+    // vector type, which the compiler keeps in registers, where an array of
+    // float4 went to scratch memory)
+    typedef float fx4 __attribute__((ext_vector_type(4)));
+    const fx4 *src = reinterpret_cast<const fx4 *>(pc);
+    fx4 *dst = reinterpret_cast<fx4 *>(so.pts);
+    fx4 v[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i)
-        if (i < cnt) put_slot(so, pc, start + i, k[i]);
+    for (int i = 0; i < N; ++i) v[i] = src[(int32_t)(uint32_t)(i < cnt ? k[i] : k[0])];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        if (i < cnt) {
+            dst[start + i] = v[i];
+            so.perm[start + i] = (int32_t)(uint32_t)k[i];
+        }
+    }
     return k[0];
 }
 
@@ -447,7 +463,7 @@ __global__ void __launch_bounds__(SB_T) k_scatter_sb(const int2 *__restrict__ kz
 // (larger ones are listed for k_sort_listed) and its depth noted.
 constexpr int FIN_T = 512;  // threads of a superbucket's workgroup
 
-__global__ void __launch_bounds__(FIN_T) k_finalize_sb(const int4 *__restrict__ rec,
+__global__ void __launch_bounds__(FIN_T) __attribute__((amdgpu_waves_per_eu(4, 8))) k_finalize_sb(const int4 *__restrict__ rec,
                                                       const int32_t *__restrict__ sb_off,
                                                       int64_t n_buckets,
                                                       int32_t *__restrict__ offsets,
