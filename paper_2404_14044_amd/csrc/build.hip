@@ -359,12 +359,26 @@ __global__ void __launch_bounds__(SB_T) k_project_sb(const float *__restrict__ x
     for (int j = threadIdx.x; j < nsb; j += SB_T) hist[j] = 0;
     __syncthreads();
     const int64_t i0 = (int64_t)blockIdx.x * SB_T * SB_PER + threadIdx.x;
+    // all of the thread's points loaded first, so that the loads are in
+    // flight together (in one loop with the stores and the exit test below
+    // they went one at a time)
+    float px[SB_PER], py[SB_PER], pz[SB_PER];
+#pragma unroll
+    for (int j = 0; j < SB_PER; ++j) {
+        const int64_t i = i0 + (int64_t)j * SB_T;
+        px[j] = py[j] = pz[j] = 0.0f;
+        if (i < n) {
+            px[j] = xyz[3 * i];
+            py[j] = xyz[3 * i + 1];
+            pz[j] = xyz[3 * i + 2];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < SB_PER; ++j) {
         const int64_t i = i0 + (int64_t)j * SB_T;
         if (i >= n) break;
         float x, y, z;
-        to_camera(V, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], x, y, z);
+        to_camera(V, px[j], py[j], pz[j], x, y, z);
         pcam[(int64_t)vi * n + i] = make_float4(x, y, z, __int_as_float((int)i));
         int32_t key = -1;
         if (z > 0.0f && __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z)) {
@@ -437,12 +451,15 @@ __global__ void __launch_bounds__(SB_T) k_scatter_sb(const int2 *__restrict__ kz
     const int64_t i0 = (int64_t)blockIdx.x * SB_T * SB_PER + threadIdx.x;
     int2 e[SB_PER];
     int r[SB_PER];
+    // loads first, then the LDS atomics (interleaved, each load waited)
 #pragma unroll
     for (int j = 0; j < SB_PER; ++j) {
         const int64_t i = i0 + (int64_t)j * SB_T;
         e[j] = i < n ? kz[(int64_t)vi * n + i] : make_int2(-1, 0);
-        r[j] = e[j].x >= 0 ? atomicAdd(&hist[(e[j].x >> SB_SHIFT) - sb_lo], 1) : 0;
     }
+#pragma unroll
+    for (int j = 0; j < SB_PER; ++j)
+        r[j] = e[j].x >= 0 ? atomicAdd(&hist[(e[j].x >> SB_SHIFT) - sb_lo], 1) : 0;
     __syncthreads();
     for (int j = threadIdx.x; j < nsb; j += SB_T) {
         const int c = hist[j];
@@ -481,7 +498,18 @@ __global__ void __launch_bounds__(FIN_T) __attribute__((amdgpu_waves_per_eu(4, 8
     const int r0 = sb_off[sb], r1 = sb_off[sb + 1];
     for (int k = threadIdx.x; k < SB; k += FIN_T) cnt[k] = 0;
     __syncthreads();
-    for (int i = r0 + threadIdx.x; i < r1; i += FIN_T) atomicAdd(&cnt[rec[i].x - (int)key0], 1);
+    // records four at a time, their loads in flight together (the order in
+    // which a bucket's records arrive does not matter: each bucket is sorted
+    // by (z, index) below)
+    constexpr int RB = 4;
+    for (int i0 = r0 + threadIdx.x; i0 < r1; i0 += RB * FIN_T) {
+        int x[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) x[j] = i0 + j * FIN_T < r1 ? rec[i0 + j * FIN_T].x : -1;
+#pragma unroll
+        for (int j = 0; j < RB; ++j)
+            if (x[j] >= 0) atomicAdd(&cnt[x[j] - (int)key0], 1);
+    }
     __syncthreads();
     // exclusive scan over the SB counts, SB / FIN_T consecutive ones per thread
     constexpr int PER = SB / FIN_T;
@@ -506,10 +534,17 @@ __global__ void __launch_bounds__(FIN_T) __attribute__((amdgpu_waves_per_eu(4, 8
         run += c[q];
     }
     __syncthreads();
-    for (int i = r0 + threadIdx.x; i < r1; i += FIN_T) {
-        const int4 e = rec[i];
-        const int slot = atomicAdd(&cur[e.x - (int)key0], 1);
-        skey[slot] = ((uint64_t)(uint32_t)e.y << 32) | (uint32_t)e.z;
+    for (int i0 = r0 + threadIdx.x; i0 < r1; i0 += RB * FIN_T) {
+        int4 e[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) e[j] = i0 + j * FIN_T < r1 ? rec[i0 + j * FIN_T] : make_int4(-1, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            if (e[j].x >= 0) {
+                const int slot = atomicAdd(&cur[e[j].x - (int)key0], 1);
+                skey[slot] = ((uint64_t)(uint32_t)e[j].y << 32) | (uint32_t)e[j].z;
+            }
+        }
     }
     __syncthreads();  // (the placed keys are read back below by other threads)
     for (int k = threadIdx.x; k < nkeys; k += FIN_T) {
