@@ -271,9 +271,26 @@ __device__ __forceinline__ float group_cells_zmin(const SearchCtx &c, const View
     const int cx0 = max(gx - h, 0) >> CELL_SHIFT, cx1 = min(gx + h, V.Wg - 1) >> CELL_SHIFT;
     const int cy0 = max(gy - h, 0) >> CELL_SHIFT, cy1 = min(gy + h, V.Hg - 1) >> CELL_SHIFT;
     float z = __builtin_inff();
-    for (int cy = cy0; cy <= cy1; ++cy)
-        for (int cx = cx0 + sub; cx <= cx1; cx += RS_LANES)
-            z = __builtin_fminf(z, __uint_as_float(c.cell_zmin[V.cell_base + cy * V.ncx + cx]));
+    // cells in row-major order, cell sub, sub + RS_LANES, ... of the block to
+    // this lane, four loads in flight at a time (a load per step of a nested
+    // loop waited for each in turn); the minimum does not depend on the order
+    const int nx = cx1 - cx0 + 1, ny = cy1 - cy0 + 1;
+    const int ncell = (nx > 0 && ny > 0) ? nx * ny : 0;  // (nx >= 1 below)
+    int cx = cx0 + sub, cy = cy0;
+    if (ncell > 0)
+        while (cx > cx1 && cy <= cy1) cx -= nx, ++cy;
+    for (int ci = sub; ci < ncell; ci += 4 * RS_LANES) {
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = ci + j * RS_LANES < ncell ? __uint_as_float(c.cell_zmin[V.cell_base + cy * V.ncx + cx])
+                                             : __builtin_inff();
+            cx += RS_LANES;
+            while (cx > cx1 && cy <= cy1) cx -= nx, ++cy;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) z = __builtin_fminf(z, v[j]);
+    }
     static_assert(RS_LANES == 4 || RS_LANES == 8, "groups of four or eight lanes");
     z = __builtin_fminf(z, __uint_as_float(xor_lane_u32<1>(__float_as_uint(z))));
     z = __builtin_fminf(z, __uint_as_float(xor_lane_u32<2>(__float_as_uint(z))));
