@@ -330,15 +330,15 @@ __device__ __forceinline__ float radius_for_depth(const SearchCtx &c, float kapp
 // view-wide bound.  If every such cell is empty, no point is near the ray.
 __device__ __forceinline__ int ray_view(const SearchCtx &c, int64_t ray)
 {
-    // the views' first rays are uniform loads, independent of each other (a
-    // walk along the list would wait for each in turn)
-    int vi = 0;
-#pragma unroll
-    for (int i = 1; i < HP_MAX_VIEWS; ++i) {
-        if (i >= c.n_views) break;
-        vi += c.views[i].ray_base <= ray ? 1 : 0;
+    // bisection over the views' first rays (a walk along the list waits for
+    // each load in turn): views[lo].ray_base <= ray < views[hi].ray_base
+    int lo = 0, hi = c.n_views;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (c.views[mid].ray_base <= ray) lo = mid;
+        else hi = mid;
     }
-    return vi;
+    return lo;
 }
 
 // Window half-width of the first depth-cell round: the view-wide bound.
