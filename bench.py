@@ -52,6 +52,7 @@ MLP_FLOP_PER_SAMPLE = 2 * (32 * 64 + 64 * 64 + 64 * 4)   # 12,800
 CHIP_CUS, CHIP_GHZ = 256, 2.4
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "forward_path_objects_1m.md")
+RENDER_KERNEL = "k_render_bf16_shared<16>"  # the default BF16 render launch
 COUNTER_SOURCES = ("paper_2404_14044_amd/csrc", "include")
 
 
@@ -225,7 +226,7 @@ def main():
                       "algorithmic_bytes": b_bytes, "achieved": b_bytes / (build_ms * 1e-3) / 1e9,
                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": b_bytes / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
-            "render_bf16": {"kernel": "k_render_bf16", "bound": "hbm",
+            "render_bf16": {"kernel": RENDER_KERNEL, "bound": "hbm",
                             "algorithmic_bytes": r_bytes,
                             "achieved": r_bytes / (render_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                             "unit": "GB/s", "frac": r_bytes / (render_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
@@ -247,9 +248,15 @@ def main():
                 "valu_insts": ks["SQ_INSTS_VALU"], "salu_insts": ks.get("SQ_INSTS_SALU"),
                 "valu_issue_frac": ks["SQ_INSTS_VALU"] / slots,
                 "valu_insts_per_ray_with_neighbours": ks["SQ_INSTS_VALU"] / max(hit_rays, 1)}
-        kr = counters["kernels"].get("k_render_bf16<32,false>")
+        kr = counters["kernels"].get(RENDER_KERNEL)
         if kr and "SQ_INSTS_MFMA" in kr:
-            result["rooflines_other"]["render_bf16"]["mfma_insts"] = kr["SQ_INSTS_MFMA"]
+            rr = result["rooflines_other"]["render_bf16"]
+            rr["mfma_insts"] = kr["SQ_INSTS_MFMA"]
+            # a 16x16x32 BF16 product is 16 cycles of one SIMD's matrix core
+            simd_cycles = render_ms * 1e-3 * CHIP_GHZ * 1e9 * CHIP_CUS * 4
+            rr["mfma_busy_frac"] = kr["SQ_INSTS_MFMA"] * 16 / simd_cycles
+            rr["valu_issue_frac"] = kr["SQ_INSTS_VALU"] / (simd_cycles / 4)
+            rr["vmem_read_insts"] = kr.get("SQ_INSTS_VMEM_RD")
         result["roofline"]["counters_from"] = os.path.relpath(COUNTERS_FILE, ROOT)
     # achievable bandwidth on this machine: a plain 1 GiB device-to-device copy
     copy_gbs = copy_bandwidth_gbs(dev)
