@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
 
     using Mlp = typename std::conditional<PREC == HP_BF16, MlpBf16, MlpF32>::type;
     auto load_mlp = [&](Mlp &m) {
-        if constexpr (PREC == HP_BF16) load_mlp_bf16(A.w, m);
+        if constexpr (PREC == HP_BF16) load_mlp_bf16_image(*A.wimg, m);
         else load_mlp_f32(A.w, m);
     };
     // a value as the decoder consumes it (bfloat16-rounded with the BF16 decoder)
@@ -639,12 +639,28 @@ __global__ void __launch_bounds__(RED_P * RED_G) k_reduce_partials(const float *
     dst[j] += t;
 }
 
-// the slices, then one 256-byte line for the work counter
-size_t backward_partial_bytes() { return (size_t)BWD_MAX_BLOCKS * SSTRIDE * sizeof(float) + 256; }
+// the slices, one 256-byte line for the work counter, then the packed BF16
+// decoder
+constexpr size_t WIMG_BYTES = (sizeof(MlpBf16Shared) + 255) / 256 * 256;
+
+size_t backward_partial_bytes()
+{
+    return (size_t)BWD_MAX_BLOCKS * SSTRIDE * sizeof(float) + 256 + WIMG_BYTES;
+}
 
 static int32_t *queue_of(float *partial)
 {
     return reinterpret_cast<int32_t *>(partial + (size_t)BWD_MAX_BLOCKS * SSTRIDE);
+}
+
+static MlpBf16Shared *wimg_of(float *partial)
+{
+    return reinterpret_cast<MlpBf16Shared *>(reinterpret_cast<char *>(queue_of(partial)) + 256);
+}
+
+__global__ void __launch_bounds__(256) k_pack_mlp_bf16(MlpWeights w, MlpBf16Shared *img)
+{
+    store_mlp_bf16_shared(w, *img, threadIdx.x / WAVE, blockDim.x / WAVE);
 }
 
 int backward_slices()
@@ -674,8 +690,10 @@ hipError_t backward_accumulate(const BwdArgs &args, int precision, hipStream_t s
     if (args.n_rays == 0) return hipSuccess;
     BwdArgs A = args;
     A.queue = queue_of(A.partial);
+    A.wimg = wimg_of(A.partial);
     // (a fill kernel, not a memset: callers may capture this in a graph)
     k_zero_f32<<<1, 64, 0, s>>>(reinterpret_cast<float *>(A.queue), 1);
+    if (precision == HP_BF16) k_pack_mlp_bf16<<<1, 256, 0, s>>>(A.w, wimg_of(A.partial));
     const int64_t chunks = (A.n_rays + A.rpw - 1) / A.rpw;
     int64_t nblk = (chunks + BWD_WAVES - 1) / BWD_WAVES;
     const int64_t nslice = backward_slices();

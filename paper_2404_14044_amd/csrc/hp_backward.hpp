@@ -29,11 +29,14 @@ struct BwdArgs {
     float *grad_feat;
     float *partial;  // per-workgroup decoder-gradient slices
     int32_t *queue;  // work counter of one accumulate launch (zeroed before it)
+    const MlpBf16Shared *wimg;  // the BF16 decoder packed per lane (after the counter)
 };
 
 // Decoder-gradient slices: one per workgroup of the backward grid, which is
 // at most backward_slices() workgroups for any number of rays, followed by
-// the work counter of the accumulate launches.
+// the work counter of the accumulate launches and the BF16 decoder's
+// fragments packed per lane (read by every tile's decode instead of loading
+// and converting the FP32 weights each time).
 size_t backward_partial_bytes();
 int backward_slices();
 int backward_rays_per_wave(int S);

@@ -194,6 +194,26 @@ __device__ __forceinline__ void store_mlp_bf16_shared(const MlpWeights &a, MlpBf
     }
 }
 
+// The register copy from a packed image (global or LDS memory): sixteen-byte
+// reads straight into the operand registers, no conversion.
+__device__ __forceinline__ void load_mlp_bf16_image(const MlpBf16Shared &img, MlpBf16 &m)
+{
+    const int l = lane_id(), q = l >> 4;
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        m.w1[ob] = img.w1[ob][l];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) m.w2[ob][kb] = img.w2[ob][kb][l];
+        const float4 b1 = img.b1[4 * ob + q], b2 = img.b2[4 * ob + q];
+        m.b1[ob][0] = b1.x, m.b1[ob][1] = b1.y, m.b1[ob][2] = b1.z, m.b1[ob][3] = b1.w;
+        m.b2[ob][0] = b2.x, m.b2[ob][1] = b2.y, m.b2[ob][2] = b2.z, m.b2[ob][3] = b2.w;
+    }
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) m.w3[kb] = img.w3[kb][l];
+    const float4 b3 = img.b3[q];
+    m.b3[0] = b3.x, m.b3[1] = b3.y, m.b3[2] = b3.z, m.b3[3] = b3.w;
+}
+
 template <typename M>
 __device__ __forceinline__ f32x4 decode_bf16(const M &m, const float *f, f32x4 *keep1 = nullptr,
                                              f32x4 *keep2 = nullptr)
