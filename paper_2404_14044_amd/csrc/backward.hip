@@ -50,6 +50,7 @@ struct BwdWave {
     int32_t pre[WAVE + 1];          // sample prefix over the chunk's rays
     int64_t row[16];                // tile: sample row (ray * S + s), -1 = padding
     float inv[16];                  // tile: 1 / sum of the inverse-distance weights
+    float4 w[16];                   // tile: four inverse-distance weights per sample
     float F[16][HP_FEAT_DIM];       // tile: aggregated features [sample][feature]
     float H1T[HP_HIDDEN][16];       // tile: layer-1 activations, then their gradients
     float H2T[HP_HIDDEN][16];       // tile: layer-2 activations, then their gradients
@@ -59,9 +60,10 @@ struct BwdWave {
 static_assert(2 * 16 * HP_MAX_K <= HP_HIDDEN * 16, "neighbour staging exceeds its LDS area");
 
 // Aggregated feature slice (features 8 q .. 8 q + 7) of sample row `row`;
-// the same arithmetic as the render (neighbours four at a time, summed in
+// the same arithmetic as the render (neighbours four at a time, the
+// sample's four lanes sharing the weights through `sw`, summed in
 // order).  Returns 1 / sum of the weights.
-__device__ __forceinline__ float idw_slice_bwd(const BwdArgs &A, int64_t row, int q, float *f)
+__device__ __forceinline__ float idw_slice_bwd(const BwdArgs &A, int64_t row, int q, float4 &sw, float *f)
 {
 #pragma unroll
     for (int e = 0; e < 8; ++e) f[e] = 0.0f;
@@ -74,8 +76,15 @@ __device__ __forceinline__ float idw_slice_bwd(const BwdArgs &A, int64_t row, in
         float d[4], w[4];
         float4 x0[4], x1[4];
         load_nbr4(ki, kd, k0, A.K, vec, idx, d);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) w[j] = 1.0f / (d[j] > A.eps_idw ? d[j] : A.eps_idw);
+        {
+            // the sample's four lanes share the four weights, one division each
+            const float dq = q == 0 ? d[0] : q == 1 ? d[1] : q == 2 ? d[2] : d[3];
+            wave_lds_sync();  // the previous four weights are read
+            reinterpret_cast<float *>(&sw)[q] = 1.0f / (dq > A.eps_idw ? dq : A.eps_idw);
+            wave_lds_sync();
+            const float4 wv = sw;
+            w[0] = wv.x, w[1] = wv.y, w[2] = wv.z, w[3] = wv.w;
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (idx[j] >= 0) {
@@ -196,26 +205,23 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
         wave_lds_sync();
         if (total == 0) continue;
 
-        // pass A: raw decoder outputs of every sample (the BF16 weights stay
-        // in registers over the chunk; the larger FP32 set is reloaded per tile)
+        // pass A: raw decoder outputs of every sample (the weights are
+        // reloaded per tile after its aggregation, cache hits, so that they
+        // hold no registers while the feature rows are in flight)
         {
             Mlp mlp;
-            if constexpr (PREC == HP_BF16) load_mlp(mlp);
             for (int s0 = 0; s0 < total; s0 += 16) {
                 const int sidx = s0 + r16;
                 float f[8];
-                if (sidx < total) idw_slice_bwd(A, sample_row(sh, A, ray0, nr, sidx), q, f);
+                if (sidx < total) idw_slice_bwd(A, sample_row(sh, A, ray0, nr, sidx), q, sh.w[r16], f);
                 else
 #pragma unroll
                     for (int e = 0; e < 8; ++e) f[e] = 0.0f;
                 f32x4 o;
-                if constexpr (PREC == HP_BF16) {
-                    o = decode_bf16(mlp, f);
-                } else {
-                    __asm__ volatile("" ::: "memory");
-                    load_mlp(mlp);
-                    o = decode_f32(mlp, f);
-                }
+                __asm__ volatile("" ::: "memory");
+                load_mlp(mlp);
+                if constexpr (PREC == HP_BF16) o = decode_bf16(mlp, f);
+                else o = decode_f32(mlp, f);
                 if (q == 0 && sidx < total) sh.o[sidx] = make_float4(o[0], o[1], o[2], o[3]);
             }
         }
@@ -280,7 +286,7 @@ __global__ void __launch_bounds__(WAVE *BWD_WAVES) k_render_backward(BwdArgs A)
                 float inv = 0.0f;
                 if (valid) {
                     row = sample_row(sh, A, ray0, nr, sidx);
-                    inv = idw_slice_bwd(A, row, q, f);
+                    inv = idw_slice_bwd(A, row, q, sh.w[r16], f);
                 } else {
 #pragma unroll
                     for (int e = 0; e < 8; ++e) f[e] = 0.0f;
