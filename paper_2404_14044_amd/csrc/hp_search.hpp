@@ -685,7 +685,7 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
     // depth exceeds the depth bound at D (the bound only falls with D).
     // Surviving cells are listed (up to 64 at a time, in the LDS the walk
     // uses later) with the prefix of their window-bucket counts; lanes then
-    // probe two chunks of those buckets per step so their loads overlap.
+    // probe four chunks of those buckets per step so their loads overlap.
     // Small windows (most rays of object-scale scenes) skip the cell pass.
     const int Wd = 2 * h + 1;
     if (Wd * Wd <= 4 * WAVE) {
@@ -755,17 +755,16 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
             dxi = e.x + (li - ry * e.z) - gx;
             dyi = e.y + ry - gy;
         };
-        for (int b0 = 0; b0 < total; b0 += 2 * WAVE) {
-            bool vA, vB;
-            int dxA, dyA, dxB, dyB;
-            locate(b0 + l, vA, dxA, dyA);
-            locate(b0 + WAVE + l, vB, dxB, dyB);
-            int stA, cntA, stB, cntB;
-            float zA, zB;
-            const bool okA = probe(vA, dxA, dyA, stA, cntA, zA);
-            const bool okB = probe(vB, dxB, dyB, stB, cntB, zB);
-            append(okA, stA, cntA, zA);
-            append(okB, stB, cntB, zB);
+        for (int b0 = 0; b0 < total; b0 += 4 * WAVE) {
+            bool v[4], ok[4];
+            int dx[4], dy[4], st[4], cnt[4];
+            float zm[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) locate(b0 + u * WAVE + l, v[u], dx[u], dy[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) ok[u] = probe(v[u], dx[u], dy[u], st[u], cnt[u], zm[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) append(ok[u], st[u], cnt[u], zm[u]);
         }
     }
     if (nbl > 0) sweep_points(nbl);
