@@ -684,8 +684,8 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
     // nearest window bucket is at distance D is skipped when its minimum
     // depth exceeds the depth bound at D (the bound only falls with D).
     // Surviving cells are listed (up to 64 at a time, in the LDS the walk
-    // uses later) with the prefix of their window-bucket counts; lanes then
-    // probe four chunks of those buckets per step so their loads overlap.
+    // uses later) with the prefix of their window-bucket counts; each cell's
+    // buckets then go to one chunk of lanes, four cells per step.
     // Small windows (most rays of object-scale scenes) skip the cell pass.
     const int Wd = 2 * h + 1;
     if (Wd * Wd <= 4 * WAVE) {
@@ -739,28 +739,28 @@ __device__ __forceinline__ void search_neighbours(const SearchCtx &c, const RayG
         if (keep) cl[rank_below(km)] = make_int4(bx0, by0, bw, inc - nk);
         lds_sync();
         const int ncl = popc64(km);
-        auto locate = [&](int b, bool &valid, int &dxi, int &dyi) {
-            valid = b < total;
-            dxi = dyi = 0;
-            if (!valid) return;
-            int lo = 0, hi = ncl;  // last listed cell with prefix <= b
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (cl[mid].w <= b) lo = mid;
-                else hi = mid;
-            }
-            const int4 e = cl[lo];
-            const int li = b - e.w;
-            const int ry = (int)(((float)li + 0.5f) * __builtin_amdgcn_rcpf((float)e.z));
-            dxi = e.x + (li - ry * e.z) - gx;
-            dyi = e.y + ry - gy;
-        };
-        for (int b0 = 0; b0 < total; b0 += 4 * WAVE) {
+        // one listed cell per chunk of lanes (a cell holds at most 64
+        // buckets), four cells per step so that their loads overlap; the
+        // order in which buckets are appended does not change the kept keys
+        for (int k0 = 0; k0 < ncl; k0 += 4) {
             bool v[4], ok[4];
             int dx[4], dy[4], st[4], cnt[4];
             float zm[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) locate(b0 + u * WAVE + l, v[u], dx[u], dy[u]);
+            for (int u = 0; u < 4; ++u) {
+                v[u] = false;
+                dx[u] = dy[u] = 0;
+                if (k0 + u < ncl) {
+                    const int4 e = cl[k0 + u];
+                    const int nin = (k0 + u + 1 < ncl ? cl[k0 + u + 1].w : total) - e.w;
+                    if (l < nin) {
+                        const int ry = (int)(((float)l + 0.5f) * __builtin_amdgcn_rcpf((float)e.z));
+                        dx[u] = e.x + (l - ry * e.z) - gx;
+                        dy[u] = e.y + ry - gy;
+                        v[u] = true;
+                    }
+                }
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) ok[u] = probe(v[u], dx[u], dy[u], st[u], cnt[u], zm[u]);
 #pragma unroll
