@@ -270,30 +270,76 @@ struct MlpF32 {
     float w2[4][16];   // [out block][step]
     float w3[16];
     float b1[4][4], b2[4][4], b3[4];
+
+    // steps 4 i .. 4 i + 3 of a layer's A operands, and the bias quarters
+    __device__ __forceinline__ f32x4 W1q(int ob, int i) const
+    {
+        return {w1[ob][4 * i], w1[ob][4 * i + 1], w1[ob][4 * i + 2], w1[ob][4 * i + 3]};
+    }
+    __device__ __forceinline__ f32x4 W2q(int ob, int i) const
+    {
+        return {w2[ob][4 * i], w2[ob][4 * i + 1], w2[ob][4 * i + 2], w2[ob][4 * i + 3]};
+    }
+    __device__ __forceinline__ f32x4 W3q(int i) const
+    {
+        return {w3[4 * i], w3[4 * i + 1], w3[4 * i + 2], w3[4 * i + 3]};
+    }
+    __device__ __forceinline__ f32x4 B1(int ob) const { return {b1[ob][0], b1[ob][1], b1[ob][2], b1[ob][3]}; }
+    __device__ __forceinline__ f32x4 B2(int ob) const { return {b2[ob][0], b2[ob][1], b2[ob][2], b2[ob][3]}; }
+    __device__ __forceinline__ f32x4 B3() const { return {b3[0], b3[1], b3[2], b3[3]}; }
 };
+
+// The lane's FP32 A operands, four steps at a time (one function per piece,
+// shared by the register and the LDS copies).
+__device__ __forceinline__ float4 w1_quad_f32(const MlpWeights &a, int ob, int i, int l)
+{
+    const int r = l & 15, q = l >> 4;
+    const float *w = a.W1 + (16 * ob + r) * HP_FEAT_DIM + 8 * q + 4 * i;
+    return make_float4(w[0], w[1], w[2], w[3]);
+}
+
+__device__ __forceinline__ float4 w2_quad_f32(const MlpWeights &a, int ob, int i, int l)
+{
+    const int r = l & 15, q = l >> 4;
+    const float *w = a.W2 + (16 * ob + r) * HP_HIDDEN + 16 * i + 4 * q;
+    return make_float4(w[0], w[1], w[2], w[3]);
+}
+
+// (padding rows: see w3_fragment)
+__device__ __forceinline__ float4 w3_quad_f32(const MlpWeights &a, int i, int l)
+{
+    const int r = l & 15, q = l >> 4, r3 = r < 4 ? r : 3;
+    const float *w = a.W3 + r3 * HP_HIDDEN + 16 * i + 4 * q;
+    const float4 v = make_float4(w[0], w[1], w[2], w[3]);
+    return r < 4 ? v : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
 
 __device__ __forceinline__ void load_mlp_f32(const MlpWeights &a, MlpF32 &m)
 {
     const int l = lane_id();
-    const int r = l & 15, q = l >> 4;
+    const int q = l >> 4;
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) m.w1[ob][ks] = a.W1[(16 * ob + r) * HP_FEAT_DIM + 8 * q + ks];
+        for (int i = 0; i < 2; ++i) {
+            const float4 v = w1_quad_f32(a, ob, i, l);
+            m.w1[ob][4 * i] = v.x, m.w1[ob][4 * i + 1] = v.y, m.w1[ob][4 * i + 2] = v.z, m.w1[ob][4 * i + 3] = v.w;
+        }
 #pragma unroll
-        for (int st = 0; st < 16; ++st)
-            m.w2[ob][st] = a.W2[(16 * ob + r) * HP_HIDDEN + 16 * (st >> 2) + 4 * q + (st & 3)];
+        for (int i = 0; i < 4; ++i) {
+            const float4 v = w2_quad_f32(a, ob, i, l);
+            m.w2[ob][4 * i] = v.x, m.w2[ob][4 * i + 1] = v.y, m.w2[ob][4 * i + 2] = v.z, m.w2[ob][4 * i + 3] = v.w;
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             m.b1[ob][e] = a.b1[16 * ob + 4 * q + e];
             m.b2[ob][e] = a.b2[16 * ob + 4 * q + e];
         }
     }
-    const int r3 = r < 4 ? r : 3;  // padding rows: see load_mlp_bf16
 #pragma unroll
-    for (int st = 0; st < 16; ++st) {
-        const float w = a.W3[r3 * HP_HIDDEN + 16 * (st >> 2) + 4 * q + (st & 3)];
-        m.w3[st] = r < 4 ? w : 0.0f;
+    for (int i = 0; i < 4; ++i) {
+        const float4 v = w3_quad_f32(a, i, l);
+        m.w3[4 * i] = v.x, m.w3[4 * i + 1] = v.y, m.w3[4 * i + 2] = v.z, m.w3[4 * i + 3] = v.w;
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -302,15 +348,51 @@ __device__ __forceinline__ void load_mlp_f32(const MlpWeights &a, MlpF32 &m)
     }
 }
 
-__device__ __forceinline__ f32x4 decode_f32(const MlpF32 &m, const float *f, f32x4 *keep1 = nullptr,
+// The FP32 weights in the LDS, shared by a workgroup's waves (as MlpBf16Shared).
+struct MlpF32Shared {
+    float4 w1[4][2][WAVE];
+    float4 w2[4][4][WAVE];
+    float4 w3[4][WAVE];
+    float4 b1[16], b2[16], b3[4];
+
+    __device__ __forceinline__ f32x4 W1q(int ob, int i) const { return as_f32x4(w1[ob][i][lane_id()]); }
+    __device__ __forceinline__ f32x4 W2q(int ob, int i) const { return as_f32x4(w2[ob][i][lane_id()]); }
+    __device__ __forceinline__ f32x4 W3q(int i) const { return as_f32x4(w3[i][lane_id()]); }
+    __device__ __forceinline__ f32x4 B1(int ob) const { return as_f32x4(b1[4 * ob + (lane_id() >> 4)]); }
+    __device__ __forceinline__ f32x4 B2(int ob) const { return as_f32x4(b2[4 * ob + (lane_id() >> 4)]); }
+    __device__ __forceinline__ f32x4 B3() const { return as_f32x4(b3[lane_id() >> 4]); }
+    static __device__ __forceinline__ f32x4 as_f32x4(const float4 &v) { return {v.x, v.y, v.z, v.w}; }
+};
+
+__device__ __forceinline__ void store_mlp_f32_shared(const MlpWeights &a, MlpF32Shared &m, int w, int nw)
+{
+    const int l = lane_id();
+    for (int p = w; p < 28; p += nw) {
+        if (p < 8) m.w1[p >> 1][p & 1][l] = w1_quad_f32(a, p >> 1, p & 1, l);
+        else if (p < 24) m.w2[(p - 8) >> 2][(p - 8) & 3][l] = w2_quad_f32(a, (p - 8) >> 2, (p - 8) & 3, l);
+        else m.w3[p - 24][l] = w3_quad_f32(a, p - 24, l);
+    }
+    if (w == 0) {
+        reinterpret_cast<float *>(m.b1)[l] = a.b1[l];
+        reinterpret_cast<float *>(m.b2)[l] = a.b2[l];
+        if (l < 16) reinterpret_cast<float *>(m.b3)[l] = l < 4 ? a.b3[l] : 0.0f;
+    }
+}
+
+template <typename M>
+__device__ __forceinline__ f32x4 decode_f32(const M &m, const float *f, f32x4 *keep1 = nullptr,
                                             f32x4 *keep2 = nullptr)
 {
     f32x4 h1[4];
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
-        f32x4 acc = {m.b1[ob][0], m.b1[ob][1], m.b1[ob][2], m.b1[ob][3]};
+        f32x4 acc = m.B1(ob);
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(m.w1[ob][ks], f[ks], acc, 0, 0, 0);
+        for (int i = 0; i < 2; ++i) {
+            const f32x4 w = m.W1q(ob, i);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w[e], f[4 * i + e], acc, 0, 0, 0);
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[e] = relu(acc[e]);
         h1[ob] = acc;
@@ -319,19 +401,25 @@ __device__ __forceinline__ f32x4 decode_f32(const MlpF32 &m, const float *f, f32
     f32x4 h2[4];
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
-        f32x4 acc = {m.b2[ob][0], m.b2[ob][1], m.b2[ob][2], m.b2[ob][3]};
+        f32x4 acc = m.B2(ob);
 #pragma unroll
-        for (int st = 0; st < 16; ++st)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(m.w2[ob][st], h1[st >> 2][st & 3], acc, 0, 0, 0);
+        for (int i = 0; i < 4; ++i) {
+            const f32x4 w = m.W2q(ob, i);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w[e], h1[i][e], acc, 0, 0, 0);
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[e] = relu(acc[e]);
         h2[ob] = acc;
         if (keep2) keep2[ob] = acc;
     }
-    f32x4 o = {m.b3[0], m.b3[1], m.b3[2], m.b3[3]};
+    f32x4 o = m.B3();
 #pragma unroll
-    for (int st = 0; st < 16; ++st)
-        o = __builtin_amdgcn_mfma_f32_16x16x4f32(m.w3[st], h2[st >> 2][st & 3], o, 0, 0, 0);
+    for (int i = 0; i < 4; ++i) {
+        const f32x4 w = m.W3q(i);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) o = __builtin_amdgcn_mfma_f32_16x16x4f32(w[e], h2[i][e], o, 0, 0, 0);
+    }
     return o;
 }
 

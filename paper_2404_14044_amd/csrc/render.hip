@@ -1,10 +1,10 @@
 // Decode and composite the samples (Sec. 3.4, Eq. 2).
 //
-// One wave per chunk of RPW consecutive rays (16 by default).  BF16: eight
-// waves per workgroup, one chunk each, with the decoder weights packed once
-// per workgroup into the LDS (k_render_bf16_shared); FP32, the persistent
-// grid and chunks too large for that: one wave per workgroup with the
-// weights in its registers (render_body).  The wave packs the chunk's
+// One wave per chunk of RPW consecutive rays (16 by default): eight waves
+// per workgroup, one chunk each, with the decoder weights packed once per
+// workgroup into the LDS (k_render_shared); the persistent grid and chunks
+// too large for that: one wave per workgroup with the weights in its
+// registers (render_body).  The wave packs the chunk's
 // samples densely into tiles of 16, and for each tile:
 //   1. aggregates the features of every sample's K neighbours with
 //      inverse-distance weights (FP32): lane l handles sample l % 16 and
@@ -242,21 +242,21 @@ k_render_fp32(RenderArgs a)
     render_body<HP_FP32, RPW, PERSIST>(a);
 }
 
-// BF16 with the decoder weights in the LDS: a workgroup of WAVES waves takes
-// WAVES consecutive chunks, one per wave, and packs the weights once for all
+// Decoder weights in the LDS: a workgroup of SHARED_WAVES waves takes as
+// many consecutive chunks, one per wave, and packs the weights once for all
 // of them (only if one of its chunks has samples).  Without the weights in
 // registers a wave needs about half as many, so more waves share a SIMD and
 // hide the latency of the feature gathers.
 constexpr int SHARED_WAVES = 8;
-// its chunks' sample outputs must fit beside the weights: three workgroups
-// per CU (24 waves) at 16 rays x 16 samples per chunk
+// its chunks' sample outputs must fit beside the weights: three (BF16) or two
+// (FP32) workgroups per CU at 16 rays x 16 samples per chunk
 constexpr size_t SHARED_DYN_MAX = 32768;
 
-template <int RPW>
-__global__ void __launch_bounds__(WAVE *SHARED_WAVES) k_render_bf16_shared(RenderArgs a)
+template <int PREC, int RPW>
+__global__ void __launch_bounds__(WAVE *SHARED_WAVES) k_render_shared(RenderArgs a)
 {
     extern __shared__ float4 sh_dyn[];  // [SHARED_WAVES][RPW * S] (rgb, sigma) per sample
-    __shared__ MlpBf16Shared mw;
+    __shared__ typename std::conditional<PREC == HP_BF16, MlpBf16Shared, MlpF32Shared>::type mw;
     __shared__ int sh_pre[SHARED_WAVES][RPW + 1];
     __shared__ float4 sh_w[SHARED_WAVES][16];
     __shared__ int busy;
@@ -272,12 +272,15 @@ __global__ void __launch_bounds__(WAVE *SHARED_WAVES) k_render_bf16_shared(Rende
     __syncthreads();
     if (busy) {
         const MlpWeights wts{a.W1, a.b1, a.W2, a.b2, a.W3, a.b3};
-        store_mlp_bf16_shared(wts, mw, w, SHARED_WAVES);
+        if constexpr (PREC == HP_BF16) store_mlp_bf16_shared(wts, mw, w, SHARED_WAVES);
+        else store_mlp_f32_shared(wts, mw, w, SHARED_WAVES);
     }
     __syncthreads();
     if (!live) return;
-    chunk_body<RPW>(a, chunk * RPW, c, [&](const float *f) -> f32x4 { return decode_bf16(mw, f); },
-                    sh_dyn + (size_t)w * RPW * a.S, sh_pre[w], sh_w[w]);
+    chunk_body<RPW>(a, chunk * RPW, c, [&](const float *f) -> f32x4 {
+        if constexpr (PREC == HP_BF16) return decode_bf16(mw, f);
+        else return decode_f32(mw, f);
+    }, sh_dyn + (size_t)w * RPW * a.S, sh_pre[w], sh_w[w]);
 }
 
 template <int RPW>
@@ -286,18 +289,17 @@ static void launch_render_rpw(const RenderArgs &a, int precision, int64_t blocks
 {
     const size_t shmem = (size_t)RPW * a.S * sizeof(float4);
     const dim3 grid((unsigned)blocks), block(WAVE);
+    const int64_t chunks = (a.n_rays + RPW - 1) / RPW;
+    const unsigned g = (unsigned)((chunks + SHARED_WAVES - 1) / SHARED_WAVES);
+    const bool shared = !persist && shmem * SHARED_WAVES <= SHARED_DYN_MAX;
+    const size_t shm = shmem * SHARED_WAVES;
     if (precision == HP_BF16) {
-        if (persist) {
-            k_render_bf16<RPW, true><<<grid, block, shmem, s>>>(a);
-        } else if (shmem * SHARED_WAVES <= SHARED_DYN_MAX) {
-            const int64_t chunks = (a.n_rays + RPW - 1) / RPW;
-            const unsigned g = (unsigned)((chunks + SHARED_WAVES - 1) / SHARED_WAVES);
-            k_render_bf16_shared<RPW><<<g, WAVE * SHARED_WAVES, shmem * SHARED_WAVES, s>>>(a);
-        } else {
-            k_render_bf16<RPW, false><<<grid, block, shmem, s>>>(a);
-        }
+        if (shared) k_render_shared<HP_BF16, RPW><<<g, WAVE * SHARED_WAVES, shm, s>>>(a);
+        else if (persist) k_render_bf16<RPW, true><<<grid, block, shmem, s>>>(a);
+        else k_render_bf16<RPW, false><<<grid, block, shmem, s>>>(a);
     } else {
-        if (persist) k_render_fp32<RPW, true><<<grid, block, shmem, s>>>(a);
+        if (shared) k_render_shared<HP_FP32, RPW><<<g, WAVE * SHARED_WAVES, shm, s>>>(a);
+        else if (persist) k_render_fp32<RPW, true><<<grid, block, shmem, s>>>(a);
         else k_render_fp32<RPW, false><<<grid, block, shmem, s>>>(a);
     }
 }
