@@ -52,7 +52,7 @@ MLP_FLOP_PER_SAMPLE = 2 * (32 * 64 + 64 * 64 + 64 * 4)   # 12,800
 CHIP_CUS, CHIP_GHZ = 256, 2.4
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "forward_path_objects_1m.md")
-RENDER_KERNEL = "k_render_bf16_shared<16>"  # the default BF16 render launch
+RENDER_KERNEL = "k_render_shared<1,16>"  # the default BF16 render launch (HP_BF16 = 1)
 COUNTER_SOURCES = ("paper_2404_14044_amd/csrc", "include")
 
 
