@@ -65,14 +65,15 @@ __device__ __forceinline__ void search_sample_body(const SearchCtx &c, const Sam
     });
 }
 
-// 6 waves per SIMD where the nearest-neighbour lists are short (85 VGPRs,
+// 6 waves per SIMD where the nearest-neighbour lists are short (80 VGPRs,
 // fewer spills than at 8; with the default grid of many more workgroups
 // than fit at once, 6 measured 3% faster than 8, and 7, 5 or 4 slower).
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_search_sample_k4(SearchCtx c, SampleOut o) { search_sample_body<4, false>(c, o); }
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_search_sample_k8(SearchCtx c, SampleOut o) { search_sample_body<8, false>(c, o); }
-__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4, 8)))
+// 16-entry lists: 5 waves per SIMD (room view 9% faster than 4, 3 slower)
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(5, 8)))
 k_search_sample_k16(SearchCtx c, SampleOut o) { search_sample_body<16, false>(c, o); }
 __global__ void __launch_bounds__(WAVE) k_search_sample_k32(SearchCtx c, SampleOut o)
 {
