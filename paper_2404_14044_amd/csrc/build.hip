@@ -299,7 +299,7 @@ __device__ __forceinline__ uint64_t sort_bucket_to_slots(const uint64_t *__restr
 #pragma unroll
     for (int i = 0; i < N; ++i) k[i] = (i < cnt) ? skey[start + i] : ~0ull;
     sort_net<N>(k);
-    // all points gathered before any is stored: the stores may alias the
+    // the points gathered before they are stored: the stores may alias the
     // gathered rows as far as the compiler knows, so put one by one each
     // load would wait for the previous store
     // (slots past the bucket's end gather its first point, unused; a plain
@@ -308,14 +308,20 @@ __device__ __forceinline__ uint64_t sort_bucket_to_slots(const uint64_t *__restr
     typedef float fx4 __attribute__((ext_vector_type(4)));
     const fx4 *src = reinterpret_cast<const fx4 *>(pc);
     fx4 *dst = reinterpret_cast<fx4 *>(so.pts);
-    fx4 v[N];
+    // (eight at a time: 32 registers, so that three 512-thread workgroups
+    // share a CU and one round of them covers the object view's superbuckets)
+    constexpr int G = N < 8 ? N : 8;
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = src[(int32_t)(uint32_t)(i < cnt ? k[i] : k[0])];
+    for (int i0 = 0; i0 < N; i0 += G) {
+        fx4 v[G];
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-        if (i < cnt) {
-            dst[start + i] = v[i];
-            so.perm[start + i] = (int32_t)(uint32_t)k[i];
+        for (int j = 0; j < G; ++j) v[j] = src[(int32_t)(uint32_t)(i0 + j < cnt ? k[i0 + j] : k[0])];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            if (i0 + j < cnt) {
+                dst[start + i0 + j] = v[j];
+                so.perm[start + i0 + j] = (int32_t)(uint32_t)k[i0 + j];
+            }
         }
     }
     return k[0];
@@ -480,7 +486,7 @@ __global__ void __launch_bounds__(SB_T) k_scatter_sb(const int2 *__restrict__ kz
 // (larger ones are listed for k_sort_listed) and its depth noted.
 constexpr int FIN_T = 512;  // threads of a superbucket's workgroup
 
-__global__ void __launch_bounds__(FIN_T) __attribute__((amdgpu_waves_per_eu(4, 8))) k_finalize_sb(const int4 *__restrict__ rec,
+__global__ void __launch_bounds__(FIN_T) __attribute__((amdgpu_waves_per_eu(6, 8))) k_finalize_sb(const int4 *__restrict__ rec,
                                                       const int32_t *__restrict__ sb_off,
                                                       int64_t n_buckets,
                                                       int32_t *__restrict__ offsets,
