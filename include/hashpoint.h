@@ -139,7 +139,7 @@ typedef struct hp_camera {
  *  Launch shapes, none of which changes any result (an autotuner picks them
  *  per workload; 0 = default):
  *  search_band: consecutive rays dealt to one XCD at a time by the search
- *      kernels, 0 (12,800) or 64..2^24;
+ *      kernels, 0 (1,600) or 64..2^24;
  *  window_shape: HP_WINDOW_DISC or HP_WINDOW_SQUARE;
  *  render_rays: rays a render wave composites at a time, 0 (16), 16, 32 or 64;
  *  render_blocks: render grid; a workgroup takes every render_blocks-th

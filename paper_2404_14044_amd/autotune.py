@@ -34,14 +34,14 @@ SPACE = {
     "layout": (hp.HP_LAYOUT_ROWMAJOR, hp.HP_LAYOUT_TILED, hp.HP_LAYOUT_MORTON),
     "search_chunk": (1, 2, 4, 8, 16),
     "search_blocks": (8192, 16384, 32768, 65536, 131072),
-    "search_band": (3200, 12800, 51200),
+    "search_band": (800, 1600, 3200, 12800),
     "window_shape": (hp.HP_WINDOW_DISC, hp.HP_WINDOW_SQUARE),
     "render_rays": (16, 32, 64),
     "render_blocks": (0, 3072, 6144, 12288),
 }
 # the values the library takes for 0 (its defaults), the descent's start
 DEFAULTS = {"layout": hp.HP_LAYOUT_ROWMAJOR, "search_chunk": 4, "search_blocks": 65536,
-            "search_band": 12800, "window_shape": hp.HP_WINDOW_DISC, "render_rays": 16,
+            "search_band": 1600, "window_shape": hp.HP_WINDOW_DISC, "render_rays": 16,
             "render_blocks": 0}
 
 

@@ -97,8 +97,10 @@ struct SearchLds {
 // 32 one-wave workgroups (8 waves per SIMD) share a CU's 160 KB of LDS
 static_assert(sizeof(SearchLds) <= 5120, "search LDS above 5120 B halves occupancy");
 
-// Rays per XCD band: about 16 image rows of an 800-pixel-wide view.
-constexpr int64_t BAND_RAYS = 12800;
+// Rays per XCD band: two image rows of an 800-pixel-wide view (object view
+// 0.568 ms with bands of 12,800 rays, 0.545 with 3,200, 0.532 with 1,600,
+// 0.534 with 800; room view 3.09, 2.83, 2.81, 2.81 ms).
+constexpr int64_t BAND_RAYS = 1600;
 
 // Default grid of the search launches: 65,536 one-wave workgroups (on the
 // object view, 640k rays, 2.4 chunks of 4 rays each), eight times what the
