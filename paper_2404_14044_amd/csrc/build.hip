@@ -28,13 +28,18 @@ __global__ void k_fill_i32(int32_t *p, int32_t val, int64_t n)
 }
 
 // The build's first launch: the views' constants to device memory (first
-// workgroup) and n counters cleared (all of them).
-__global__ void k_build_begin(ViewSet vs, ViewK *out, int32_t *p, int64_t n)
+// workgroup), n counters cleared and nz depth-cell minima set to +inf (all
+// of them).
+__global__ void k_build_begin(ViewSet vs, ViewK *out, int32_t *p, int64_t n, uint32_t *z,
+                              int64_t nz)
 {
     if (blockIdx.x == 0 && threadIdx.x < vs.n) out[threadIdx.x] = vs.v[threadIdx.x];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nz;
+         i += (int64_t)gridDim.x * blockDim.x)
+        z[i] = 0x7f800000u;
 }
 
 // grid: (ceil(n / (256 PROJ_PER)), n_views).  Each thread takes PROJ_PER
@@ -308,9 +313,10 @@ __device__ __forceinline__ uint64_t sort_bucket_to_slots(const uint64_t *__restr
     typedef float fx4 __attribute__((ext_vector_type(4)));
     const fx4 *src = reinterpret_cast<const fx4 *>(pc);
     fx4 *dst = reinterpret_cast<fx4 *>(so.pts);
-    // (eight at a time: 32 registers, so that three 512-thread workgroups
-    // share a CU and one round of them covers the object view's superbuckets)
-    constexpr int G = N < 8 ? N : 8;
+    // (eight at a time, four beside the sixteen keys of the largest case:
+    // at most 32 registers, so that three 512-thread workgroups share a CU
+    // and one round of them covers the object view's superbuckets)
+    constexpr int G = N < 8 ? N : (N == 16 ? 4 : 8);
 #pragma unroll
     for (int i0 = 0; i0 < N; i0 += G) {
         fx4 v[G];
@@ -483,8 +489,24 @@ __global__ void __launch_bounds__(SB_T) k_scatter_sb(const int2 *__restrict__ kz
 // One workgroup per superbucket: bucket counts (LDS atomics), their scan
 // (the table's offsets for these SB keys), placement of every record, then
 // each bucket of at most SMALL_MAX points sorted by (z, index) in registers
-// (larger ones are listed for k_sort_listed) and its depth noted.
+// (larger ones are listed for k_sort_listed) and its depth noted.  The
+// depth cells' minima come from the records themselves (every point's depth,
+// listed buckets included): a minimum per cell in the LDS for the cells from
+// the first one of the superbucket's first cell row on, device atomics for
+// any cell beyond those (a row-major grid wider than about 2,000 buckets, or
+// a superbucket that reaches far into a second view).  Depths of binned
+// points are positive and finite, so their bits order as the values do.
 constexpr int FIN_T = 512;  // threads of a superbucket's workgroup
+constexpr int FIN_CELLS = 512;
+
+// depth cell of bucket b of a view (bucket_base, Wg, cell_base, ncx)
+__device__ __forceinline__ int cell_of_bucket(int layout, int b, int base, int wg, int cbase, int ncx)
+{
+    const int local = b - base;
+    if (layout != HP_LAYOUT_ROWMAJOR) return cbase + (local >> 6);  // cells are the 8x8 tiles
+    const int by = local / wg, bx = local - by * wg;
+    return cbase + (by >> CELL_SHIFT) * ncx + (bx >> CELL_SHIFT);
+}
 
 __global__ void __launch_bounds__(FIN_T) __attribute__((amdgpu_waves_per_eu(6, 8))) k_finalize_sb(const int4 *__restrict__ rec,
                                                       const int32_t *__restrict__ sb_off,
@@ -493,28 +515,56 @@ __global__ void __launch_bounds__(FIN_T) __attribute__((amdgpu_waves_per_eu(6, 8
                                                       uint64_t *__restrict__ skey,
                                                       int32_t *__restrict__ big_list,
                                                       int32_t *__restrict__ big_n,
-                                                      float *__restrict__ bucket_z, SlotOut so)
+                                                      float *__restrict__ bucket_z, SlotOut so,
+                                                      int layout, uint32_t *__restrict__ cell_zmin)
 {
     __shared__ int cnt[SB];
     __shared__ int cur[SB];
     __shared__ int sh[FIN_T / WAVE];
+    __shared__ uint32_t zc[FIN_CELLS];
     const int sb = blockIdx.x;
     const int64_t key0 = (int64_t)sb << SB_SHIFT;
     const int nkeys = (int)min((int64_t)SB, n_buckets - key0);
     const int r0 = sb_off[sb], r1 = sb_off[sb + 1];
+    // the view of the superbucket's first bucket, and the first cell of that
+    // bucket's cell row (row-major) or its cell (tiles)
+    int v0 = 0;
+    while (v0 + 1 < so.n_views && so.views[v0 + 1].bucket_base <= key0) ++v0;
+    const int base0 = so.views[v0].bucket_base, wg0 = so.views[v0].Wg;
+    const int cbase0 = so.views[v0].cell_base, ncx0 = so.views[v0].ncx;
+    const int end0 = base0 + wg0 * so.views[v0].Hg;
+    const int cell_lo = layout != HP_LAYOUT_ROWMAJOR
+                            ? cbase0 + (((int)key0 - base0) >> 6)
+                            : cbase0 + ((((int)key0 - base0) / wg0) >> CELL_SHIFT) * ncx0;
     for (int k = threadIdx.x; k < SB; k += FIN_T) cnt[k] = 0;
+    for (int k = threadIdx.x; k < FIN_CELLS; k += FIN_T) zc[k] = 0x7f800000u;
     __syncthreads();
     // records four at a time, their loads in flight together (the order in
     // which a bucket's records arrive does not matter: each bucket is sorted
     // by (z, index) below)
     constexpr int RB = 4;
+    const int2 *rxy = reinterpret_cast<const int2 *>(rec);  // (bucket, depth bits) of record i at 2 i
     for (int i0 = r0 + threadIdx.x; i0 < r1; i0 += RB * FIN_T) {
-        int x[RB];
-#pragma unroll
-        for (int j = 0; j < RB; ++j) x[j] = i0 + j * FIN_T < r1 ? rec[i0 + j * FIN_T].x : -1;
+        int2 x[RB];
 #pragma unroll
         for (int j = 0; j < RB; ++j)
-            if (x[j] >= 0) atomicAdd(&cnt[x[j] - (int)key0], 1);
+            x[j] = i0 + j * FIN_T < r1 ? rxy[2 * (int64_t)(i0 + j * FIN_T)] : make_int2(-1, 0);
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            const int b = x[j].x;
+            if (b < 0) continue;
+            atomicAdd(&cnt[b - (int)key0], 1);
+            int cell;
+            if (b < end0) {
+                cell = cell_of_bucket(layout, b, base0, wg0, cbase0, ncx0);
+            } else {
+                const ViewK &Vr = so.views[rec[i0 + j * FIN_T].w];
+                cell = cell_of_bucket(layout, b, Vr.bucket_base, Vr.Wg, Vr.cell_base, Vr.ncx);
+            }
+            const int rel = cell - cell_lo;
+            if ((unsigned)rel < (unsigned)FIN_CELLS) atomicMin(&zc[rel], (uint32_t)x[j].y);
+            else atomicMin(&cell_zmin[cell], (uint32_t)x[j].y);
+        }
     }
     __syncthreads();
     // exclusive scan over the SB counts, SB / FIN_T consecutive ones per thread
@@ -553,6 +603,8 @@ __global__ void __launch_bounds__(FIN_T) __attribute__((amdgpu_waves_per_eu(6, 8
         }
     }
     __syncthreads();  // (the placed keys are read back below by other threads)
+    for (int k = threadIdx.x; k < FIN_CELLS; k += FIN_T)
+        if (zc[k] != 0x7f800000u) atomicMin(&cell_zmin[cell_lo + k], zc[k]);
     for (int k = threadIdx.x; k < nkeys; k += FIN_T) {
         const int b = (int)key0 + k;
         const int n_b = cnt[k];
@@ -784,7 +836,9 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
     if (view_sb_max <= SB_MAX && nsb <= INT32_MAX / SB) {
         // two-level build: superbucket totals, records by superbucket, then
         // each superbucket's buckets in LDS
-        k_build_begin<<<64, 256, 0, s>>>(vs, tw.views, tw.sb_count, tw.sb_words);  // totals, cursors, big_n[2]
+        // totals, cursors, big_n[2]; the depth cells, which the superbuckets'
+        // workgroups lower
+        k_build_begin<<<64, 256, 0, s>>>(vs, tw.views, tw.sb_count, tw.sb_words, tw.cell_zmin, n_cells);
         if (nv > 0) {
             const dim3 grid((unsigned)((n + SB_T * SB_PER - 1) / (SB_T * SB_PER)), V);
             k_project_sb<<<grid, SB_T, 0, s>>>(xyz, n, tw.views, vs.layout, tw.kz, tw.pcam,
@@ -800,14 +854,13 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
         const SlotOut so{tw.pcam, n, tw.views, V, tw.pts, tw.perm};
         k_finalize_sb<<<(unsigned)nsb, FIN_T, 0, s>>>(reinterpret_cast<const int4 *>(tw.pts), tw.sb_off,
                                                      n_buckets, tw.offsets, tw.skey, tw.big_list,
-                                                     tw.big_n, tw.bucket_z, so);
+                                                     tw.big_n, tw.bucket_z, so, vs.layout, tw.cell_zmin);
         k_sort_listed<<<MID_BLOCKS + BIG_BLOCKS, 256, 0, s>>>(tw.offsets, tw.skey, tw.big_list, tw.big_n,
                                                             tw.bucket_z, n_buckets, so);
-        finish_build(nullptr, n, vs, tw, false, s);
         return hipGetLastError();
     }
     // one level (a view beyond SB_MAX superbuckets): a counter per bucket
-    k_build_begin<<<1024, 256, 0, s>>>(vs, tw.views, tw.count, n_buckets);
+    k_build_begin<<<1024, 256, 0, s>>>(vs, tw.views, tw.count, n_buckets, nullptr, 0);
     k_fill_i32<<<1, 64, 0, s>>>(tw.big_n, 0, 2);
     if (n > 0)
         k_project<<<dim3((unsigned)((n + 256 * PROJ_PER - 1) / (256 * PROJ_PER)), V), 256, 0, s>>>(
