@@ -442,24 +442,37 @@ __global__ void __launch_bounds__(1024) k_sb_scan(const int32_t *__restrict__ sb
     }
 }
 
+// Tables of at most SCAN_SB superbuckets in all skip the scan's launch: every
+// workgroup of the scatter scans the totals itself (SCAN_SB / SB_T per
+// thread) into LDS, and the first one also writes them out for the
+// superbucket workgroups.
+constexpr int SCAN_SB = 1024;
+
 // grid as k_project_sb.  Each point's record (key, z bits, index) goes to its
 // superbucket's range: rank among the workgroup's points of the superbucket
 // (LDS atomic) plus the workgroup's share of the range (one global atomic per
 // superbucket touched).  The order inside a superbucket does not matter: its
-// buckets are sorted by (z, index) next.
+// buckets are sorted by (z, index) next.  With SCAN, the superbucket offsets
+// are scanned here from the nsb_all totals (nsb_all <= SCAN_SB) instead of
+// read from sb_off, which workgroup (0, 0) fills, with the table's last
+// offset.
+template <bool SCAN>
 __global__ void __launch_bounds__(SB_T) k_scatter_sb(const int2 *__restrict__ kz, int64_t n,
                                                      const ViewK *__restrict__ views,
-                                                     const int32_t *__restrict__ sb_off,
+                                                     int32_t *__restrict__ sb_off,
                                                      int32_t *__restrict__ sb_cursor,
-                                                     int4 *__restrict__ rec)
+                                                     int4 *__restrict__ rec,
+                                                     const int32_t *__restrict__ sb_count,
+                                                     int nsb_all, int32_t *__restrict__ offsets_end)
 {
     __shared__ int hist[SB_MAX];
+    __shared__ int offs[SCAN ? SCAN_SB : 1];
+    __shared__ int wsum[SB_T / WAVE];
     const int vi = blockIdx.y;
     const ViewK &V = views[vi];
     int sb_lo, nsb;
     view_superbuckets(V, sb_lo, nsb);
     for (int j = threadIdx.x; j < nsb; j += SB_T) hist[j] = 0;
-    __syncthreads();
     const int64_t i0 = (int64_t)blockIdx.x * SB_T * SB_PER + threadIdx.x;
     int2 e[SB_PER];
     int r[SB_PER];
@@ -469,13 +482,47 @@ __global__ void __launch_bounds__(SB_T) k_scatter_sb(const int2 *__restrict__ kz
         const int64_t i = i0 + (int64_t)j * SB_T;
         e[j] = i < n ? kz[(int64_t)vi * n + i] : make_int2(-1, 0);
     }
+    if constexpr (SCAN) {
+        // exclusive scan of the totals, PER consecutive ones per thread
+        constexpr int PER = SCAN_SB / SB_T;
+        const int k0 = threadIdx.x * PER;
+        int c[PER], t = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            c[q] = k0 + q < nsb_all ? sb_count[k0 + q] : 0;
+            t += c[q];
+        }
+        const int l = lane_id(), w = threadIdx.x / WAVE;
+        const int inc = wave_incl_scan_i32(t);
+        if (l == WAVE - 1) wsum[w] = inc;
+        __syncthreads();
+        int run = inc - t, tot = 0;
+#pragma unroll
+        for (int k = 0; k < SB_T / WAVE; ++k) {
+            run += k < w ? wsum[k] : 0;
+            tot += wsum[k];
+        }
+        const bool first = blockIdx.x == 0 && blockIdx.y == 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            offs[k0 + q] = run;
+            if (first && k0 + q < nsb_all) sb_off[k0 + q] = run;
+            run += c[q];
+        }
+        if (first && threadIdx.x == 0) {
+            sb_off[nsb_all] = tot;
+            *offsets_end = tot;
+        }
+    }
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < SB_PER; ++j)
         r[j] = e[j].x >= 0 ? atomicAdd(&hist[(e[j].x >> SB_SHIFT) - sb_lo], 1) : 0;
     __syncthreads();
     for (int j = threadIdx.x; j < nsb; j += SB_T) {
         const int c = hist[j];
-        hist[j] = c ? sb_off[sb_lo + j] + atomicAdd(&sb_cursor[sb_lo + j], c) : 0;
+        const int base = SCAN ? offs[sb_lo + j] : sb_off[sb_lo + j];
+        hist[j] = c ? base + atomicAdd(&sb_cursor[sb_lo + j], c) : 0;
     }
     __syncthreads();
 #pragma unroll
@@ -843,9 +890,16 @@ hipError_t launch_build(const float *xyz, int64_t n, const ViewSet &vs, int64_t 
             const dim3 grid((unsigned)((n + SB_T * SB_PER - 1) / (SB_T * SB_PER)), V);
             k_project_sb<<<grid, SB_T, 0, s>>>(xyz, n, tw.views, vs.layout, tw.kz, tw.pcam,
                                                tw.sb_count);
-            k_sb_scan<<<1, 1024, 0, s>>>(tw.sb_count, (int)nsb, tw.sb_off, tw.offsets + n_buckets);
-            k_scatter_sb<<<grid, SB_T, 0, s>>>(tw.kz, n, tw.views, tw.sb_off, tw.sb_cursor,
-                                               reinterpret_cast<int4 *>(tw.pts));
+            if (nsb <= SCAN_SB) {
+                k_scatter_sb<true><<<grid, SB_T, 0, s>>>(tw.kz, n, tw.views, tw.sb_off, tw.sb_cursor,
+                                                         reinterpret_cast<int4 *>(tw.pts), tw.sb_count,
+                                                         (int)nsb, tw.offsets + n_buckets);
+            } else {
+                k_sb_scan<<<1, 1024, 0, s>>>(tw.sb_count, (int)nsb, tw.sb_off, tw.offsets + n_buckets);
+                k_scatter_sb<false><<<grid, SB_T, 0, s>>>(tw.kz, n, tw.views, tw.sb_off, tw.sb_cursor,
+                                                          reinterpret_cast<int4 *>(tw.pts), nullptr,
+                                                          (int)nsb, nullptr);
+            }
         } else {
             k_sb_scan<<<1, 1024, 0, s>>>(tw.sb_count, (int)nsb, tw.sb_off, tw.offsets + n_buckets);
         }
