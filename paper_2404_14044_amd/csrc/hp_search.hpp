@@ -476,29 +476,31 @@ __device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, RayGeom 
                                                     Empty empty)
 {
     const int l = lane_id();
-    const int64_t n_chunks = (c.n_rays + c.chunk - 1) / c.chunk;
+    // (chunk, band and slot numbers in 32 bits: a launch has fewer than 2^31
+    // rays, so every chunk number below fits an unsigned 32-bit integer, and
+    // 64-bit ones held scalar registers that the body then spilled)
+    const uint32_t n_chunks = (uint32_t)((c.n_rays + c.chunk - 1) / c.chunk);
     // chunks per band (fewer when the launch has fewer than eight full bands,
     // so that every XCD gets a share)
-    int64_t band = ((int64_t)c.band + c.chunk - 1) / c.chunk;
-    if (band * 8 > n_chunks) band = (n_chunks + 7) / 8 > 0 ? (n_chunks + 7) / 8 : 1;
-    const int xcd = blockIdx.x & 7;
-    const int64_t slot = blockIdx.x >> 3, n_slots = gridDim.x >> 3;
-    const int64_t n_bands = (n_chunks + band - 1) / band;
-    const int64_t my_chunks = (n_bands > xcd ? (n_bands - xcd + 7) / 8 : 0) * band;
-    // first ray and ray count of this workgroup's li-th chunk
-    auto chunk_rays = [&](int64_t li, int64_t &r0, int &n) {
+    uint32_t band = (uint32_t)(((int64_t)c.band + c.chunk - 1) / c.chunk);
+    if ((uint64_t)band * 8 > n_chunks) band = (n_chunks + 7) / 8 > 0 ? (n_chunks + 7) / 8 : 1;
+    const uint32_t xcd = blockIdx.x & 7;
+    const uint32_t slot = blockIdx.x >> 3, n_slots = gridDim.x >> 3;
+    const uint32_t n_bands = (n_chunks + band - 1) / band;
+    const uint32_t my_chunks = (n_bands > xcd ? (n_bands - xcd + 7) / 8 : 0) * band;
+    // first ray (relative to c.ray0) and ray count of this workgroup's li-th chunk
+    auto chunk_rays = [&](uint32_t li, uint32_t &r0, int &n) {
         n = 0;
         r0 = 0;
         if (li >= my_chunks) return;
-        const int64_t ch = (xcd + 8 * (li / band)) * band + li % band;
+        const uint32_t ch = (xcd + 8 * (li / band)) * band + li % band;
         if (ch >= n_chunks) return;
-        r0 = ch * c.chunk;
-        n = (int)min((int64_t)c.chunk, c.n_rays - r0);
-        r0 += c.ray0;
+        r0 = ch * (uint32_t)c.chunk;
+        n = (int)min((int64_t)c.chunk, c.n_rays - (int64_t)r0);
     };
     // four chunks per set-up pass (the chunks themselves stay small, for balance)
-    for (int64_t li = slot; li < my_chunks; li += 4 * n_slots) {
-        int64_t ra, rb, rc, rd;
+    for (uint32_t li = slot; li < my_chunks; li += 4 * n_slots) {
+        uint32_t ra, rb, rc, rd;
         int na, nb, nc, nd;
         chunk_rays(li, ra, na);
         chunk_rays(li + n_slots, rb, nb);
@@ -506,7 +508,8 @@ __device__ __forceinline__ void for_each_ray_banded(const SearchCtx &c, RayGeom 
         chunk_rays(li + 3 * n_slots, rd, nd);
         const int nab = na + nb, nabc = nab + nc, ntot = nabc + nd;
         auto ray_at = [&](int i) -> int64_t {
-            return i < na ? ra + i : i < nab ? rb + (i - na) : i < nabc ? rc + (i - nab) : rd + (i - nabc);
+            const uint32_t r = i < na ? ra + i : i < nab ? rb + (i - na) : i < nabc ? rc + (i - nab) : rd + (i - nabc);
+            return c.ray0 + (int64_t)r;
         };
         for (int s0 = 0; s0 < ntot; s0 += RS_CAP) {
             const int n = min(RS_CAP, ntot - s0);
