@@ -158,13 +158,36 @@ __device__ __forceinline__ uint64_t xor_lane_u64(uint64_t v)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// The lanes whose index has bit k set, as a 64-bit lane mask.
+constexpr uint64_t lane_bit_mask(int k)
+{
+    return k == 0   ? 0xAAAAAAAAAAAAAAAAull
+           : k == 1 ? 0xCCCCCCCCCCCCCCCCull
+           : k == 2 ? 0xF0F0F0F0F0F0F0F0ull
+           : k == 3 ? 0xFF00FF00FF00FF00ull
+           : k == 4 ? 0xFFFF0000FFFF0000ull
+                    : 0xFFFFFFFF00000000ull;
+}
+
+// Per-lane predicate "bit i of mask M" from a constant mask: the compiler
+// builds the mask with two scalar moves where it is used, where a lane-index
+// test was kept in a scalar register pair for the whole kernel (six of them
+// for the sorts) and pushed other scalars out to vector lanes.
+template <uint64_t M>
+__device__ __forceinline__ bool lanes_in(void)
+{
+    return __builtin_amdgcn_inverse_ballot_w64(M);
+}
+
+constexpr int log2_lane(int j) { return j == 1 ? 0 : j == 2 ? 1 : j == 4 ? 2 : j == 8 ? 3 : j == 16 ? 4 : 5; }
+
 // One compare-exchange stage in which every block ascends: lanes l and l ^ J
 // keep the minimum in the lower lane (one 64-bit compare, two selects).
 template <int J>
-__device__ __forceinline__ uint64_t cx_stage(uint64_t x, int l)
+__device__ __forceinline__ uint64_t cx_stage(uint64_t x, int)
 {
     const uint64_t y = xor_lane_u64<J>(x);
-    const bool take = (y < x) != ((l & J) != 0);
+    const bool take = (y < x) != lanes_in<lane_bit_mask(log2_lane(J))>();
     return take ? y : x;
 }
 
@@ -176,16 +199,13 @@ __device__ __forceinline__ uint64_t cx_merge(uint64_t x, int l)
     return x;
 }
 
-// Inverts the keys of the lanes whose lane-index bits a and b differ (b = -1:
-// bit a alone): bitwise NOT reverses the order of keys.
-__device__ __forceinline__ uint64_t flip_keys(uint64_t x, int l, int a, int b)
+// Inverts the keys of the lanes whose lane-index bits A and B differ (B = -1:
+// bit A alone): bitwise NOT reverses the order of keys.
+template <int A, int B>
+__device__ __forceinline__ uint64_t flip_keys(uint64_t x)
 {
-    // (recomputed at each use: kept from the start of the kernel, the six
-    // masks would hold registers the whole time)
-    asm volatile("" : "+v"(l));
-    const int bits = (l >> a) ^ (b >= 0 ? (l >> b) : 0);
-    const uint32_t m = (uint32_t)(-(bits & 1));
-    return x ^ (((uint64_t)m << 32) | m);
+    constexpr uint64_t m = lane_bit_mask(A) ^ (B >= 0 ? lane_bit_mask(B) : 0ull);
+    return lanes_in<m>() ? ~x : x;
 }
 
 // Bitonic sort of one key per lane across the wave.  In the merge of blocks
@@ -196,18 +216,18 @@ template <bool DESC>
 __device__ __forceinline__ uint64_t wave_sort_dir(uint64_t x)
 {
     const int l = lane_id();
-    x = flip_keys(x, l, 1, -1);  // K = 2 blocks descend where lane bit 1 is set
+    x = flip_keys<1, -1>(x);  // K = 2 blocks descend where lane bit 1 is set
     if constexpr (DESC) x = ~x;
     x = cx_merge<1>(x, l);
-    x = flip_keys(x, l, 1, 2);
+    x = flip_keys<1, 2>(x);
     x = cx_merge<2>(x, l);
-    x = flip_keys(x, l, 2, 3);
+    x = flip_keys<2, 3>(x);
     x = cx_merge<4>(x, l);
-    x = flip_keys(x, l, 3, 4);
+    x = flip_keys<3, 4>(x);
     x = cx_merge<8>(x, l);
-    x = flip_keys(x, l, 4, 5);
+    x = flip_keys<4, 5>(x);
     x = cx_merge<16>(x, l);
-    x = flip_keys(x, l, 5, -1);  // one block of 64: ascends (descends with DESC)
+    x = flip_keys<5, -1>(x);  // one block of 64: ascends (descends with DESC)
     x = cx_merge<32>(x, l);
     if constexpr (DESC) x = ~x;
     return x;
