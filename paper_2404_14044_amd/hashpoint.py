@@ -253,6 +253,14 @@ class Table:
     def pts(self, n_in: int) -> torch.Tensor:
         return _wrap(self.ws, self.tab.pts, 4 * n_in, torch.float32).view(n_in, 4)
 
+    def bucket_z(self) -> torch.Tensor:
+        """Depth of each bucket's first point (+inf if empty)."""
+        return _wrap(self.ws, self.tab.bucket_z, self.n_buckets, torch.float32)
+
+    def cell_zmin(self) -> torch.Tensor:
+        """Minimum depth of each 8x8-bucket cell as binary32 bits (int32 view)."""
+        return _wrap(self.ws, self.tab.cell_zmin, int(self.tab.n_cells), torch.int32)
+
 
 def _wrap(ws: torch.Tensor, ptr: int, count: int, dtype) -> torch.Tensor:
     """View of `count` elements of workspace `ws` starting at device address ptr."""

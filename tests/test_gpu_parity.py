@@ -326,6 +326,51 @@ def test_views_beyond_the_superbucket_limit_together():
         assert (ex["n_sel"] > 0).sum() > 20
 
 
+def test_depth_summaries_of_a_wide_view():
+    """A 6000 x 64 view: a superbucket (1024 buckets of one grid row) spans
+    more than the 512 depth cells the build keeps in LDS, so cells beyond
+    them are lowered by device atomics.  Every bucket's first depth and every
+    8x8 cell's minimum (+inf where empty) must equal the values taken from
+    the oracle's table, bit for bit, and sampled rays must match the oracle."""
+    import oracle
+    rng = np.random.default_rng(29)
+    cam = scenes.pinhole(6000, 64, 90.0, np.eye(3), np.zeros(3))
+    p = scenes.default_params(0.01, 1.0, 6.0, K=4, S=4)
+    n = 60000
+    z = rng.uniform(2.5, 3.0, n)
+    xyz = np.stack([rng.uniform(-0.98, 0.98, n) * z, rng.uniform(-0.01, 0.01, n) * z, z],
+                   1).astype(np.float32)
+    feat = rng.normal(size=(n, 32)).astype(np.float32)
+    sc = scenes.Scene("wide_row", xyz, feat, [cam], p, scenes.make_mlp(4))
+    out = gpu_forward(sc, debug=False)
+    tab = out["table"]
+    compare_table_rowmajor(sc, tab)
+    info = tab.view(0)
+    Wg, Hg = info.Wg, info.Hg
+    assert (Wg + 7) // 8 > 512
+    offs = host(tab.offsets())
+    g = oracle.guard(cam, p)
+    pc = oracle.to_camera(sc.xyz, cam)
+    key, order = oracle.table(pc, cam, g)
+    nb = Wg * Hg
+    cnt = np.diff(offs[:nb + 1])
+    want_bz = np.full(nb, np.inf, np.float32)
+    hit = cnt > 0
+    want_bz[hit] = pc[order[offs[:nb][hit]], 2]
+    got_bz = host(tab.bucket_z())[:nb]
+    assert np.array_equal(got_bz.view(np.uint32), want_bz.view(np.uint32))
+    ncx, ncy = (Wg + 7) // 8, (Hg + 7) // 8
+    grid = np.full((ncy * 8, ncx * 8), np.inf, np.float32)
+    grid[:Hg, :Wg] = want_bz.reshape(Hg, Wg)
+    want_cz = grid.reshape(ncy, 8, ncx, 8).min(axis=(1, 3)).reshape(-1)
+    got_cz = host(tab.cell_zmin())[:ncx * ncy]
+    assert np.array_equal(got_cz.view(np.uint32), want_cz.view(np.uint32))
+    assert np.isfinite(want_cz.reshape(ncy, ncx)[:, 512:]).any()
+    pix = sample_pixels(cam, 2048, seed=31)
+    ex = compare_exact(sc, out["samples"], pix, check_lists=False)
+    assert (ex["n_sel"] > 0).sum() > 100
+
+
 def test_objects_sampled_rays(objects):
     sc = objects
     from paper_2404_14044_amd import hashpoint as hp
