@@ -54,6 +54,35 @@ def compare_table_rowmajor(sc, tab, view=0, params=None):
     assert np.array_equal(np.diff(offs[b0:b0 + nb + 1]), cnt)
 
 
+def check_depth_summaries(sc, tab, view=0, params=None):
+    """The table's depth summaries of a row-major view against the oracle's
+    table: each bucket's first depth and each 8x8-bucket cell's minimum
+    (+inf where empty), bit for bit.  Returns the expected cell minima as a
+    (cells down, cells across) array."""
+    cam, p = sc.cams[view], params or sc.params
+    info = tab.view(view)
+    Wg, Hg, b0 = info.Wg, info.Hg, info.bucket_base
+    nb = Wg * Hg
+    offs = host(tab.offsets())
+    pc = oracle.to_camera(sc.xyz, cam)
+    key, order = oracle.table(pc, cam, oracle.guard(cam, p))
+    lo = int(offs[b0])
+    first = offs[b0:b0 + nb] - lo
+    hit = np.diff(offs[b0:b0 + nb + 1]) > 0
+    want_bz = np.full(nb, np.inf, np.float32)
+    want_bz[hit] = pc[order[first[hit]], 2]
+    got_bz = host(tab.bucket_z())[b0:b0 + nb]
+    assert np.array_equal(got_bz.view(np.uint32), want_bz.view(np.uint32))
+    ncx, ncy = (Wg + 7) // 8, (Hg + 7) // 8
+    cbase = sum(((tab.view(v).Wg + 7) // 8) * ((tab.view(v).Hg + 7) // 8) for v in range(view))
+    grid = np.full((ncy * 8, ncx * 8), np.inf, np.float32)
+    grid[:Hg, :Wg] = want_bz.reshape(Hg, Wg)
+    want_cz = grid.reshape(ncy, 8, ncx, 8).min(axis=(1, 3))
+    got_cz = host(tab.cell_zmin())[cbase:cbase + ncx * ncy]
+    assert np.array_equal(got_cz.view(np.uint32), want_cz.reshape(-1).view(np.uint32))
+    return want_cz
+
+
 def compare_exact(sc, smp, pix, params=None, view=0, ray_base=0, check_lists=True):
     """Bit-exact comparison of the search and sampling outputs on rays `pix`."""
     cam = sc.cams[view]
