@@ -411,13 +411,18 @@ def test_deterministic(objects):
 
 
 def test_multiview_table_and_search():
-    """Four views in one table: every view's rays match the oracle."""
+    """Four views in one table (fewer than 1,024 superbuckets, so the scatter
+    scans their totals itself, and superbuckets straddle the views): every
+    view's table, depth summaries and rays match the oracle."""
     base = scenes.objects_1m(n=200_000, res=64)
     sc = scenes.diff_4x400(base=base, res=160)
     out = gpu_forward(sc, debug=True)
     tab = out["table"]
+    assert tab.n_buckets <= 1024 * 1024
+    assert any(tab.view(v).bucket_base % 1024 for v in range(1, len(sc.cams)))
     for v, cam in enumerate(sc.cams):
         info = tab.view(v)
+        compare_table_rowmajor(sc, tab, view=v)
         check_depth_summaries(sc, tab, view=v)
         pix = sample_pixels(cam, 1024, seed=30 + v)
         ex = compare_exact(sc, out["samples"], pix, view=v, ray_base=info.ray_base)
